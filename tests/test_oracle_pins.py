@@ -1,0 +1,366 @@
+"""Pins of the CPU reference against facts that do not come from the reference itself: library
+routines (numpy / scipy LAPACK), closed forms, invariants and brute force on small inputs.
+
+Each test names the part of the method it pins; a plausible mistake in the reference (a dropped
+term, a wrong sign or conjugation, a transposed operand, an off-by-one in the recurrence) makes at
+least one of them fail.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_1206_3768_amd import synth
+
+RNG = np.random.default_rng(1234)
+
+
+def cgauss(n, m, rng=RNG):
+    return np.asfortranarray((rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))) / math.sqrt(2))
+
+
+def hpd(n, rng=RNG):
+    g = cgauss(n, n, rng)
+    return np.asfortranarray(g @ g.conj().T / n + np.eye(n))
+
+
+def herm(n, rng=RNG):
+    g = cgauss(n, n, rng)
+    return np.asfortranarray(0.5 * (g + g.conj().T))
+
+
+# ---- counter-based generator --------------------------------------------------------------------
+
+def test_philox_matches_numpy_bit_generator(orc):
+    # numpy's Philox (4x64-10) increments its counter before each block: block q of a generator
+    # started at counter c is philox(c + 1).
+    for key in ([5, 0], [0xDEADBEEF12345678, 77]):
+        for ctr in ([1, 0, 0, 0], [12345, 9, 0, 0], [2**64 - 1, 3, 0, 0]):
+            c0 = list(ctr)
+            # counter - 1 with borrow
+            if c0[0] == 0:
+                c0[0] = 2**64 - 1; c0[1] -= 1
+            else:
+                c0[0] -= 1
+            bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c0, dtype=np.uint64))
+            ref = bg.random_raw(4)
+            got = orc.philox4x64(ctr, key)
+            assert np.array_equal(got, ref), (ctr, key, got, ref)
+
+
+def test_random_block_layout_and_range(orc):
+    y = orc.random_block(7, 1, 33, 5)
+    assert np.all(np.abs(y.real) < 1) and np.all(np.abs(y.imag) < 1)
+    # element e uses counter (e/2, stream, 0, 0), key (seed, 0); parity selects words (0,1) or (2,3)
+    for (i, j) in [(0, 0), (1, 0), (32, 4), (5, 3)]:
+        e = i + j * 33
+        w = orc.philox4x64([e >> 1, 1, 0, 0], [7, 0])
+        k = 2 * (e & 1)
+        u = lambda v: float(int(v) >> 11) * 2.0**-53
+        assert y[i, j] == complex(2 * u(w[k]) - 1, 2 * u(w[k + 1]) - 1)
+    big = orc.random_block(3, 1, 4000, 4)
+    assert abs(big.real.mean()) < 0.03 and abs(big.imag.var() - 1 / 3) < 0.02
+
+
+# ---- dense products ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
+def test_zgemm_matches_numpy(orc, ta, tb):
+    A = cgauss(37, 300) if ta == "N" else cgauss(300, 37)
+    B = cgauss(300, 11) if tb == "N" else cgauss(11, 300)
+    Cm = cgauss(37, 11)
+    opa = A if ta == "N" else A.conj().T
+    opb = B if tb == "N" else B.conj().T
+    got = orc.zgemm(ta, tb, A, B, alpha=0.5 - 0.25j, beta=2.0, Cm=Cm)
+    ref = (0.5 - 0.25j) * (opa @ opb) + 2.0 * Cm
+    assert np.allclose(got, ref, rtol=0, atol=1e-12)
+
+
+# ---- Cholesky, triangular solves, reduction ----------------------------------------------------
+
+def test_cholesky_matches_lapack_and_reconstructs(orc):
+    S = hpd(60)
+    L, st = orc.cholesky(S)
+    assert st == 0
+    assert np.allclose(L, sla.cholesky(S, lower=True), atol=1e-13)
+    assert np.all(np.triu(L, 1) == 0) and np.all(np.diag(L).imag == 0) and np.all(np.diag(L).real > 0)
+    assert np.linalg.norm(L @ L.conj().T - S) <= 1e-14 * np.linalg.norm(S) * 10
+
+
+def test_cholesky_rejects_indefinite(orc):
+    S = hpd(20)
+    S[7, 7] = -5.0
+    _, st = orc.cholesky(S)
+    assert st == 1
+
+
+def test_triangular_solves(orc):
+    L, _ = orc.cholesky(hpd(50))
+    B = cgauss(50, 7)
+    X = orc.trsm_lower(L, B)
+    assert np.allclose(L @ X, B, atol=1e-12)
+    Xh = orc.trsm_lower(L, B, conj_trans=True)
+    assert np.allclose(L.conj().T @ Xh, B, atol=1e-12)
+    assert np.allclose(Xh, sla.solve_triangular(L, B, lower=True, trans="C"), atol=1e-12)
+
+
+def test_reduction_preserves_designed_spectrum(orc):
+    spec = synth.SequenceSpec(n=96, n_low=8, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=5)
+    p = synth.designed_pencil(spec)
+    L, st = orc.cholesky(p.S)
+    H = orc.reduce(p.A, L)
+    assert np.array_equal(H, H.conj().T)
+    ev = np.linalg.eigvalsh(H)
+    assert np.max(np.abs(ev - p.lam_exact)) <= 1e-13 * np.max(np.abs(p.lam_exact)) * 10
+    # H = L^-1 A L^-H exactly as the definition states
+    Linv = np.linalg.inv(L)
+    assert np.allclose(H, Linv @ p.A @ Linv.conj().T, atol=1e-12)
+
+
+# ---- QR ----------------------------------------------------------------------------------------
+
+def test_householder_qr_unique_factor(orc):
+    Y = cgauss(80, 12)
+    Q, R, st = orc.qr(Y)
+    assert st == 0
+    assert np.allclose(Q.conj().T @ Q, np.eye(12), atol=1e-13)
+    assert np.allclose(Q @ R, Y, atol=1e-13)
+    assert np.all(np.tril(R, -1) == 0)
+    assert np.all(np.diag(R).imag == 0) and np.all(np.diag(R).real >= 0)
+    # the factorisation with a real positive diagonal is unique: compare with LAPACK after
+    # normalising its diagonal phases
+    q2, r2 = np.linalg.qr(Y)
+    ph = np.diag(r2) / np.abs(np.diag(r2))
+    assert np.allclose(Q, q2 * ph[None, :], atol=1e-12)
+    assert np.allclose(R, np.conj(ph)[:, None] * r2, atol=1e-12)
+
+
+def test_qr_flags_dependent_columns(orc):
+    # an exactly zero column leaves nothing to normalise: R_jj == 0 is reported
+    Z = np.zeros((30, 3), dtype=complex, order="F")
+    _, _, st0 = orc.qr(Z)
+    assert st0 == 1
+
+
+# ---- Jacobi ------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m", [1, 2, 7, 40])
+def test_jacobi_matches_eigvalsh(orc, m):
+    G = herm(m)
+    w, V, sweeps = orc.jacobi(G)
+    assert np.all(np.diff(w) >= 0)
+    assert np.max(np.abs(w - np.linalg.eigvalsh(G))) <= 1e-13 * max(1.0, np.abs(w).max())
+    assert np.allclose(V.conj().T @ V, np.eye(m), atol=1e-13)
+    assert np.allclose(V @ np.diag(w) @ V.conj().T, G, atol=1e-13)
+    # phase convention: largest-magnitude entry of each column is real positive
+    for j in range(m):
+        i = int(np.argmax(np.abs(V[:, j])))
+        assert V[i, j].imag == 0 and V[i, j].real > 0
+
+
+def test_jacobi_degenerate_and_diagonal(orc):
+    G = np.diag([3.0, -1.0, 3.0, 0.5]).astype(complex)
+    w, V, sweeps = orc.jacobi(G)
+    assert np.array_equal(w, [-1.0, 0.5, 3.0, 3.0]) and sweeps == 0
+    # ties keep index order: the two 3.0 columns are e_0 then e_2
+    assert np.array_equal(np.abs(V[:, 2]), [1, 0, 0, 0]) and np.array_equal(np.abs(V[:, 3]), [0, 0, 1, 0])
+
+
+# ---- Lanczos -----------------------------------------------------------------------------------
+
+def test_lanczos_full_run_recovers_spectrum(orc):
+    H = herm(30)
+    theta, zw, bk = orc.lanczos(H, 30, seed=3)
+    assert np.allclose(theta, np.linalg.eigvalsh(H), atol=1e-11)
+    assert abs(zw.sum() - 1.0) < 1e-12          # weights of a unit start vector sum to one
+    assert bk < 1e-8                            # Krylov space is invariant after n steps
+
+
+def test_lanczos_upper_bound_holds_on_test_seeds(orc):
+    spec = synth.config_single_standard()
+    p = synth.designed_pencil(spec)
+    lmax = p.lam_exact.max()
+    for seed in range(100):
+        theta, zw, bk = orc.lanczos(p.A, 25, seed=seed)
+        mu1, a, b = orc.bounds(theta, zw, bk, 48, 512)
+        assert b >= lmax, seed
+        assert mu1 >= p.lam_exact.min() - 1e-12    # Ritz values lie inside the spectrum
+        assert mu1 < a < b
+
+
+# ---- Chebyshev filter --------------------------------------------------------------------------
+
+def cheb_T(d, t):
+    t = np.asarray(t, dtype=float)
+    out = np.empty_like(t)
+    inside = np.abs(t) <= 1
+    out[inside] = np.cos(d * np.arccos(t[inside]))
+    up = t > 1
+    out[up] = np.cosh(d * np.arccosh(t[up]))
+    lo = t < -1
+    out[lo] = (-1) ** d * np.cosh(d * np.arccosh(-t[lo]))
+    return out
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 5, 12])
+def test_filter_closed_form_on_diagonal(orc, d):
+    n, m = 64, 5
+    h = np.sort(RNG.uniform(-1.0, 1.0, n))
+    H = np.diag(h).astype(complex)
+    Y0 = cgauss(n, m)
+    a, b, mu1 = -0.5, 1.2, -1.0
+    Yd = orc.cheb_filter(H, Y0, a, b, mu1, deg=d)
+    c, e = (a + b) / 2, (b - a) / 2
+    scale = cheb_T(d, (h - c) / e) / cheb_T(d, np.array([(mu1 - c) / e]))[0]
+    ref = scale[:, None] * Y0
+    assert np.max(np.abs(Yd - ref)) <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_filter_degree_one_is_one_product_and_unitary_invariance(orc):
+    n, m = 40, 3
+    h = RNG.uniform(-1, 1, n)
+    Q = synth.haar_unitary(np.random.default_rng(9), n)
+    H = np.asfortranarray((Q * h[None, :]) @ Q.conj().T)
+    H = 0.5 * (H + H.conj().T)
+    Y0 = cgauss(n, m)
+    a, b, mu1 = -0.3, 1.1, -1.0
+    c, e = (a + b) / 2, (b - a) / 2
+    Y1 = orc.cheb_filter(H, Y0, a, b, mu1, deg=1)
+    assert np.allclose(Y1, (H @ Y0 - c * Y0) / (mu1 - c), atol=1e-13)
+    # filter(Q D Q^H, Q X) = Q filter(D, X)
+    X = cgauss(n, m)
+    lhs = orc.cheb_filter(H, Q @ X, a, b, mu1, deg=9)
+    rhs = Q @ orc.cheb_filter(np.diag(h).astype(complex), X, a, b, mu1, deg=9)
+    assert np.allclose(lhs, rhs, atol=1e-11 * np.abs(rhs).max())
+
+
+def test_filter_per_column_degrees(orc):
+    n = 50
+    H = herm(n) / 10
+    Y0 = cgauss(n, 4)
+    degs = [0, 3, 7, 1]
+    got = orc.cheb_filter(H, Y0, -0.1, 0.9, -0.8, deg=degs)
+    for j, d in enumerate(degs):
+        ref = orc.cheb_filter(H, Y0[:, j:j + 1], -0.1, 0.9, -0.8, deg=d)
+        assert np.array_equal(got[:, j:j + 1], ref)
+
+
+def test_residuals_and_analytic_degree(orc):
+    H = herm(20)
+    Y = cgauss(20, 3)
+    th = np.array([0.1, -0.2, 0.3])
+    r = orc.residuals(H @ Y, Y, th)
+    assert np.allclose(r, np.linalg.norm(H @ Y - Y * th[None, :], axis=0), rtol=1e-14)
+    # t = -cosh(s)  =>  rho = e^s, so d = ceil(ln(r/thr)/s)
+    a, b = 0.0, 2.0                  # c = 1, e = 1
+    s = 0.7
+    theta = 1.0 - math.cosh(s)
+    d = orc.analytic_degree(theta, 1e-3, a, b, 1e-10, 4, 30)
+    assert d == min(30, max(4, math.ceil(math.log(1e7) / s)))
+    assert orc.analytic_degree(0.5, 1e-3, a, b, 1e-10, 4, 30) == 30     # inside [a, b]: dmax
+    assert orc.analytic_degree(-5.0, 1e-12, a, b, 1e-10, 4, 30) == 4    # converged: dmin
+
+
+# ---- whole solver ------------------------------------------------------------------------------
+
+def _angles(X, Y, S=None):
+    if S is not None:
+        L = np.linalg.cholesky(S)
+        X = L.conj().T @ X
+        Y = L.conj().T @ Y
+    return sla.subspace_angles(X, Y)
+
+
+def test_solve_standard_matches_designed_spectrum(orc):
+    spec = synth.config_single_standard()
+    p = synth.designed_pencil(spec)
+    r = orc.solve(p.A, None, nev=32, nex=16, deg=10, tol=1e-10, seed=1)
+    assert r.status == 0 and r.stats["nlocked"] >= 32
+    lam = p.lam_exact[:32]
+    assert np.all(np.abs(r.lam[:32] - lam) <= 1e-10 * np.maximum(np.abs(lam), 1e-3))
+    assert r.resid[:32].max() <= 1e-10
+    assert np.abs(r.X.conj().T @ r.X - np.eye(48)).max() <= 1e-12
+    # subspace of the nev wanted vectors equals the designed eigenvectors' subspace
+    assert _angles(r.X[:, :32], p.X_exact[:, :32]).max() <= 1e-8
+    # interlacing: Ritz values of the extra block never undercut the true eigenvalues
+    assert np.all(r.lam[32:48] >= p.lam_exact[32:48] - 1e-12)
+
+
+def test_solve_generalized_matches_lapack(orc):
+    spec = synth.SequenceSpec(n=200, n_low=10, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=4)
+    p = synth.designed_pencil(spec)
+    A = p.A + 1e-2 * synth.hermitian_noise(np.random.default_rng(2), 200)
+    A = 0.5 * (A + A.conj().T)
+    r = orc.solve(A, p.S, nev=12, nex=6, deg=12, tol=1e-10, seed=2)
+    ev, evec = sla.eigh(A, p.S)
+    assert r.status == 0
+    assert np.all(np.abs(r.lam[:12] - ev[:12]) <= 1e-10 * np.maximum(np.abs(ev[:12]), 1e-3))
+    assert r.resid[:12].max() <= 1e-10
+    assert np.abs(r.X.conj().T @ p.S @ r.X - np.eye(18)).max() <= 1e-12
+    assert _angles(r.X[:, :12], evec[:, :12], p.S).max() <= 1e-8
+
+
+def test_solve_warm_start_sequence(orc):
+    spec = synth.config_generalized_sequence(n=256, cycles=3)
+    X = None
+    bnd = None
+    for pen in synth.sequence(spec):
+        r = orc.solve(pen.A, pen.S, nev=spec.nev, nex=spec.nex, deg=12, tol=1e-10, X0=X, bounds=bnd, seed=3)
+        ev = sla.eigh(pen.A, pen.S, eigvals_only=True)
+        assert r.status == 0
+        assert np.all(np.abs(r.lam[:spec.nev] - ev[:spec.nev]) <= 1e-10 * np.maximum(np.abs(ev[:spec.nev]), 1e-3))
+        if pen.cycle > 0:
+            rnd = orc.solve(pen.A, pen.S, nev=spec.nev, nex=spec.nex, deg=12, tol=1e-10, seed=3)
+            assert r.stats["filtered_vectors"] <= rnd.stats["filtered_vectors"]
+        X = r.X
+        bnd = (r.lam[0], r.lam[-1])
+
+
+def test_solve_analytic_degree_policy(orc):
+    spec = synth.config_single_standard()
+    p = synth.designed_pencil(spec)
+    r = orc.solve(p.A, None, nev=32, nex=16, deg=10, tol=1e-10, seed=1, degree_policy=1)
+    assert r.status == 0
+    assert np.all(np.abs(r.lam[:32] - p.lam_exact[:32]) <= 1e-10)
+
+
+def test_solve_error_paths(orc):
+    p = synth.designed_pencil(synth.SequenceSpec(n=40, n_low=4, generalized=True, cycles=1, eps0=0,
+                                                 eps_decay=1, seed=1), keep_vectors=False)
+    S = p.S.copy(order="F")
+    S[3, 3] = -1.0
+    assert orc.solve(p.A, S, nev=4, nex=2).status == 2
+    assert orc.solve(p.A, p.S, nev=30, nex=20).status == 1
+    r = orc.solve(p.A, p.S, nev=4, nex=2, max_loops=1, deg=2, tol=1e-14)
+    assert r.status == 3
+
+
+# ---- degree network ----------------------------------------------------------------------------
+
+def test_mlp_gradient_matches_finite_differences(orc):
+    rng = np.random.default_rng(0)
+    npar = orc.mlp_nparams()
+    assert npar == 8769
+    P = rng.standard_normal(npar) * 0.2
+    X = rng.standard_normal((16, 5))
+    y = rng.uniform(4, 30, 16)
+    loss, g = orc.mlp_loss_grad(P, X, y)
+    idx = rng.choice(npar, 60, replace=False)
+    idx = np.concatenate([idx, [0, 319, 320, 8703, 8704, 8768]])
+    for i in idx:
+        h = 1e-5
+        Pp = P.copy(); Pp[i] += h
+        Pm = P.copy(); Pm[i] -= h
+        fd = (orc.mlp_loss_grad(Pp, X, y)[0] - orc.mlp_loss_grad(Pm, X, y)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-3 * max(1e-4, abs(fd)), (i, fd, g[i])
+    out = orc.mlp_forward(P, X)
+    assert np.all((out > 4) & (out < 30))
+    assert abs(loss - np.mean((out - y) ** 2)) < 1e-12
+
+
+def test_adam_first_step_is_signed_lr(orc):
+    P = np.array([1.0, -2.0, 0.5]); g = np.array([0.3, -4.0, 1e-3])
+    m = np.zeros(3); v = np.zeros(3)
+    orc.adam_step(P, g, m, v, 1, lr=0.01, eps=0.0)
+    assert np.allclose(P, [1.0 - 0.01, -2.0 + 0.01, 0.5 - 0.01], atol=1e-15)
