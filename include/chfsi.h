@@ -1,0 +1,211 @@
+/*
+ * chfsi.h -- C ABI of the MI355X (gfx950) Chebyshev-filtered subspace iteration library.
+ *
+ * The method is Algorithm 1 of Di Napoli & Berljafa, "Block iterative eigensolvers for sequences
+ * of correlated eigenvalue problems" (ChFSI with deflation and locking), wrapped by the reduction
+ * of a generalized Hermitian pencil A x = lambda S x to standard form (Section 3.2) and the
+ * back-transformation of the eigenvectors.
+ *
+ * Conventions for every entry point
+ *  - Matrices are column-major complex double (interleaved re, im; layout-compatible with
+ *    C99 `double _Complex` and std::complex<double>), leading dimension >= rows.
+ *  - Matrix arguments are DEVICE pointers on the handle's device; `lambda`, `resid`, `deg`,
+ *    `theta` and other small vectors are HOST pointers unless stated otherwise.
+ *  - The caller owns every pointer it passes; the library never frees or keeps them past the
+ *    return.  The library owns its workspace, grows it on demand and frees it in chfsi_destroy.
+ *  - Every call enqueues its work on the handle's stream and is synchronous on return.
+ *  - A status code is returned; no C++ exception crosses this interface.  Outputs are undefined
+ *    on any status other than CHFSI_SUCCESS, except as stated for CHFSI_ERR_NO_CONVERGENCE.
+ *  - One handle per host thread.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chfsi_handle_s* chfsi_handle;
+
+typedef enum {
+    CHFSI_SUCCESS = 0,
+    CHFSI_ERR_ARG = 1,            /* invalid size, pointer or parameter                         */
+    CHFSI_ERR_NOT_HPD = 2,        /* a Cholesky pivot of S was not positive                     */
+    CHFSI_ERR_NO_CONVERGENCE = 3, /* max_loops reached; the locked prefix is valid              */
+    CHFSI_ERR_NUMERIC = 4,        /* NaN/Inf in inputs or iterates, or a breakdown in QR        */
+    CHFSI_ERR_DEVICE = 5,         /* a HIP runtime call failed                                  */
+    CHFSI_ERR_ALLOC = 6           /* device or host allocation failed                           */
+} chfsi_status;
+
+/* Arithmetic of the Chebyshev filter.  Every other step (reduction, Lanczos, QR, Rayleigh-Ritz,
+ * residuals, locking) is FP64 regardless of this setting. */
+typedef enum {
+    CHFSI_FP64 = 0,               /* complex128 on FP64 MFMA                                    */
+    CHFSI_FP32 = 1,               /* complex64 on FP32 MFMA, FP32 accumulation                  */
+    CHFSI_BF16X3 = 2,             /* FP32 operands split into 2 BF16 terms, 3 products, FP32 acc */
+    CHFSI_BF16X6 = 3              /* FP32 operands split into 3 BF16 terms, 6 products, FP32 acc */
+} chfsi_precision;
+
+/* Per-vector filter degree (Algorithm 1 uses one fixed degree). */
+typedef enum {
+    CHFSI_DEG_FIXED = 0,          /* every vector gets `deg`                                    */
+    CHFSI_DEG_ANALYTIC = 1,       /* from the Chebyshev growth rate at its Ritz value           */
+    CHFSI_DEG_LEARNED = 2         /* from the degree network set by chfsi_set_degree_model      */
+} chfsi_degree_policy;
+
+typedef struct {
+    int nev;                      /* wanted eigenpairs (lowest part of the spectrum)            */
+    int nex;                      /* extra vectors: block size m = nev + nex (paper: nev + 40)  */
+    int deg;                      /* filter degree; initial degree for adaptive policies (25)   */
+    double tol;                   /* target for ||A x - lambda S x|| / ||A||  (1e-10)           */
+    int max_loops;                /* inner-loop limit (50)                                      */
+    int lanczos_steps;            /* clamped to [10, 3 m] and to n (25)                         */
+    int filter_precision;         /* chfsi_precision (CHFSI_FP64)                               */
+    int degree_policy;            /* chfsi_degree_policy (CHFSI_DEG_FIXED)                      */
+    int deg_min, deg_max;         /* degree clamp for adaptive policies ([4, 30])               */
+    unsigned long long seed;      /* random start block and Lanczos start vector (0)            */
+    int have_bounds;              /* 1: use mu1 and a below (warm start of a sequence)          */
+    double mu1;                   /* lower spectral estimate (previous lambda_1)                */
+    double a;                     /* lower end of the damped interval (previous largest Ritz)   */
+    int trace;                    /* 1: record per-vector (features, residual history) rows     */
+    double switch_residual;       /* mixed precision: a vector whose residual falls below
+                                     switch_residual * ||A||_lo is filtered in FP64 from then on
+                                     (0 = precision-dependent default)                          */
+} chfsi_params;
+
+typedef struct {
+    int loops;                    /* inner loops of Algorithm 1                                 */
+    int nlocked;                  /* locked (converged) pairs                                   */
+    long long filtered_vectors;   /* sum over loops of the active block width                   */
+    long long matvecs;            /* sum over loops and vectors of the filter degree            */
+    double filter_flops;          /* 8 n^2 * matvecs (complex GEMM count)                       */
+    double t_reduce, t_lanczos, t_filter, t_qr, t_rr, t_resid, t_lock, t_back, t_total; /* ms */
+    double mu1, a, b;             /* final filter bounds                                        */
+    double norm_a;                /* largest column 2-norm of A (lower bound of ||A||_2)        */
+    int lanczos_steps;            /* Lanczos steps taken                                        */
+    int precision_switches;       /* vectors moved from low precision to FP64                   */
+    int status;                   /* chfsi_status of this solve                                 */
+} chfsi_stats;
+
+/* One problem of a batch (chfsi_solve_batched); same meaning as chfsi_solve's arguments. */
+typedef struct {
+    int n, nev, nex;
+    const void* A; int lda;
+    const void* S; int lds;       /* NULL = standard problem                                    */
+    void* X; int ldx;
+    int x_is_guess;
+    double* lambda;               /* host [nev + nex]                                           */
+    double* resid;                /* host [nev + nex]                                           */
+} chfsi_problem;
+
+/* Fills *p with the defaults listed above (Table 3 of the paper: degree 25, TOL 1e-10). */
+void chfsi_default_params(chfsi_params* p);
+
+/* Creates a handle on `device` that enqueues on `hip_stream` (NULL = the null stream).
+ * Errors: CHFSI_ERR_ARG (h NULL), CHFSI_ERR_DEVICE, CHFSI_ERR_ALLOC. */
+chfsi_status chfsi_create(chfsi_handle* h, int device, void* hip_stream);
+chfsi_status chfsi_destroy(chfsi_handle h);
+
+/* Solves A x = lambda S x for the nev lowest eigenpairs with Algorithm 1 (Section 3.1), after
+ * reducing to H = L^{-1} A L^{-H}, S = L L^H (Section 3.2; L^T in the paper read as L^H).
+ *   A, lda   n x n Hermitian, full storage, not modified.
+ *   S, lds   n x n Hermitian positive definite, not modified; NULL = standard problem (S = I).
+ *   X, ldx   n x m, m = nev + nex.  In: warm-start block in generalized coordinates when
+ *            x_is_guess != 0 (ignored otherwise: a Philox4x64-10 uniform block of stream 1 keyed
+ *            by p->seed is used).  Out: Ritz vectors, S-orthonormal; the first nev converged.
+ *   lambda   host [m]: ascending Ritz values; the first nev converged.
+ *   resid    host [m]: ||A x_i - lambda_i S x_i||_2 / ||A||_lo.
+ *   p        parameters (NULL = defaults); stats (nullable) receives counters and phase times.
+ * Returns CHFSI_ERR_NOT_HPD if S is not positive definite, CHFSI_ERR_NO_CONVERGENCE when
+ * max_loops is reached (stats->nlocked pairs at the front of X, lambda, resid are valid),
+ * CHFSI_ERR_NUMERIC on NaN/Inf or QR breakdown. */
+chfsi_status chfsi_solve(chfsi_handle h, int n, const void* A, int lda, const void* S, int lds,
+                         void* X, int ldx, int x_is_guess, double* lambda, double* resid,
+                         const chfsi_params* p, chfsi_stats* stats);
+
+/* Solves `count` independent problems (k-points of one self-consistent cycle, Section 2.1) with
+ * shared parameters p (p->nev and p->nex are ignored: each problem carries its own).  The filter
+ * steps of all unconverged problems run as one persistent launch per step.  stats: [count],
+ * nullable.  Returns the first non-success status of any problem. */
+chfsi_status chfsi_solve_batched(chfsi_handle h, int count, const chfsi_problem* probs,
+                                 const chfsi_params* p, chfsi_stats* stats);
+
+/* Applies the Chebyshev filter of Algorithm 1 in place to Y (n x m):
+ *   Y <- T_d((H - cI)/e) Y / T_d((mu1 - c)/e),  c = (a+b)/2, e = (b-a)/2,
+ * by the scaled three-term recurrence, column i taking deg[i] steps (deg == NULL: deg_uniform).
+ * H (n x n Hermitian) is not modified.  prec selects the arithmetic (chfsi_precision).
+ * Requires mu1 < a < b.  This is the hot path exposed for tests and benchmarks. */
+chfsi_status chfsi_filter(chfsi_handle h, int n, const void* H, int ldh, void* Y, int ldy, int m,
+                          const int* deg, int deg_uniform, double a, double b, double mu1, int prec);
+
+/* Step-level entry points (the pieces chfsi_solve is made of), for parity tests.
+ *  chfsi_reduce:  L L^H = S, H = L^{-1} A L^{-H} (Hermitized).  H, L: n x n device outputs
+ *                 (leading dimension n).  CHFSI_ERR_NOT_HPD on a non-positive pivot.
+ *  chfsi_lanczos: k-step Lanczos with full reorthogonalisation from the stream-2 Philox vector;
+ *                 theta[k] ascending Ritz values of T_k, zw[k] = |z_1j|^2, *beta_k, *k_used (host).
+ *  chfsi_orthonormalize: Y (n x m) <- Q with Y = Q R, R upper triangular with real positive
+ *                 diagonal, after removing components along the nl columns of YL (may be 0).
+ *  chfsi_rayleigh_ritz: Y (n x m, orthonormal columns) <- Y W where Y^H H Y = W diag(theta) W^H,
+ *                 theta ascending (host [m]); resid (host [m]) = ||H y_i - theta_i y_i||_2. */
+chfsi_status chfsi_reduce(chfsi_handle h, int n, const void* A, int lda, const void* S, int lds,
+                          void* H, void* L);
+chfsi_status chfsi_lanczos(chfsi_handle h, int n, const void* H, int ldh, int k,
+                           unsigned long long seed, double* theta, double* zw, double* beta_k,
+                           int* k_used);
+chfsi_status chfsi_orthonormalize(chfsi_handle h, int n, int m, void* Y, int ldy, int nl,
+                                  const void* YL, int ldyl);
+chfsi_status chfsi_rayleigh_ritz(chfsi_handle h, int n, const void* H, int ldh, int m, void* Y,
+                                 int ldy, double* theta, double* resid);
+
+/* Fills Y (n x m, device) with the library's random block: element e = i + j n of stream `stream`
+ * is Philox4x64-10 (Salmon et al., SC'11) of counter (e/2, stream, 0, 0) and key (seed, 0); the
+ * parity of e selects words (0,1) or (2,3); each word w gives a part 2 (w >> 11) 2^-53 - 1 in
+ * [-1, 1).  Stream 1 is the cold-start block of chfsi_solve, stream 2 the Lanczos start vector. */
+chfsi_status chfsi_random_block(chfsi_handle h, unsigned long long seed, unsigned long long stream, int n, int m,
+                                void* Y, int ldy);
+
+/* Dense complex product C = alpha op(A) op(B) + beta C (op: 'N' or 'C' = conjugate transpose),
+ * op(A) m x k, op(B) k x n, real alpha and beta, device pointers.  The MFMA kernel the filter and
+ * the Rayleigh-Ritz step use. */
+chfsi_status chfsi_zgemm(chfsi_handle h, char transa, char transb, int m, int n, int k,
+                         double alpha, const void* A, int lda, const void* B, int ldb,
+                         double beta, void* C, int ldc);
+
+/* Degree network (learned per-vector degree).  A blob is the float32 parameter vector of the
+ * 5 -> 64 -> 64 -> 64 -> 1 network (8769 values, layout W1[64][5] b1 W2[64][64] b2 W3[64][64] b3
+ * W4[1][64] b4) followed by 10 float32 feature normalisation constants (mean[5], std[5]).
+ * NULL clears the model; CHFSI_ERR_ARG if nbytes does not match. */
+chfsi_status chfsi_set_degree_model(chfsi_handle h, const void* blob, size_t nbytes);
+
+/* Copies the trace recorded by the last solve with p->trace = 1 into host_buf.  Each row is
+ * CHFSI_TRACE_COLS doubles: loop, column, t = (theta - c)/e, log10 r_before, a, b, degree used,
+ * r_after (the same column's residual after the next loop; -1 if none), lock threshold.
+ * With host_buf NULL only *nbytes is set. */
+#define CHFSI_TRACE_COLS 9
+chfsi_status chfsi_get_trace(chfsi_handle h, void* host_buf, size_t* nbytes);
+
+/* Degree-network kernels (FP32, device pointers), used by training and by the gradient checks.
+ *  forward:   out[N] = dmin + (dmax - dmin) sigmoid(net(X[N][5]))
+ *  loss_grad: grad[8769] and *loss (host) of mean((out - y)^2)
+ *  adam:      one bias-corrected Adam step on P with moments m, v (all [8769]), step t >= 1
+ *  train:     epochs of shuffled minibatch Adam on (X, y); the shuffle uses Philox keyed by seed;
+ *             loss_hist (host, nullable) receives the mean loss of each epoch. */
+chfsi_status chfsi_mlp_forward(chfsi_handle h, const float* P, int N, const float* X, float dmin,
+                               float dmax, float* out);
+chfsi_status chfsi_mlp_loss_grad(chfsi_handle h, const float* P, int N, const float* X,
+                                 const float* y, float dmin, float dmax, float* grad, float* loss);
+chfsi_status chfsi_mlp_adam(chfsi_handle h, float* P, const float* grad, float* m, float* v, int t,
+                            float lr, float beta1, float beta2, float eps);
+chfsi_status chfsi_mlp_train(chfsi_handle h, float* P, int N, const float* X, const float* y,
+                             float dmin, float dmax, int epochs, int batch, float lr,
+                             unsigned long long seed, float* loss_hist);
+
+/* Human-readable name of a status code (static storage). */
+const char* chfsi_status_string(chfsi_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHFSI_H */

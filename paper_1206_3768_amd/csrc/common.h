@@ -1,0 +1,103 @@
+// Internal declarations of the gfx950 ChFSI library: complex types, device helpers and the
+// launchers each translation unit exports to the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double2 zd;   // complex double, interleaved (re, im)
+typedef float2 zf;    // complex float
+typedef double __attribute__((ext_vector_type(4))) d4;
+typedef float __attribute__((ext_vector_type(4))) f4;
+
+#define CHK_HIP(x)                                                   \
+    do {                                                             \
+        hipError_t e_ = (x);                                         \
+        if (e_ != hipSuccess) return chfsi_internal_hip_error(e_);   \
+    } while (0)
+
+int chfsi_internal_hip_error(hipError_t e);
+
+__host__ __device__ inline zd zmul(zd a, zd b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline zd zcmul(zd a, zd b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }  // conj(a) b
+__host__ __device__ inline double zabs2(zd a) { return a.x * a.x + a.y * a.y; }
+
+// ---- GEMM (gemm.hip) --------------------------------------------------------------------------
+// C = alpha op(A) op(B) + beta C, complex, op = N or C, all device pointers, real scalars.
+// `ws`/`ws_bytes` is scratch for split-K partials (may be null: no split).
+enum { OP_N = 0, OP_C = 1 };
+enum { PREC_F64 = 0, PREC_F32 = 1 };
+
+struct FilterStep {
+    // out = alpha * (H Yk - shift Yk) + beta * Yprev, columns [0, ncols)
+    double alpha, beta, shift;
+};
+
+// FP64 complex GEMM on MFMA.  Returns hipError_t as int.
+int launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, double alpha, const zd* A, int lda,
+                 const zd* B, int ldb, double beta, zd* C, int ldc, void* ws, size_t ws_bytes);
+// One filter step, FP64: Yout = alpha (H Yk - shift Yk) + beta Yprev (Yout may alias Yprev).
+int launch_filter_step_f64(hipStream_t s, int n, int ncols, const zd* H, int ldh, const zd* Yk, int ldyk,
+                           const zd* Yprev, int ldyp, zd* Yout, int ldyo, FilterStep fs, void* ws,
+                           size_t ws_bytes);
+// One filter step, FP32 complex (complex64 storage, FP32 MFMA and accumulation).
+int launch_filter_step_f32(hipStream_t s, int n, int ncols, const zf* H, int ldh, const zf* Yk, int ldyk,
+                           const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs, void* ws,
+                           size_t ws_bytes);
+size_t zgemm_ws_bytes(int M, int N, int K, int elem_bytes);
+
+// ---- BF16-split filter (gemm_bf16.hip) ---------------------------------------------------------
+// H planes: for each of the `nterms` split terms, separate re and im planes of bf16, column-major
+// with leading dimension ldh (elements).  Yk is complex64.
+int launch_split_h_bf16(hipStream_t s, int n, const zd* H, int ldh, uint16_t* planes, int ldp, int nterms);
+int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hplanes, int ldp, int nterms,
+                            const zf* Yk, int ldyk, const zf* Yprev, int ldyp, zf* Yout, int ldyo,
+                            FilterStep fs, uint16_t* ysplit, void* ws, size_t ws_bytes);
+size_t bf16_ysplit_bytes(int n, int ncols, int nterms);
+size_t bf16_hplanes_elems(int n, int nterms);
+
+// ---- level-1/2 and small kernels (blas1.hip) ----------------------------------------------------
+int launch_zlacpy(hipStream_t s, int M, int N, const zd* A, int lda, zd* B, int ldb);
+int launch_z2c(hipStream_t s, int M, int N, const zd* A, int lda, zf* B, int ldb);   // complex128 -> complex64
+int launch_c2z(hipStream_t s, int M, int N, const zf* A, int lda, zd* B, int ldb);   // complex64 -> complex128
+int launch_hermitize(hipStream_t s, int n, zd* H, int ldh);
+int launch_philox_block(hipStream_t s, unsigned long long seed, unsigned long long stream, int n, int m, zd* Y,
+                        int ldy);
+// y[j] = conj(V[:, j]) . x  for j < ncols (column dot products; for Hermitian V this is V x)
+int launch_coldots(hipStream_t s, int n, int ncols, const zd* V, int ldv, const zd* x, zd* y);
+// x += alpha * V c   (c length ncols, device; alpha real)
+int launch_gemv_n(hipStream_t s, int n, int ncols, const zd* V, int ldv, const zd* c, double alpha, zd* x);
+// residual norms r[j] = || HY[:, j] - theta[j] Y[:, j] ||  (theta, r device)
+int launch_residual_norms(hipStream_t s, int n, int m, const zd* HY, int ldhy, const zd* Y, int ldy,
+                          const double* theta, double* r);
+int launch_colnorms(hipStream_t s, int n, int m, const zd* Y, int ldy, double* r);
+int launch_scale_cols_inv(hipStream_t s, int n, int m, zd* Y, int ldy, const double* nrm);   // Y[:, j] /= nrm[j]
+int launch_max_colnorm(hipStream_t s, int n, const zd* A, int lda, double* out);            // max_j ||A[:, j]||
+int launch_max_rowsum_abs(hipStream_t s, int n, const zd* A, int lda, double* out);         // ||A||_inf
+int launch_add_diag(hipStream_t s, int m, zd* G, int ldg, const double* shift_dev, double factor);
+int launch_fro2(hipStream_t s, int n, int m, const zd* Y, int ldy, double* out);            // ||Y||_F^2
+// Lanczos helpers
+int launch_lanczos_alpha(hipStream_t s, int n, const zd* v, zd* w, const zd* vprev, double* alpha_out,
+                         const double* beta_prev);
+int launch_lanczos_normalize(hipStream_t s, int n, const zd* w, zd* vnext, double* beta_out);
+// phase-normalize eigenvector columns: largest-magnitude entry (first on ties) real positive
+int launch_phase_normalize(hipStream_t s, int m, int ncols, zd* W, int ldw);
+int launch_any_nonfinite(hipStream_t s, int n, const double* v, int* flag);
+// gather/scatter columns: dst[:, j] = src[:, perm[j]]
+int launch_permute_cols(hipStream_t s, int n, int m, const zd* src, int lds, zd* dst, int ldd, const int* perm);
+int launch_copy_cols_flag(hipStream_t s, int n, int m, const zd* src, int lds, zd* dst, int ldd, const int* flag);
+int launch_copy_cols_flag_c(hipStream_t s, int n, int m, const zf* src, int lds, zf* dst, int ldd, const int* flag);
+
+// ---- degree network (mlp.hip) -------------------------------------------------------------------
+#define MLP_NF 5
+#define MLP_NH 64
+#define MLP_NPARAM (MLP_NH * MLP_NF + MLP_NH + 2 * (MLP_NH * MLP_NH + MLP_NH) + MLP_NH + 1)
+int launch_mlp_forward(hipStream_t s, const float* P, int N, const float* X, float dmin, float dmax, float* out);
+int launch_mlp_loss_grad(hipStream_t s, const float* P, int N, const float* X, const float* y, float dmin,
+                         float dmax, float* grad, float* loss_dev, float* scratch);
+size_t mlp_scratch_floats(int N);
+int launch_mlp_adam(hipStream_t s, int np, float* P, const float* g, float* m, float* v, int t, float lr,
+                    float b1, float b2, float eps);
+int launch_gather_rows5(hipStream_t s, int nb, const float* X, const float* y, const int* idx, float* Xb, float* yb);
+// features for the degree network from per-column (theta, r) and the filter bounds
+int launch_degree_features_ext(hipStream_t s, int m, const double* theta, const double* r, double a, double b,
+                               double mu1, double thr, const int* dprev, const float* norm, float* feat);

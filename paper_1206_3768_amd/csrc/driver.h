@@ -1,0 +1,80 @@
+// Host-side structures of the ChFSI library shared by the driver translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <functional>
+#include <vector>
+
+#include "chfsi.h"
+#include "common.h"
+
+// Grow-only device arena.  A first pass with `measuring` set sums the sizes of a buffer layout;
+// the second pass carves the buffers out of one allocation.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, off = 0;
+    bool measuring = false, failed = false;
+    void grow(size_t bytes);
+    void* get(size_t bytes);
+    template <class T> T* take(size_t count) { return (T*)get(count * sizeof(T)); }
+    void begin(bool measure) { off = 0; measuring = measure; failed = false; }
+};
+
+enum { PH_REDUCE = 0, PH_LANCZOS, PH_FILTER, PH_QR, PH_RR, PH_RESID, PH_LOCK, PH_BACK, PH_TOTAL, NPHASE };
+
+// hipEvent pairs per phase, summed after the final synchronisation of a solve
+struct PhaseTimer {
+    struct Span { int phase; hipEvent_t b, e; };
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Span> spans;
+    hipEvent_t open[NPHASE] = {};
+    ~PhaseTimer();
+    void mark(int phase, hipStream_t s, bool begin);
+    void collect(double* out);
+};
+
+struct chfsi_handle_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    rocblas_handle rb = nullptr;
+    Arena ws;
+    PhaseTimer timer;
+    std::vector<double> trace;
+    float* model = nullptr;        // device: MLP parameters followed by 10 normalisation constants
+    bool has_model = false;
+};
+
+// steps (solver.hip)
+chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, int* info_dev);
+chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed, zd* LV, zd* w,
+                          zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
+                          double& beta_k, int& k_used);
+chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
+                                 zd* G, zd* Cm, double* dsc, int* info_dev, void* ws, size_t wsb);
+chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY, zd* T,
+                                zd* G, double* theta_dev, double* E, double* r_dev, int* info_dev, void* ws,
+                                size_t wsb, PhaseTimer* tm);
+void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps);
+chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
+                        size_t wsb, double& flops, long long& matvecs);
+chfsi_status filter_f32(chfsi_handle h, int n, const zf* Hf, int ldh, int ma, zf* Yf, int ldy, zf* Tf,
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
+                        size_t wsb, double& flops, long long& matvecs);
+void host_tridiag_eig(int k, const double* al, const double* be, std::vector<double>& theta,
+                      std::vector<double>& z1sq);
+
+chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int nterms, int ma, zf* Yf, int ldy,
+                         zf* Tf, uint16_t* ysplit, const std::vector<int>& deg, double a, double b, double mu1,
+                         int* flag_dev, void* ws, size_t wsb, double& flops, long long& matvecs);
+// degree network (mlp.hip)
+chfsi_status learned_degrees(chfsi_handle h, int ma, const double* theta_dev, const double* r_dev, double a,
+                             double b, double mu1, double thr, const std::vector<int>& dprev, float* feat,
+                             float* dpred, int* iscr, int dmin, int dmax, int* out,
+                             const std::function<int(int)>& fallback);
+
+// extra small kernels (blas1.hip)
+int launch_zero_upper(hipStream_t s, int n, zd* L, int ldl);
+int launch_add_diag_const(hipStream_t s, int m, zd* G, int ldg, double shift);

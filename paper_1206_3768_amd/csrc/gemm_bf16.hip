@@ -1,0 +1,364 @@
+// BF16-split Chebyshev filter step on CDNA4 matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Each real operand x is split into bf16 terms x ~ x_0 + x_1 (+ x_2), every term the bf16
+// rounding (to nearest even) of what the previous terms leave.  A real product is then the sum of
+// the term products with t_x + t_y < nterms: 3 products for two terms ("x3", ~16 significant
+// bits) or 6 for three terms ("x6", ~24 bits, FP32-like), accumulated in FP32.  A complex product
+// is four real products: re += Hre Yre - Him Yim, im += Hre Yim + Him Yre.
+//
+// Layouts.  H is split once per solve into 2*nterms planes (term t, part re/im) stored row-major
+// (row i, k contiguous): since H is Hermitian, row i of H is the conjugate of column i, so each
+// plane row is written from one contiguous column.  Y_k (complex64) is split each step into planes
+// stored column-major (k contiguous).  Both are zero-padded to a multiple of 32 in k, so an MFMA
+// operand (8 consecutive k of one row or column) is one 16-byte load.  The MFMA A operand carries
+// Y (row = output column j) and the B operand carries H (column = output row i), as in the FP64
+// kernel, so each lane stores complete complex64 outputs of one row.
+#include "common.h"
+#include "driver.h"
+
+#include <vector>
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float x)
+{
+    uint32_t u;
+    __builtin_memcpy(&u, &x, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float x;
+    __builtin_memcpy(&x, &u, 4);
+    return x;
+}
+
+// split of a double (H) and of a float (Y): term t = bf16(float(remainder)), remainder -= term
+__device__ inline void split_terms_d(double x, int nterms, uint16_t* out)
+{
+    double r = x;
+    for (int t = 0; t < nterms; ++t) {
+        const uint16_t b = f32_to_bf16_rne((float)r);
+        out[t] = b;
+        r -= (double)bf16_to_f32(b);
+    }
+}
+
+__device__ inline void split_terms_f(float x, int nterms, uint16_t* out)
+{
+    float r = x;
+    for (int t = 0; t < nterms; ++t) {
+        const uint16_t b = f32_to_bf16_rne(r);
+        out[t] = b;
+        r -= bf16_to_f32(b);
+    }
+}
+
+inline int pad32(int n) { return (n + 31) / 32 * 32; }
+
+// H planes: plane (t, part) element (i, k) at planes[(2t + part) * np * np + i * np + k]
+//   = term t of Re/Im H[i, k] = term t of Re H[k, i], -Im H[k, i]  (H Hermitian)
+__global__ void k_split_h(int n, int np, const zd* __restrict__ H, int ldh, uint16_t* __restrict__ planes, int nterms)
+{
+    const size_t total = (size_t)np * np;
+    const size_t ps = total;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % np), i = (int)(e / np);   // consecutive threads: consecutive k of row i
+        zd v = make_double2(0.0, 0.0);
+        if (i < n && k < n) {
+            const zd c = H[(size_t)k + (size_t)i * ldh];   // column i, row k: contiguous in k
+            v = make_double2(c.x, -c.y);
+        }
+        uint16_t tr[3], ti[3];
+        split_terms_d(v.x, nterms, tr);
+        split_terms_d(v.y, nterms, ti);
+        for (int t = 0; t < nterms; ++t) {
+            planes[(size_t)(2 * t) * ps + e] = tr[t];
+            planes[(size_t)(2 * t + 1) * ps + e] = ti[t];
+        }
+    }
+}
+
+// Y planes: plane (t, part) element (k, j) at ys[(2t + part) * np * ncp + j * np + k]
+__global__ void k_split_y(int n, int np, int ncols, int ncp, const zf* __restrict__ Y, int ldy,
+                          uint16_t* __restrict__ ys, int nterms)
+{
+    const size_t total = (size_t)np * ncp;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % np), j = (int)(e / np);
+        zf v = make_float2(0.f, 0.f);
+        if (k < n && j < ncols) v = Y[(size_t)k + (size_t)j * ldy];
+        uint16_t tr[3], ti[3];
+        split_terms_f(v.x, nterms, tr);
+        split_terms_f(v.y, nterms, ti);
+        for (int t = 0; t < nterms; ++t) {
+            ys[(size_t)(2 * t) * total + e] = tr[t];
+            ys[(size_t)(2 * t + 1) * total + e] = ti[t];
+        }
+    }
+}
+
+__device__ inline int xcd_remap(int w, int nt)
+{
+    const int X = 8;
+    const int per = nt / X, rem = nt % X;
+    const int x = w % X, q = w / X;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
+struct BArgs {
+    int n, np, ncols, ncp, nterms;
+    const uint16_t* Hp;     // planes, row-major, np x np each
+    const uint16_t* Ys;     // planes, column-major, np x ncp each
+    const zf* Yk; int ldyk;
+    const zf* Yp; int ldyp;
+    zf* Yo; int ldyo;
+    float alpha, beta, shift;
+    zf* P;                  // split-K partials [ksplit][ncols][n]
+    int kchunk, tiles_m, tiles_n, ksplit;
+};
+
+template <int NT, bool PARTIAL>
+__global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
+{
+    constexpr int BM = 64, BN = 64, BK = 32;
+    constexpr int NPL = 2 * NT;                  // planes per operand
+    constexpr int RS = BK + 8;                   // LDS row stride in bf16 (80 bytes)
+    __shared__ __attribute__((aligned(16))) uint16_t Hs[2][NPL][BM * RS];
+    __shared__ __attribute__((aligned(16))) uint16_t Ys[2][NPL][BN * RS];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nt = g.tiles_m * g.tiles_n * g.ksplit;
+    const int tile = xcd_remap(blockIdx.x, nt);
+    const int jt = tile % g.tiles_n;
+    const int r1 = tile / g.tiles_n;
+    const int ks = r1 % g.ksplit;
+    const int it = r1 / g.ksplit;
+    const int i0 = it * BM, j0 = jt * BN;
+    const int kb = ks * g.kchunk;
+    const int ke = min(g.np, kb + g.kchunk);
+    const int nstages = ke > kb ? (ke - kb) / BK : 0;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+
+    f4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accr[a][b][r] = 0.f; acci[a][b][r] = 0.f; }
+
+    // global -> register: thread t moves 16 bytes (8 k) of row/col t/4, chunk t%4, per plane
+    const int lrow = tid >> 2, lch = tid & 3;
+    u4v rh[NPL], ry[NPL];
+    const size_t hps = (size_t)g.np * g.np, yps = (size_t)g.np * g.ncp;
+    auto gload = [&](int k0) {
+        const int gi = i0 + lrow, gj = j0 + lrow;
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) {
+            const uint16_t* hsrc = g.Hp + (size_t)p * hps + (size_t)gi * g.np + k0 + lch * 8;
+            rh[p] = gi < g.np ? *(const u4v*)hsrc : u4v{0, 0, 0, 0};
+            const uint16_t* ysrc = g.Ys + (size_t)p * yps + (size_t)gj * g.np + k0 + lch * 8;
+            ry[p] = gj < g.ncp ? *(const u4v*)ysrc : u4v{0, 0, 0, 0};
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) {
+            *(u4v*)&Hs[buf][p][lrow * RS + lch * 8] = rh[p];
+            *(u4v*)&Ys[buf][p][lrow * RS + lch * 8] = ry[p];
+        }
+    };
+    auto compute = [&](int buf) {
+        const int fr = lane & 15, fk = (lane >> 4) * 8;
+        u4v hf[2][NPL], yf[2][NPL];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) {
+                hf[b][p] = *(const u4v*)&Hs[buf][p][(wr + b * 16 + fr) * RS + fk];
+                yf[b][p] = *(const u4v*)&Ys[buf][p][(wc + b * 16 + fr) * RS + fk];
+            }
+#pragma unroll
+        for (int s = 0; s < NT; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (s + t >= NT) continue;
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj) {
+                        const bf8 hre = __builtin_bit_cast(bf8, hf[bi][2 * s]);
+                        const bf8 him = __builtin_bit_cast(bf8, hf[bi][2 * s + 1]);
+                        const bf8 yre = __builtin_bit_cast(bf8, yf[bj][2 * t]);
+                        const u4v ymi = yf[bj][2 * t + 1];
+                        const bf8 yim = __builtin_bit_cast(bf8, ymi);
+                        const bf8 nyim = __builtin_bit_cast(bf8, ymi ^ u4v{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u});
+                        accr[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yre, hre, accr[bi][bj], 0, 0, 0);
+                        acci[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yim, hre, acci[bi][bj], 0, 0, 0);
+                        accr[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nyim, him, accr[bi][bj], 0, 0, 0);
+                        acci[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yre, him, acci[bi][bj], 0, 0, 0);
+                    }
+            }
+    };
+
+    if (nstages > 0) {
+        gload(kb);
+        sstore(0);
+        __syncthreads();
+        for (int s = 0; s < nstages; ++s) {
+            const int buf = s & 1;
+            if (s + 1 < nstages) gload(kb + (s + 1) * BK);
+            compute(buf);
+            if (s + 1 < nstages) sstore(buf ^ 1);
+            __syncthreads();
+        }
+    }
+
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr + bi * 16 + (lane & 15);
+                const int j = j0 + wc + bj * 16 + (lane >> 4) * 4 + r;
+                if (i >= g.n || j >= g.ncols) continue;
+                const float vr = accr[bi][bj][r], vi = acci[bi][bj][r];
+                if (PARTIAL) {
+                    g.P[(size_t)ks * g.n * g.ncols + (size_t)i + (size_t)j * g.n] = make_float2(vr, vi);
+                } else {
+                    const zf yk = g.Yk[(size_t)i + (size_t)j * g.ldyk];
+                    const zf yp = g.Yp[(size_t)i + (size_t)j * g.ldyp];
+                    g.Yo[(size_t)i + (size_t)j * g.ldyo] =
+                        make_float2(g.alpha * (vr - g.shift * yk.x) + g.beta * yp.x,
+                                    g.alpha * (vi - g.shift * yk.y) + g.beta * yp.y);
+                }
+            }
+}
+
+__global__ void k_bf16_reduce(BArgs g)
+{
+    const size_t total = (size_t)g.n * g.ncols;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.n), j = (int)(e / g.n);
+        float vr = 0.f, vi = 0.f;
+        for (int s = 0; s < g.ksplit; ++s) {
+            const zf p = g.P[(size_t)s * total + e];
+            vr += p.x;
+            vi += p.y;
+        }
+        const zf yk = g.Yk[(size_t)i + (size_t)j * g.ldyk];
+        const zf yp = g.Yp[(size_t)i + (size_t)j * g.ldyp];
+        g.Yo[(size_t)i + (size_t)j * g.ldyo] = make_float2(g.alpha * (vr - g.shift * yk.x) + g.beta * yp.x,
+                                                         g.alpha * (vi - g.shift * yk.y) + g.beta * yp.y);
+    }
+}
+
+inline int grid_for(size_t total)
+{
+    size_t b = (total + 255) / 256;
+    return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+size_t bf16_ysplit_bytes(int n, int ncols, int nterms)
+{
+    const size_t np = (size_t)pad32(n), ncp = (size_t)(ncols + 63) / 64 * 64;
+    return 2 * (size_t)nterms * np * ncp * sizeof(uint16_t);
+}
+
+size_t bf16_hplanes_elems(int n, int nterms)
+{
+    const size_t np = (size_t)pad32(n);
+    return 2 * (size_t)nterms * np * np;
+}
+
+int launch_split_h_bf16(hipStream_t s, int n, const zd* H, int ldh, uint16_t* planes, int /*ldp*/, int nterms)
+{
+    const int np = pad32(n);
+    hipLaunchKernelGGL(k_split_h, dim3(grid_for((size_t)np * np)), dim3(256), 0, s, n, np, H, ldh, planes, nterms);
+    return (int)hipGetLastError();
+}
+
+int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hplanes, int /*ldp*/, int nterms,
+                            const zf* Yk, int ldyk, const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs,
+                            uint16_t* ysplit, void* ws, size_t ws_bytes)
+{
+    if (n <= 0 || ncols <= 0) return 0;
+    if (nterms != 2 && nterms != 3) return (int)hipErrorInvalidValue;
+    const int np = pad32(n), ncp = (ncols + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_split_y, dim3(grid_for((size_t)np * ncp)), dim3(256), 0, s, n, np, ncols, ncp, Yk, ldyk,
+                       ysplit, nterms);
+    BArgs g;
+    g.n = n; g.np = np; g.ncols = ncols; g.ncp = ncp; g.nterms = nterms;
+    g.Hp = Hplanes; g.Ys = ysplit; g.Yk = Yk; g.ldyk = ldyk; g.Yp = Yprev; g.ldyp = ldyp; g.Yo = Yout; g.ldyo = ldyo;
+    g.alpha = (float)fs.alpha; g.beta = (float)fs.beta; g.shift = (float)fs.shift;
+    g.P = (zf*)ws;
+    g.tiles_m = (n + 63) / 64;
+    g.tiles_n = (ncols + 63) / 64;
+    const long tiles = (long)g.tiles_m * g.tiles_n;
+    int ksp = 1;
+    while (tiles * ksp < 512 && np / (2 * ksp) >= 512) ksp *= 2;
+    while (ksp > 1 && (size_t)ksp * n * ncols * sizeof(zf) > ws_bytes) ksp /= 2;
+    int kc = (np + ksp - 1) / ksp;
+    kc = (kc + 31) / 32 * 32;
+    g.kchunk = kc;
+    g.ksplit = (np + kc - 1) / kc;
+    const int nt = g.tiles_m * g.tiles_n * g.ksplit;
+    const bool part = g.ksplit > 1;
+    if (nterms == 2) {
+        if (part) hipLaunchKernelGGL((k_filter_bf16<2, true>), dim3(nt), dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((k_filter_bf16<2, false>), dim3(nt), dim3(256), 0, s, g);
+    } else {
+        if (part) hipLaunchKernelGGL((k_filter_bf16<3, true>), dim3(nt), dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((k_filter_bf16<3, false>), dim3(nt), dim3(256), 0, s, g);
+    }
+    if (part) hipLaunchKernelGGL(k_bf16_reduce, dim3(grid_for((size_t)n * ncols)), dim3(256), 0, s, g);
+    return (int)hipGetLastError();
+}
+
+// Filter in BF16-split arithmetic; same sequencing as the FP64/FP32 filters (degrees sorted
+// non-increasing, columns finishing on odd steps copied back from T at the end).
+chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int nterms, int ma, zf* Yf, int ldy,
+                         zf* Tf, uint16_t* ysplit, const std::vector<int>& deg, double a, double b, double mu1,
+                         int* flag_dev, void* ws, size_t wsb, double& flops, long long& matvecs)
+{
+    hipStream_t st = h->stream;
+    if (ma <= 0 || deg[0] <= 0) return CHFSI_SUCCESS;
+    const int dmax = deg[0];
+    std::vector<FilterStep> steps;
+    filter_coefficients(dmax, a, b, mu1, steps);
+    for (int k = 1; k <= dmax; ++k) {
+        int w = 0;
+        while (w < ma && deg[w] >= k) ++w;
+        const zf* yk = (k % 2 == 1) ? Yf : Tf;
+        const int ldk = (k % 2 == 1) ? ldy : n;
+        zf* yo = (k % 2 == 1) ? Tf : Yf;
+        const int ldo = (k % 2 == 1) ? n : ldy;
+        const zf* yp = (k == 1) ? yk : yo;
+        const int ldp = (k == 1) ? ldk : ldo;
+        if (launch_filter_step_bf16(st, n, w, Hb, ldh, nterms, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ysplit, ws, wsb))
+            return CHFSI_ERR_DEVICE;
+        flops += 8.0 * (double)n * (double)n * (double)w;
+        matvecs += w;
+    }
+    std::vector<int> odd(ma);
+    bool any = false;
+    for (int j = 0; j < ma; ++j) { odd[j] = deg[j] % 2; any |= odd[j] != 0; }
+    if (any) {
+        if (hipMemcpyAsync(flag_dev, odd.data(), sizeof(int) * ma, hipMemcpyHostToDevice, st) != hipSuccess)
+            return CHFSI_ERR_DEVICE;
+        if (launch_copy_cols_flag_c(st, n, ma, Tf, n, Yf, ldy, flag_dev)) return CHFSI_ERR_DEVICE;
+        if (hipStreamSynchronize(st) != hipSuccess) return CHFSI_ERR_DEVICE;
+    }
+    return CHFSI_SUCCESS;
+}

@@ -1,0 +1,426 @@
+// Host driver of the ChFSI library: the C ABI of include/chfsi.h.
+//
+// The solver follows Algorithm 1 (Chebyshev filtered subspace iteration with locking) inside the
+// reduction of Section 3.2:
+//   reduction      S = L L^H, H = L^{-1} A L^{-H}          (rocSOLVER potrf + rocBLAS trsm)
+//   Lanczos        k steps, full reorthogonalisation      (own kernels; k x k eig on the host)
+//   loop           filter -> orthonormalise -> Rayleigh-Ritz -> residuals -> lock prefix
+//   back-transform X = L^{-H} Y and ||A x - lambda S x|| / ||A||_lo verification
+// Every matrix operation runs on the handle's stream; the host synchronises once per loop to read
+// the m_a Ritz values and residual norms it needs for the locking decision.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "chfsi.h"
+#include "driver.h"
+
+int chfsi_internal_hip_error(hipError_t e) { return (int)e; }
+
+// ---------------------------------------------------------------------------------------------
+// handle, workspace and timers
+// ---------------------------------------------------------------------------------------------
+
+void Arena::grow(size_t bytes)
+{
+    if (bytes <= cap) return;
+    if (base) (void)hipFree(base);
+    base = nullptr;
+    cap = 0;
+    if (hipMalloc((void**)&base, bytes) != hipSuccess) { base = nullptr; return; }
+    cap = bytes;
+}
+
+void* Arena::get(size_t bytes)
+{
+    size_t b = (bytes + 255) & ~(size_t)255;
+    if (measuring) { off += b; return (void*)(uintptr_t)256; }
+    if (!base || off + b > cap) { failed = true; return nullptr; }
+    void* p = base + off;
+    off += b;
+    return p;
+}
+
+PhaseTimer::~PhaseTimer()
+{
+    for (auto& e : pool) (void)hipEventDestroy(e);
+}
+
+void PhaseTimer::mark(int phase, hipStream_t s, bool begin)
+{
+    if (used == pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        pool.push_back(e);
+    }
+    hipEvent_t e = pool[used++];
+    (void)hipEventRecord(e, s);
+    if (begin) open[phase] = e;
+    else if (open[phase]) { spans.push_back({phase, open[phase], e}); open[phase] = nullptr; }
+}
+
+void PhaseTimer::collect(double* out /* [NPHASE] ms */)
+{
+    for (int i = 0; i < NPHASE; ++i) out[i] = 0;
+    for (auto& sp : spans) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, sp.b, sp.e) == hipSuccess) out[sp.phase] += ms;
+    }
+    spans.clear();
+    used = 0;
+    for (int i = 0; i < NPHASE; ++i) open[i] = nullptr;
+}
+
+const char* chfsi_status_string(chfsi_status s)
+{
+    switch (s) {
+    case CHFSI_SUCCESS: return "success";
+    case CHFSI_ERR_ARG: return "invalid argument";
+    case CHFSI_ERR_NOT_HPD: return "S is not Hermitian positive definite";
+    case CHFSI_ERR_NO_CONVERGENCE: return "no convergence within max_loops";
+    case CHFSI_ERR_NUMERIC: return "non-finite values or breakdown";
+    case CHFSI_ERR_DEVICE: return "HIP runtime error";
+    case CHFSI_ERR_ALLOC: return "allocation failed";
+    }
+    return "unknown status";
+}
+
+void chfsi_default_params(chfsi_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->nev = 0;
+    p->nex = 40;            // Table 3: blk = nev + 40
+    p->deg = 25;            // Table 3: degree 25
+    p->tol = 1e-10;         // Table 3: TOL 1e-10
+    p->max_loops = 50;
+    p->lanczos_steps = 25;  // within Table 3's "10 .. 3 blk"
+    p->filter_precision = CHFSI_FP64;
+    p->degree_policy = CHFSI_DEG_FIXED;
+    p->deg_min = 4;
+    p->deg_max = 30;
+    p->seed = 0;
+    p->have_bounds = 0;
+    p->trace = 0;
+    p->switch_residual = 0.0;
+}
+
+chfsi_status chfsi_create(chfsi_handle* out, int device, void* hip_stream)
+{
+    if (!out) return CHFSI_ERR_ARG;
+    *out = nullptr;
+    if (hipSetDevice(device) != hipSuccess) return CHFSI_ERR_DEVICE;
+    chfsi_handle h = new (std::nothrow) chfsi_handle_s();
+    if (!h) return CHFSI_ERR_ALLOC;
+    h->device = device;
+    h->stream = (hipStream_t)hip_stream;
+    if (rocblas_create_handle(&h->rb) != rocblas_status_success) { delete h; return CHFSI_ERR_DEVICE; }
+    rocblas_set_stream(h->rb, h->stream);
+    rocblas_set_pointer_mode(h->rb, rocblas_pointer_mode_host);
+    *out = h;
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_destroy(chfsi_handle h)
+{
+    if (!h) return CHFSI_ERR_ARG;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->ws.base) (void)hipFree(h->ws.base);
+    if (h->model) (void)hipFree(h->model);
+    if (h->rb) rocblas_destroy_handle(h->rb);
+    delete h;
+    return CHFSI_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------------------------
+// host-side small eigenproblem: symmetric tridiagonal T_k of Lanczos, cyclic Jacobi (k <= 3m).
+// ---------------------------------------------------------------------------------------------
+
+void host_tridiag_eig(int k, const double* al, const double* be, std::vector<double>& theta,
+                      std::vector<double>& z1sq)
+{
+    std::vector<double> T((size_t)k * k, 0.0), V((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        T[i + (size_t)i * k] = al[i];
+        V[i + (size_t)i * k] = 1.0;
+        if (i + 1 < k) { T[i + 1 + (size_t)i * k] = be[i]; T[i + (size_t)(i + 1) * k] = be[i]; }
+    }
+    double fro = 0;
+    for (double v : T) fro += v * v;
+    fro = std::sqrt(fro);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        bool any = false;
+        for (int p = 0; p < k - 1; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                const double apq = T[p + (size_t)q * k];
+                if (!(std::fabs(apq) > 1e-16 * fro)) continue;
+                any = true;
+                const double app = T[p + (size_t)p * k], aqq = T[q + (size_t)q * k];
+                const double th = (aqq - app) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int i = 0; i < k; ++i) {   // columns p, q
+                    const double x = T[i + (size_t)p * k], y = T[i + (size_t)q * k];
+                    T[i + (size_t)p * k] = c * x - s * y;
+                    T[i + (size_t)q * k] = s * x + c * y;
+                    const double vx = V[i + (size_t)p * k], vy = V[i + (size_t)q * k];
+                    V[i + (size_t)p * k] = c * vx - s * vy;
+                    V[i + (size_t)q * k] = s * vx + c * vy;
+                }
+                for (int i = 0; i < k; ++i) {   // rows p, q
+                    const double x = T[p + (size_t)i * k], y = T[q + (size_t)i * k];
+                    T[p + (size_t)i * k] = c * x - s * y;
+                    T[q + (size_t)i * k] = s * x + c * y;
+                }
+                T[p + (size_t)q * k] = 0.0;
+                T[q + (size_t)p * k] = 0.0;
+            }
+        if (!any) break;
+    }
+    std::vector<int> ord(k);
+    for (int i = 0; i < k; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return T[a + (size_t)a * k] < T[b + (size_t)b * k]; });
+    theta.resize(k);
+    z1sq.resize(k);
+    for (int j = 0; j < k; ++j) {
+        theta[j] = T[ord[j] + (size_t)ord[j] * k];
+        const double z = V[0 + (size_t)ord[j] * k];
+        z1sq[j] = z * z;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// steps of the method on device buffers
+// ---------------------------------------------------------------------------------------------
+
+static inline rocblas_double_complex* rbz(zd* p) { return reinterpret_cast<rocblas_double_complex*>(p); }
+static inline const rocblas_double_complex* rbz(const zd* p) { return reinterpret_cast<const rocblas_double_complex*>(p); }
+
+#define TRY(x)                                              \
+    do {                                                    \
+        int rc_ = (int)(x);                                 \
+        if (rc_ != 0) return CHFSI_ERR_DEVICE;              \
+    } while (0)
+#define TRYRB(x)                                            \
+    do {                                                    \
+        if ((x) != rocblas_status_success) return CHFSI_ERR_DEVICE; \
+    } while (0)
+
+// S = L L^H (L lower, strict upper part zeroed), H = L^{-1} A L^{-H}, Hermitized.
+chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
+                         int* info_dev)
+{
+    hipStream_t st = h->stream;
+    TRY(launch_zlacpy(st, n, n, S, lds, L, n));
+    TRY(hipMemsetAsync(info_dev, 0, sizeof(int), st));
+    TRYRB(rocsolver_zpotrf(h->rb, rocblas_fill_lower, n, rbz(L), n, info_dev));
+    int info = 0;
+    TRY(hipMemcpyAsync(&info, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    if (info != 0) return CHFSI_ERR_NOT_HPD;
+    TRY(launch_zero_upper(st, n, L, n));
+    TRY(launch_zlacpy(st, n, n, A, lda, H, n));
+    const rocblas_double_complex one(1.0, 0.0);
+    TRYRB(rocblas_ztrsm(h->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                        rocblas_diagonal_non_unit, n, n, &one, rbz(L), n, rbz(H), n));
+    TRYRB(rocblas_ztrsm(h->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                        rocblas_diagonal_non_unit, n, n, &one, rbz(L), n, rbz(H), n));
+    TRY(launch_hermitize(st, n, H, n));
+    return CHFSI_SUCCESS;
+}
+
+// k-step Lanczos with full reorthogonalisation (two classical Gram-Schmidt passes per step).
+chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed, zd* LV,
+                          zd* w, zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
+                          double& beta_k, int& k_used)
+{
+    hipStream_t st = h->stream;
+    double* al = coef_dev;             // [k]
+    double* be = coef_dev + k;         // [k]
+    double* scr = coef_dev + 2 * k;    // [8] scratch
+    TRY(launch_philox_block(st, seed, 2, n, 1, LV, n));
+    TRY(launch_lanczos_normalize(st, n, LV, LV, scr));
+    for (int j = 0; j < k; ++j) {
+        zd* vj = LV + (size_t)j * n;
+        TRY(launch_coldots(st, n, n, H, ldh, vj, w));           // w = H v_j (H Hermitian)
+        TRY(launch_lanczos_alpha(st, n, vj, w, j > 0 ? vj - n : nullptr, scr, j > 0 ? be + j - 1 : nullptr));
+        TRY(hipMemcpyAsync(al + j, scr, sizeof(double), hipMemcpyDeviceToDevice, st));
+        for (int pass = 0; pass < 2; ++pass) {
+            TRY(launch_coldots(st, n, j + 1, LV, n, w, c));
+            TRY(launch_gemv_n(st, n, j + 1, LV, n, c, -1.0, w));
+        }
+        TRY(launch_lanczos_normalize(st, n, w, LV + (size_t)(j + 1) * n, be + j));
+    }
+    std::vector<double> hal(k), hbe(k);
+    TRY(hipMemcpyAsync(hal.data(), al, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(hbe.data(), be, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    int kk = k;
+    for (int j = 0; j < k; ++j)
+        if (!(hbe[j] > 1e-300)) { kk = j + 1; break; }
+    for (int j = 0; j < kk; ++j)
+        if (!std::isfinite(hal[j]) || !std::isfinite(hbe[j])) return CHFSI_ERR_NUMERIC;
+    host_tridiag_eig(kk, hal.data(), hbe.data(), theta, z1sq);
+    beta_k = hbe[kk - 1];
+    k_used = kk;
+    return CHFSI_SUCCESS;
+}
+
+// Y (n x ma) <- orthonormal basis: CGS twice against the nl locked columns YL, then shifted
+// Cholesky QR followed by two Cholesky QR passes (shift s = 11 (n m + m (m+1)) u ||Y||_F^2 after
+// column normalisation; Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SISC 2020).  R's
+// diagonal is real positive in every pass, so Q is the Q factor of Y.
+chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
+                                 zd* G, zd* Cm, double* dsc, int* info_dev, void* ws, size_t wsb)
+{
+    hipStream_t st = h->stream;
+    if (ma <= 0) return CHFSI_SUCCESS;
+    if (nl > 0)
+        for (int pass = 0; pass < 2; ++pass) {
+            TRY(launch_zgemm(st, OP_C, OP_N, nl, ma, n, 1.0, YL, ldyl, Y, ldy, 0.0, Cm, nl, ws, wsb));
+            TRY(launch_zgemm(st, OP_N, OP_N, n, ma, nl, -1.0, YL, ldyl, Cm, nl, 1.0, Y, ldy, ws, wsb));
+        }
+    TRY(launch_colnorms(st, n, ma, Y, ldy, dsc));
+    TRY(launch_scale_cols_inv(st, n, ma, Y, ldy, dsc));
+    const double u = 1.1102230246251565e-16;
+    const double shift = 11.0 * ((double)n * ma + (double)ma * (ma + 1)) * u * (double)ma;
+    const rocblas_double_complex one(1.0, 0.0);
+    for (int pass = 0; pass < 3; ++pass) {
+        TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, Y, ldy, 0.0, G, ma, ws, wsb));
+        if (pass == 0) TRY(launch_add_diag_const(st, ma, G, ma, shift));
+        TRYRB(rocsolver_zpotrf(h->rb, rocblas_fill_upper, ma, rbz(G), ma, info_dev + pass));
+        TRYRB(rocblas_ztrsm(h->rb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                            rocblas_diagonal_non_unit, n, ma, &one, rbz(G), ma, rbz(Y), ldy));
+    }
+    return CHFSI_SUCCESS;
+}
+
+// Rayleigh-Ritz on orthonormal Y (n x ma): HY = H Y, G = Y^H HY, G = W diag(theta) W^H (ascending,
+// phase-normalised W), Y <- Y W, HY <- HY W, then r_j = ||HY_j - theta_j Y_j||.
+chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY,
+                                zd* T, zd* G, double* theta_dev, double* E, double* r_dev, int* info_dev,
+                                void* ws, size_t wsb, PhaseTimer* tm)
+{
+    hipStream_t st = h->stream;
+    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, n, 1.0, H, ldh, Y, ldy, 0.0, HY, n, ws, wsb));
+    TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, HY, n, 0.0, G, ma, ws, wsb));
+    TRYRB(rocsolver_zheevd(h->rb, rocblas_evect_original, rocblas_fill_lower, ma, rbz(G), ma, theta_dev, E,
+                           info_dev));
+    TRY(launch_phase_normalize(st, ma, ma, G, ma));
+    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, 1.0, Y, ldy, G, ma, 0.0, T, n, ws, wsb));
+    TRY(launch_zlacpy(st, n, ma, T, n, Y, ldy));
+    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, 1.0, HY, n, G, ma, 0.0, T, n, ws, wsb));
+    TRY(launch_zlacpy(st, n, ma, T, n, HY, n));
+    if (tm) tm->mark(PH_RESID, st, true);
+    TRY(launch_residual_norms(st, n, ma, HY, n, Y, ldy, theta_dev, r_dev));
+    if (tm) tm->mark(PH_RESID, st, false);
+    return CHFSI_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------------------------
+// the Chebyshev filter
+// ---------------------------------------------------------------------------------------------
+
+// Scaled recurrence coefficients: step 1 has alpha = sigma_1/e, beta = 0; step k+1 (k >= 1) has
+// sigma_{k+1} = 1/(2/sigma_1 - sigma_k), alpha = 2 sigma_{k+1}/e, beta = -sigma_k sigma_{k+1}.
+void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps)
+{
+    const double c = 0.5 * (a + b), e = 0.5 * (b - a);
+    const double sigma1 = e / (mu1 - c);
+    steps.resize(dmax);
+    double sigma = sigma1;
+    for (int k = 0; k < dmax; ++k) {
+        FilterStep fs;
+        fs.shift = c;
+        if (k == 0) {
+            fs.alpha = sigma1 / e;
+            fs.beta = 0.0;
+        } else {
+            const double sn = 1.0 / (2.0 / sigma1 - sigma);
+            fs.alpha = 2.0 * sn / e;
+            fs.beta = -sigma * sn;
+            sigma = sn;
+        }
+        steps[k] = fs;
+    }
+}
+
+// Filters the ma columns of Y whose degrees deg[] are sorted in non-increasing order.  T is a
+// second n x ma buffer.  Step k (1-based) updates the first #{j : deg[j] >= k} columns; columns
+// finishing on an odd step are copied back from T at the end (flag buffer on device).
+template <typename C2, typename HT>
+chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma, C2* Y, int ldy, C2* T, int ldt,
+                           const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev,
+                           void* ws, size_t wsb, double& flops, long long& matvecs,
+                           int (*step_fn)(hipStream_t, int, int, const HT*, int, const C2*, int, const C2*, int,
+                                          C2*, int, FilterStep, void*, size_t),
+                           int (*copy_fn)(hipStream_t, int, int, const C2*, int, C2*, int, const int*))
+{
+    hipStream_t st = h->stream;
+    if (ma <= 0) return CHFSI_SUCCESS;
+    const int dmax = deg[0];
+    if (dmax <= 0) return CHFSI_SUCCESS;
+    std::vector<FilterStep> steps;
+    filter_coefficients(dmax, a, b, mu1, steps);
+    for (int k = 1; k <= dmax; ++k) {
+        int w = 0;
+        while (w < ma && deg[w] >= k) ++w;
+        // Y_k lives in Y when k is even, in T when k is odd; Y_{k-1} in the other one
+        const C2* yk = (k % 2 == 1) ? Y : T;        // input Y_{k-1}
+        const int ldk = (k % 2 == 1) ? ldy : ldt;
+        C2* yo = (k % 2 == 1) ? T : Y;              // output Y_k overwrites Y_{k-2}
+        const int ldo = (k % 2 == 1) ? ldt : ldy;
+        const C2* yp = (k == 1) ? yk : yo;          // beta == 0 on step 1: any finite input
+        const int ldp = (k == 1) ? ldk : ldo;
+        TRY(step_fn(st, n, w, Hm, ldh, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ws, wsb));
+        flops += 8.0 * (double)n * (double)n * (double)w;
+        matvecs += w;
+    }
+    // columns with an odd degree finished in T
+    std::vector<int> odd(ma);
+    bool any = false;
+    for (int j = 0; j < ma; ++j) { odd[j] = deg[j] % 2; any |= odd[j] != 0; }
+    if (any) {
+        TRY(hipMemcpyAsync(flag_dev, odd.data(), sizeof(int) * ma, hipMemcpyHostToDevice, st));
+        TRY(copy_fn(st, n, ma, T, ldt, Y, ldy, flag_dev));
+        // the host vector must stay alive until the copy has been consumed
+        TRY(hipStreamSynchronize(st));
+    }
+    return CHFSI_SUCCESS;
+}
+
+static int step_f64(hipStream_t s, int n, int w, const zd* H, int ldh, const zd* yk, int ldk, const zd* yp, int ldp,
+                    zd* yo, int ldo, FilterStep fs, void* ws, size_t wsb)
+{
+    return launch_filter_step_f64(s, n, w, H, ldh, yk, ldk, yp, ldp, yo, ldo, fs, ws, wsb);
+}
+static int step_f32(hipStream_t s, int n, int w, const zf* H, int ldh, const zf* yk, int ldk, const zf* yp, int ldp,
+                    zf* yo, int ldo, FilterStep fs, void* ws, size_t wsb)
+{
+    return launch_filter_step_f32(s, n, w, H, ldh, yk, ldk, yp, ldp, yo, ldo, fs, ws, wsb);
+}
+
+chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
+                        size_t wsb, double& flops, long long& matvecs)
+{
+    return filter_sorted<zd, zd>(h, n, H, ldh, ma, Y, ldy, T, n, deg, a, b, mu1, flag_dev, ws, wsb, flops, matvecs,
+                                 step_f64, launch_copy_cols_flag);
+}
+
+chfsi_status filter_f32(chfsi_handle h, int n, const zf* Hf, int ldh, int ma, zf* Yf, int ldy, zf* Tf,
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
+                        size_t wsb, double& flops, long long& matvecs)
+{
+    return filter_sorted<zf, zf>(h, n, Hf, ldh, ma, Yf, ldy, Tf, n, deg, a, b, mu1, flag_dev, ws, wsb, flops,
+                                 matvecs, step_f32, launch_copy_cols_flag_c);
+}
