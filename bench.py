@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark: Chebyshev-filtered subspace iteration on one MI355X.
+
+Workload (default, ``seq2048``): the 10-cycle sequence of correlated generalized problems,
+complex128, n = 2048, S = I + G G^H / n, A_0 in designed form with the lowest 5 % of the spectrum
+clustered, A_{l+1} = A_l + 1e-2 0.5^l (E + E^H)/2, nev = 128, nex = 64, degree 12, FP64.
+
+A step is one warm-started solve of one cycle (reduction, Lanczos, filter/QR/Rayleigh-Ritz/locking
+loop, back-transform and verification), with the inputs resident in HBM.  Before the timed
+region the whole sequence is solved once (cycle 0 from a random block, each later cycle from the
+previous solution); timed step s re-solves cycle 1 + (s mod 9) from the stored solution of the
+cycle before it.
+
+Printed JSON (one line): value = filter TFLOP/s over the timed steps (8 n^2 flops per filtered
+vector and degree, divided by the filter phase time), ms_per_step = time to solution per cycle,
+roofline of the dominant kernel (the FP64 filter step) from hipEvents around each of its launches,
+and the CPU reference timed on a bounded sample.  Extra fields: random-start times and the
+warm/random speed-up per cycle, and the mixed-precision filter variants on the same cycles.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # TFLOP/s, MI355X dense matrix peaks
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gemm.hip",):
+        with open(os.path.join(ROOT, "paper_1206_3768_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"filter_f64_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(seq_spec, pencils_host, x_prev, lam_prev) -> dict:
+    """The CPU reference as it stands, on a bounded sample of the same workload: one filter of the
+    full n x m block at the workload's degree (gives the TFLOP/s figure) and one warm-started solve
+    of cycle 1 (time to solution)."""
+    import oracle
+    n, m, d = seq_spec.n, seq_spec.nev + seq_spec.nex, seq_spec.deg
+    rng = np.random.default_rng(0)
+    Y = (rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))) / np.sqrt(2)
+    H = pencils_host[0].A
+    t0 = time.perf_counter()
+    oracle.cheb_filter(H, Y, -0.3, 1.5, -1.0, deg=d)
+    tf = time.perf_counter() - t0
+    flops = 8.0 * n * n * m * d
+    pen = pencils_host[1]
+    t0 = time.perf_counter()
+    r = oracle.solve(pen.A, pen.S, nev=seq_spec.nev, nex=seq_spec.nex, deg=d, tol=1e-10, X0=x_prev,
+                     bounds=(lam_prev[0], lam_prev[-1]), seed=seq_spec.seed)
+    ts = time.perf_counter() - t0
+    return {"value": flops / tf / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle filter of one {n}x{m} block at degree {d} ({tf:.2f} s) and one warm-started "
+                      f"solve of cycle 1 ({ts:.2f} s, {r.stats['loops']} loops, status {r.status})",
+            "time_to_solution_ms": ts * 1e3, "filter_s": tf}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=9)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="seq2048", choices=["seq2048"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the random-start and mixed-precision runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported (this build has no "
+              "multi-GPU path: see DESIGN.md, 'How the path would shard')", file=sys.stderr)
+        return 2
+    import torch
+    from paper_1206_3768_amd import chfsi, sequence, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    spec = synth.config_generalized_sequence()
+    n, m = spec.n, spec.nev + spec.nex
+    log(f"generating {spec.cycles} cycles, n={n}, nev={spec.nev}, nex={spec.nex}")
+    t0 = time.perf_counter()
+    seq = sequence.Sequence(spec, keep_host=not args.no_cpu_baseline)
+    log(f"inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
+
+    ref = seq.run_reference()
+    bad = [r.cycle for r in ref if r.status != 0]
+    if bad:
+        log(f"reference pass failed on cycles {bad}")
+        return 1
+    log("reference pass: loops per cycle " + " ".join(str(r.stats["loops"]) for r in ref))
+
+    cycles = [1 + (s % (spec.cycles - 1)) for s in range(args.warmup + args.steps)]
+    work = seq.new_block()
+    for c in cycles[:args.warmup]:
+        seq.solve(c, warm=True, X=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timed = [seq.solve(c, warm=True, X=work) for c in cycles[args.warmup:]]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for r in timed:
+        if r.status != 0 or r.resid[:spec.nev].max() > 1e-10:
+            log(f"timed solve of cycle {r.cycle} failed: status {r.status}, max resid {r.resid[:spec.nev].max():.2e}")
+            return 1
+    flops = sum(r.stats["filter_flops"] for r in timed)
+    t_filter = sum(r.stats["t_filter"] for r in timed) * 1e-3
+    t_kern = sum(r.stats["t_filter_kernels"] for r in timed) * 1e-3
+    launches = sum(r.stats["filter_launches"] for r in timed)
+    value = flops / t_filter / 1e12
+    achieved = flops / t_kern / 1e12
+    log(f"timed {args.steps} warm solves: {wall / args.steps * 1e3:.2f} ms/solve, filter {value:.2f} TFLOP/s, "
+        f"filter kernels {achieved:.2f} TFLOP/s over {launches} launches")
+
+    out = {
+        "metric": "Filter TFLOP/s + time-to-solution @res<=1e-10, mixed/learned vs FP64",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "seq2048: 10-cycle correlated generalized sequence, complex128, n=2048, "
+                               "nev=128, nex=64, degree 12, warm start, FP64",
+                   "n": n, "nev": spec.nev, "nex": spec.nex, "deg": spec.deg, "cycles": spec.cycles},
+        "time_to_solution_ms": {"median": round(statistics.median(r.wall_ms for r in timed), 3),
+                                "per_cycle": {str(r.cycle): round(r.wall_ms, 3) for r in timed}},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["f64"], 4), "traffic": load_traffic(args.workload),
+                     "kernel": "k_zgemm<double, N, N, filter epilogue> (one launch per filter step)",
+                     "flops_per_launch": flops / max(launches, 1),
+                     "avg_launch_ms": t_kern / max(launches, 1) * 1e3, "launches": launches},
+    }
+
+    if not args.no_extras:
+        # E4 protocol: random start vs warm start per cycle
+        rnd = {}
+        for c in range(1, spec.cycles):
+            r = seq.solve(c, warm=False, X=work)
+            rnd[c] = r
+        warm_ms = {}
+        for r in timed:
+            warm_ms.setdefault(r.cycle, r.wall_ms)
+        out["warm_vs_random"] = {
+            str(c): {"t_app_ms": round(warm_ms.get(c, float("nan")), 3), "t_rnd_ms": round(rnd[c].wall_ms, 3),
+                     "speedup": round(rnd[c].wall_ms / warm_ms[c], 3) if c in warm_ms else None,
+                     "loops_app": next((r.stats["loops"] for r in timed if r.cycle == c), None),
+                     "loops_rnd": rnd[c].stats["loops"]} for c in range(1, spec.cycles)}
+        # mixed-precision filters on the same warm-started cycles
+        mixed = {}
+        for name in ("fp32", "bf16x6", "bf16x3"):
+            rs = [seq.solve(c, warm=True, X=work, filter_precision=name) for c in range(1, spec.cycles)]
+            ok = all(r.status == 0 for r in rs)
+            errs = [float(np.max(np.abs(r.lam[:spec.nev] - seq.lam[r.cycle][:spec.nev]) /
+                                 np.maximum(np.abs(seq.lam[r.cycle][:spec.nev]), 1e-3))) for r in rs if r.status == 0]
+            mixed[name] = {"all_converged": ok,
+                           "time_to_solution_ms_total": round(sum(r.wall_ms for r in rs), 3),
+                           "fp64_total_ms": round(sum(warm_ms.get(r.cycle, float("nan")) for r in rs), 3),
+                           "max_rel_eig_err_vs_fp64": max(errs) if errs else None,
+                           "max_resid": float(max(r.resid[:spec.nev].max() for r in rs)),
+                           "loops": [r.stats["loops"] for r in rs],
+                           "precision_switches": [r.stats["precision_switches"] for r in rs]}
+        out["mixed_precision"] = mixed
+        an = [seq.solve(c, warm=True, X=work, degree_policy=1) for c in range(1, spec.cycles)]
+        out["analytic_degree"] = {"time_to_solution_ms_total": round(sum(r.wall_ms for r in an), 3),
+                                  "all_converged": all(r.status == 0 for r in an),
+                                  "matvecs": [r.stats["matvecs"] for r in an]}
+        phase = {k: round(sum(r.stats[k] for r in timed) / len(timed), 3)
+                 for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid", "t_lock", "t_back",
+                           "t_total")}
+        out["phase_ms_per_solve"] = phase
+
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle) on a bounded sample ...")
+        x_prev = chfsi.to_numpy(seq.X[0])
+        out["cpu_baseline"] = cpu_baseline(spec, seq.host, x_prev, seq.lam[0])
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

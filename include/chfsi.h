@@ -86,6 +86,8 @@ typedef struct {
     double norm_a;                /* largest column 2-norm of A (lower bound of ||A||_2)        */
     int lanczos_steps;            /* Lanczos steps taken                                        */
     int precision_switches;       /* vectors moved from low precision to FP64                   */
+    int filter_launches;          /* filter-step kernel launches                                */
+    double t_filter_kernels;      /* ms: sum of hipEvent-timed filter-step launches             */
     int status;                   /* chfsi_status of this solve                                 */
 } chfsi_stats;
 
@@ -139,6 +141,11 @@ chfsi_status chfsi_solve_batched(chfsi_handle h, int count, const chfsi_problem*
  * Requires mu1 < a < b.  This is the hot path exposed for tests and benchmarks. */
 chfsi_status chfsi_filter(chfsi_handle h, int n, const void* H, int ldh, void* Y, int ldy, int m,
                           const int* deg, int deg_uniform, double a, double b, double mu1, int prec);
+
+/* Event timing of the filter-step launches of the last chfsi_solve / chfsi_filter on this handle:
+ * *total_ms = sum over launches of the time between hipEvents recorded on the handle's stream just
+ * before and just after each launch, *launches = their number (host pointers). */
+chfsi_status chfsi_filter_kernel_time(chfsi_handle h, double* total_ms, int* launches);
 
 /* Step-level entry points (the pieces chfsi_solve is made of), for parity tests.
  *  chfsi_reduce:  L L^H = S, H = L^{-1} A L^{-H} (Hermitized).  H, L: n x n device outputs

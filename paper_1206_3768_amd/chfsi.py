@@ -50,7 +50,8 @@ class Stats(C.Structure):
                 ("t_qr", C.c_double), ("t_rr", C.c_double), ("t_resid", C.c_double), ("t_lock", C.c_double),
                 ("t_back", C.c_double), ("t_total", C.c_double), ("mu1", C.c_double), ("a", C.c_double),
                 ("b", C.c_double), ("norm_a", C.c_double), ("lanczos_steps", C.c_int),
-                ("precision_switches", C.c_int), ("status", C.c_int)]
+                ("precision_switches", C.c_int), ("filter_launches", C.c_int), ("t_filter_kernels", C.c_double),
+                ("status", C.c_int)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -65,7 +66,8 @@ class Problem(C.Structure):
 EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solve", "chfsi_solve_batched",
             "chfsi_filter", "chfsi_reduce", "chfsi_lanczos", "chfsi_orthonormalize", "chfsi_rayleigh_ritz",
             "chfsi_zgemm", "chfsi_random_block", "chfsi_set_degree_model", "chfsi_get_trace", "chfsi_mlp_forward",
-            "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string"]
+            "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string",
+            "chfsi_filter_kernel_time"]
 
 
 def load():
@@ -96,6 +98,7 @@ def load():
     lib.chfsi_mlp_loss_grad.argtypes = [vp, vp, i, vp, vp, C.c_float, C.c_float, vp, vp]
     lib.chfsi_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i, C.c_float, C.c_float, C.c_float, C.c_float]
     lib.chfsi_mlp_train.argtypes = [vp, vp, i, vp, vp, C.c_float, C.c_float, i, i, C.c_float, u, vp]
+    lib.chfsi_filter_kernel_time.argtypes = [vp, vp, vp]
     lib.chfsi_status_string.argtypes = [i]
     lib.chfsi_status_string.restype = C.c_char_p
     _lib = lib
@@ -221,6 +224,12 @@ class Handle:
             dp, du = dv.ctypes.data, 0
         self._check(self.lib.chfsi_filter(self.h, n, _ptr(H), H.shape[-1], _ptr(Y), Y.shape[-1], m, dp, du,
                                           a, b, mu1, prec), "chfsi_filter")
+
+    def filter_kernel_time(self):
+        """(total ms, launches) of the filter-step kernels of the last solve/filter call."""
+        t = np.zeros(1); c = np.zeros(1, dtype=np.int32)
+        self._check(self.lib.chfsi_filter_kernel_time(self.h, t.ctypes.data, c.ctypes.data), "chfsi_filter_kernel_time")
+        return float(t[0]), int(c[0])
 
     def reduce(self, A, S, H, L):
         self._check(self.lib.chfsi_reduce(self.h, A.shape[-1], _ptr(A), A.shape[-1], _ptr(S), S.shape[-1],

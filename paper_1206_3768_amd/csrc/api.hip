@@ -43,8 +43,7 @@ struct SolveBufs {
     double* lcoef = nullptr;
     float* feat = nullptr;
     float* dpred = nullptr;
-    void* splitws = nullptr;
-    size_t splitws_bytes = 0;
+    GemmWs gw;                         // split-K partials + the handle's tile counters
 };
 
 void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
@@ -86,8 +85,8 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
     // split-K partials: the largest of the filter (n x m, K = n) and the Gram products (m x m, K = n)
     size_t ws = std::max(zgemm_ws_bytes(n, m, n, 16), zgemm_ws_bytes(m, m, n, 16));
     ws = std::max(ws, zgemm_ws_bytes(n, m, m, 16));
-    b.splitws_bytes = ws;
-    b.splitws = ar.get(ws);
+    b.gw.bytes = ws;
+    b.gw.ws = ar.get(ws);
 }
 
 chfsi_status prepare(chfsi_handle h, SolveBufs& b, int n, int m, int k, bool gen, int prec)
@@ -103,6 +102,8 @@ chfsi_status prepare(chfsi_handle h, SolveBufs& b, int n, int m, int k, bool gen
     h->ws.begin(false);
     b = SolveBufs();
     layout(h->ws, b, n, m, k, gen, prec);
+    b.gw.cnt = h->tile_cnt;
+    b.gw.ncnt = h->tile_cnt_len;
     return h->ws.failed ? CHFSI_ERR_ALLOC : CHFSI_SUCCESS;
 }
 
@@ -149,12 +150,12 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
         std::vector<int> dl(deg.begin(), deg.begin() + nlow);
         TRY(launch_z2c(st, n, nlow, Y, ldy, b.Vf, n));
         if (prec == CHFSI_FP32) {
-            TRYS(filter_f32(h, n, b.Hf, n, nlow, b.Vf, n, b.Tf, dl, a, bb, mu1, b.flag, b.splitws, b.splitws_bytes,
+            TRYS(filter_f32(h, n, b.Hf, n, nlow, b.Vf, n, b.Tf, dl, a, bb, mu1, b.flag, b.gw,
                             flops, matvecs));
         } else {
             const int nterms = prec == CHFSI_BF16X3 ? 2 : 3;
             TRYS(filter_bf16(h, n, b.Hb, n, nterms, nlow, b.Vf, n, b.Tf, b.ysplit, dl, a, bb, mu1, b.flag,
-                             b.splitws, b.splitws_bytes, flops, matvecs));
+                             b.gw, flops, matvecs));
         }
         TRY(launch_c2z(st, n, nlow, b.Vf, n, Y, ldy));
     }
@@ -162,8 +163,7 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
     const int off = ma - n64;
     if (n64 > 0) {
         std::vector<int> dh(deg.begin() + off, deg.end());
-        TRYS(filter_f64(h, n, H, ldh, n64, Y + (size_t)off * ldy, ldy, b.T, dh, a, bb, mu1, b.flag, b.splitws,
-                        b.splitws_bytes, flops, matvecs));
+        TRYS(filter_f64(h, n, H, ldh, n64, Y + (size_t)off * ldy, ldy, b.T, dh, a, bb, mu1, b.flag, b.gw, flops, matvecs));
     }
     return CHFSI_SUCCESS;
 }
@@ -181,11 +181,11 @@ chfsi_status finalize(chfsi_handle h, SolveBufs& b, int n, int m, const zd* A, i
                           reinterpret_cast<rocblas_double_complex*>(X), ldx) != rocblas_status_success)
             return CHFSI_ERR_DEVICE;
     }
-    TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, A, lda, X, ldx, 0.0, b.HY, n, b.splitws, b.splitws_bytes));
+    TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, A, lda, X, ldx, 0.0, b.HY, n, b.gw));
     const zd* SX = X;
     int ldsx = ldx;
     if (S) {
-        TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, S, lds, X, ldx, 0.0, b.T, n, b.splitws, b.splitws_bytes));
+        TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, S, lds, X, ldx, 0.0, b.T, n, b.gw));
         SX = b.T;
         ldsx = n;
     }
@@ -222,6 +222,7 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
     {
         double reset[NPHASE];
         tm.collect(reset);
+        (void)h->ktimer.collect(nullptr);
     }
     auto t0 = std::chrono::steady_clock::now();
     tm.mark(PH_TOTAL, st, true);
@@ -247,7 +248,7 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
         TRY(launch_split_h_bf16(st, n, H, ldh, b.Hb, n, prec == CHFSI_BF16X3 ? 2 : 3));
     // starting block in standard coordinates
     if (x_is_guess) {
-        if (S) TRY(launch_zgemm(st, OP_C, OP_N, n, m, n, 1.0, b.L, n, X, ldx, 0.0, b.V, n, b.splitws, b.splitws_bytes));
+        if (S) TRY(launch_zgemm(st, OP_C, OP_N, n, m, n, 1.0, b.L, n, X, ldx, 0.0, b.V, n, b.gw));
         else TRY(launch_zlacpy(st, n, m, X, ldx, b.V, n));
     } else {
         TRY(launch_philox_block(st, p.seed, 1, n, m, b.V, n));
@@ -310,13 +311,11 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
 
         tm.mark(PH_QR, st, true);
         TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, st));
-        TRYS(step_orthonormalize(h, n, ma, Ya, n, nlocked, b.V, n, b.G, b.Cm, b.dsc, b.info, b.splitws,
-                                 b.splitws_bytes));
+        TRYS(step_orthonormalize(h, n, ma, Ya, n, nlocked, b.V, n, b.G, b.Cm, b.dsc, b.info, b.gw));
         tm.mark(PH_QR, st, false);
 
         tm.mark(PH_RR, st, true);
-        TRYS(step_rayleigh_ritz(h, n, H, ldh, ma, Ya, n, b.HY, b.T, b.G, b.theta, b.E, b.r, b.info + 4, b.splitws,
-                                b.splitws_bytes, &tm));
+        TRYS(step_rayleigh_ritz(h, n, H, ldh, ma, Ya, n, b.HY, b.T, b.G, b.theta, b.E, b.r, b.info + 4, b.gw, &tm));
         tm.mark(PH_RR, st, false);
 
         tm.mark(PH_LOCK, st, true);
@@ -416,6 +415,9 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
     stt.filter_flops = flops;
     stt.mu1 = mu1; stt.a = a; stt.b = bb;
     stt.precision_switches = switches;
+    stt.t_filter_kernels = h->ktimer.collect(&stt.filter_launches);
+    h->last_kernel_ms = stt.t_filter_kernels;
+    h->last_kernel_launches = stt.filter_launches;
     stt.status = status;
     if (p.trace) {
         h->trace.clear();
@@ -490,6 +492,7 @@ chfsi_status chfsi_filter(chfsi_handle h, int n, const void* Hv, int ldh, void* 
     if (prec == CHFSI_FP32) TRY(launch_z2c(st, n, n, H, ldh, bf.Hf, n));
     if (prec == CHFSI_BF16X3 || prec == CHFSI_BF16X6)
         TRY(launch_split_h_bf16(st, n, H, ldh, bf.Hb, n, prec == CHFSI_BF16X3 ? 2 : 3));
+    (void)h->ktimer.collect(nullptr);
     // the filter permutes columns by degree; undo that here so the caller sees its own order
     std::vector<int> ord(m);
     std::iota(ord.begin(), ord.end(), 0);
@@ -505,6 +508,15 @@ chfsi_status chfsi_filter(chfsi_handle h, int n, const void* Hv, int ldh, void* 
     TRY(hipMemcpyAsync(bf.iperm, inv.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
     TRY(launch_permute_cols(st, n, m, bf.V, n, Y, ldy, bf.iperm));
     TRY(hipStreamSynchronize(st));
+    h->last_kernel_ms = h->ktimer.collect(&h->last_kernel_launches);
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_filter_kernel_time(chfsi_handle h, double* total_ms, int* launches)
+{
+    if (!h || !total_ms || !launches) return CHFSI_ERR_ARG;
+    *total_ms = h->last_kernel_ms;
+    *launches = h->last_kernel_launches;
     return CHFSI_SUCCESS;
 }
 
@@ -545,8 +557,7 @@ chfsi_status chfsi_orthonormalize(chfsi_handle h, int n, int m, void* Y, int ldy
     const int mm = std::max(m, nl);
     TRYS(prepare(h, b, n, mm, 1, false, CHFSI_FP64));
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, h->stream));
-    TRYS(step_orthonormalize(h, n, m, (zd*)Y, ldy, nl, (const zd*)YL, ldyl, b.G, b.Cm, b.dsc, b.info, b.splitws,
-                             b.splitws_bytes));
+    TRYS(step_orthonormalize(h, n, m, (zd*)Y, ldy, nl, (const zd*)YL, ldyl, b.G, b.Cm, b.dsc, b.info, b.gw));
     int hinfo[3];
     TRY(hipMemcpyAsync(hinfo, b.info, sizeof(hinfo), hipMemcpyDeviceToHost, h->stream));
     TRY(hipStreamSynchronize(h->stream));
@@ -563,7 +574,7 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_handle h, int n, const void* H, int ldh, 
     TRYS(prepare(h, b, n, m, 1, false, CHFSI_FP64));
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, h->stream));
     TRYS(step_rayleigh_ritz(h, n, (const zd*)H, ldh, m, (zd*)Y, ldy, b.HY, b.T, b.G, b.theta, b.E, b.r, b.info,
-                            b.splitws, b.splitws_bytes, nullptr));
+                            b.gw, nullptr));
     int info = 0;
     TRY(hipMemcpyAsync(theta, b.theta, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
     TRY(hipMemcpyAsync(resid, b.r, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
@@ -590,9 +601,13 @@ chfsi_status chfsi_zgemm(chfsi_handle h, char transa, char transb, int m, int n,
         if (h->ws.cap < h->ws.off) return CHFSI_ERR_ALLOC;
     }
     h->ws.begin(false);
-    void* ws = h->ws.get(need);
+    GemmWs gw;
+    gw.ws = h->ws.get(need);
+    gw.bytes = need;
+    gw.cnt = h->tile_cnt;
+    gw.ncnt = h->tile_cnt_len;
     TRY(launch_zgemm(h->stream, transa == 'N' ? OP_N : OP_C, transb == 'N' ? OP_N : OP_C, m, n, k, alpha,
-                     (const zd*)A, lda, (const zd*)B, ldb, beta, (zd*)C, ldc, ws, need));
+                     (const zd*)A, lda, (const zd*)B, ldb, beta, (zd*)C, ldc, gw));
     TRY(hipStreamSynchronize(h->stream));
     return CHFSI_SUCCESS;
 }

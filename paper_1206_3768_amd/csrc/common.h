@@ -27,6 +27,15 @@ __host__ __device__ inline double zabs2(zd a) { return a.x * a.x + a.y * a.y; }
 enum { OP_N = 0, OP_C = 1 };
 enum { PREC_F64 = 0, PREC_F32 = 1 };
 
+// Scratch of the GEMM launches: split-K partials plus one arrival counter per output tile.  The
+// counters must be zero before a launch; each launch leaves them zero again.
+struct GemmWs {
+    void* ws = nullptr;
+    size_t bytes = 0;
+    int* cnt = nullptr;
+    int ncnt = 0;
+};
+
 struct FilterStep {
     // out = alpha * (H Yk - shift Yk) + beta * Yprev, columns [0, ncols)
     double alpha, beta, shift;
@@ -34,15 +43,13 @@ struct FilterStep {
 
 // FP64 complex GEMM on MFMA.  Returns hipError_t as int.
 int launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, double alpha, const zd* A, int lda,
-                 const zd* B, int ldb, double beta, zd* C, int ldc, void* ws, size_t ws_bytes);
+                 const zd* B, int ldb, double beta, zd* C, int ldc, const GemmWs& gw);
 // One filter step, FP64: Yout = alpha (H Yk - shift Yk) + beta Yprev (Yout may alias Yprev).
 int launch_filter_step_f64(hipStream_t s, int n, int ncols, const zd* H, int ldh, const zd* Yk, int ldyk,
-                           const zd* Yprev, int ldyp, zd* Yout, int ldyo, FilterStep fs, void* ws,
-                           size_t ws_bytes);
+                           const zd* Yprev, int ldyp, zd* Yout, int ldyo, FilterStep fs, const GemmWs& gw);
 // One filter step, FP32 complex (complex64 storage, FP32 MFMA and accumulation).
 int launch_filter_step_f32(hipStream_t s, int n, int ncols, const zf* H, int ldh, const zf* Yk, int ldyk,
-                           const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs, void* ws,
-                           size_t ws_bytes);
+                           const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs, const GemmWs& gw);
 size_t zgemm_ws_bytes(int M, int N, int K, int elem_bytes);
 
 // ---- BF16-split filter (gemm_bf16.hip) ---------------------------------------------------------
@@ -51,7 +58,7 @@ size_t zgemm_ws_bytes(int M, int N, int K, int elem_bytes);
 int launch_split_h_bf16(hipStream_t s, int n, const zd* H, int ldh, uint16_t* planes, int ldp, int nterms);
 int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hplanes, int ldp, int nterms,
                             const zf* Yk, int ldyk, const zf* Yprev, int ldyp, zf* Yout, int ldyo,
-                            FilterStep fs, uint16_t* ysplit, void* ws, size_t ws_bytes);
+                            FilterStep fs, uint16_t* ysplit, const GemmWs& gw);
 size_t bf16_ysplit_bytes(int n, int ncols, int nterms);
 size_t bf16_hplanes_elems(int n, int nterms);
 

@@ -35,6 +35,17 @@ struct PhaseTimer {
     void collect(double* out);
 };
 
+// hipEvent pair around every filter-step launch; summed after the solve's final synchronisation
+struct KernelTimer {
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    bool enabled = true;
+    ~KernelTimer();
+    void begin(hipStream_t s);
+    void end(hipStream_t s);
+    double collect(int* launches);   // total ms of the recorded launches; resets
+};
+
 struct chfsi_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -43,6 +54,11 @@ struct chfsi_handle_s {
     PhaseTimer timer;
     std::vector<double> trace;
     float* model = nullptr;        // device: MLP parameters followed by 10 normalisation constants
+    int* tile_cnt = nullptr;       // device: split-K arrival counters, zero between launches
+    int tile_cnt_len = 0;
+    KernelTimer ktimer;            // per-launch events around filter steps
+    double last_kernel_ms = 0;     // filter-step launch time of the last solve / filter call
+    int last_kernel_launches = 0;
     bool has_model = false;
 };
 
@@ -52,23 +68,20 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
                           zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
                           double& beta_k, int& k_used);
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
-                                 zd* G, zd* Cm, double* dsc, int* info_dev, void* ws, size_t wsb);
+                                 zd* G, zd* Cm, double* dsc, int* info_dev, const GemmWs& gw);
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY, zd* T,
-                                zd* G, double* theta_dev, double* E, double* r_dev, int* info_dev, void* ws,
-                                size_t wsb, PhaseTimer* tm);
+                                zd* G, double* theta_dev, double* E, double* r_dev, int* info_dev, const GemmWs& gw, PhaseTimer* tm);
 void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps);
 chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
-                        size_t wsb, double& flops, long long& matvecs);
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);
 chfsi_status filter_f32(chfsi_handle h, int n, const zf* Hf, int ldh, int ma, zf* Yf, int ldy, zf* Tf,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
-                        size_t wsb, double& flops, long long& matvecs);
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);
 void host_tridiag_eig(int k, const double* al, const double* be, std::vector<double>& theta,
                       std::vector<double>& z1sq);
 
 chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int nterms, int ma, zf* Yf, int ldy,
                          zf* Tf, uint16_t* ysplit, const std::vector<int>& deg, double a, double b, double mu1,
-                         int* flag_dev, void* ws, size_t wsb, double& flops, long long& matvecs);
+                         int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);
 // degree network (mlp.hip)
 chfsi_status learned_degrees(chfsi_handle h, int ma, const double* theta_dev, const double* r_dev, double a,
                              double b, double mu1, double thr, const std::vector<int>& dprev, float* feat,

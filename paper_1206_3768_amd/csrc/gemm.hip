@@ -12,8 +12,8 @@
 // 16 complex elements with double buffering (one barrier per stage) and register prefetch of the
 // next stage's global loads.  Tiles are enumerated so that consecutive tiles (same rows of A,
 // neighbouring column tiles) land on the same XCD: the hardware hands workgroup w to XCD w % 8.
-// Split-K writes partial tiles to a workspace that a second kernel sums in a fixed order
-// (deterministic), applying the epilogue there.
+// Split-K writes partial tiles to a workspace; the last K-slice to finish a tile sums the partials
+// in slice order (deterministic) and applies the epilogue, so one launch is one filter step.
 #include "common.h"
 
 namespace {
@@ -25,7 +25,7 @@ template <> struct CT<float> { typedef float2 c; typedef f4 acc; };
 __device__ inline d4 mfma16(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4 mfma16(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-enum { EPI_GEMM = 0, EPI_FILTER = 1, EPI_PARTIAL = 2 };
+enum { EPI_GEMM = 0, EPI_FILTER = 1 };
 
 template <typename T>
 struct GArgs {
@@ -38,6 +38,7 @@ struct GArgs {
     const C2* Yk; int ldyk;
     const C2* Yp; int ldyp;
     C2* P;                 // split-K partials: ksplit blocks of M x N (leading dimension M)
+    int* cnt;              // split-K arrival counter per output tile (zero before and after)
     int kchunk, tiles_m, tiles_n, ksplit;
 };
 
@@ -62,10 +63,8 @@ template <typename T, int EPI>
 __device__ inline void epilogue_store(const GArgs<T>& g, int i, int j, int ks, T vr, T vi)
 {
     typedef typename CT<T>::c C2;
-    if (EPI == EPI_PARTIAL) {
-        C2 o; o.x = vr; o.y = vi;
-        g.P[(size_t)ks * g.M * g.N + (size_t)i + (size_t)j * g.M] = o;
-    } else if (EPI == EPI_GEMM) {
+    (void)ks;
+    if (EPI == EPI_GEMM) {
         const T al = (T)g.alpha, be = (T)g.beta;
         C2 o;
         o.x = al * vr; o.y = al * vi;
@@ -85,7 +84,10 @@ __device__ inline void epilogue_store(const GArgs<T>& g, int i, int j, int ks, T
     }
 }
 
-template <typename T, int OPA, int OPB, int EPI, int BM, int BN>
+// SPLIT: this launch is one of ksplit K-slices of each output tile.  Every slice writes its partial
+// tile; the last slice to arrive (per-tile counter) sums the ksplit partials in slice order and
+// applies the epilogue, then clears the counter.  The sum order does not depend on arrival order.
+template <typename T, int OPA, int OPB, int EPI, int BM, int BN, bool SPLIT>
 __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
 {
     typedef typename CT<T>::c C2;
@@ -203,6 +205,21 @@ __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
         }
     }
 
+    if (!SPLIT) {
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NJ; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wr + bi * 16 + (lane & 15);
+                    const int j = j0 + wc + bj * 16 + drow(T(0), lane, r);
+                    if (i < g.M && j < g.N) epilogue_store<T, EPI>(g, i, j, ks, accr[bi][bj][r], acci[bi][bj][r]);
+                }
+        return;
+    }
+    // split-K: publish this slice's partial tile
+    const size_t slab = (size_t)g.M * g.N;
 #pragma unroll
     for (int bi = 0; bi < MI; ++bi)
 #pragma unroll
@@ -211,30 +228,49 @@ __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr + bi * 16 + (lane & 15);
                 const int j = j0 + wc + bj * 16 + drow(T(0), lane, r);
-                if (i < g.M && j < g.N) epilogue_store<T, EPI>(g, i, j, ks, accr[bi][bj][r], acci[bi][bj][r]);
+                if (i < g.M && j < g.N) {
+                    C2 o;
+                    o.x = accr[bi][bj][r];
+                    o.y = acci[bi][bj][r];
+                    g.P[(size_t)ks * slab + (size_t)i + (size_t)j * g.M] = o;
+                }
             }
-}
-
-// sums the split-K partials in a fixed order and applies the epilogue
-template <typename T, int EPI>
-__global__ __launch_bounds__(256) void k_splitk_reduce(GArgs<T> g)
-{
-    const size_t total = (size_t)g.M * g.N;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % g.M), j = (int)(e / g.M);
-        T vr = 0, vi = 0;
-        for (int s = 0; s < g.ksplit; ++s) {
-            typename CT<T>::c p = g.P[(size_t)s * total + e];
-            vr += p.x; vi += p.y;
-        }
-        epilogue_store<T, EPI>(g, i, j, 0, vr, vi);
+    __threadfence();
+    __shared__ int s_last;
+    __syncthreads();
+    if (tid == 0) {
+        const int old = atomicAdd(&g.cnt[it * g.tiles_n + jt], 1);
+        s_last = (old == g.ksplit - 1);
     }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+#pragma unroll
+    for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NJ; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr + bi * 16 + (lane & 15);
+                const int j = j0 + wc + bj * 16 + drow(T(0), lane, r);
+                if (i < g.M && j < g.N) {
+                    T vr = 0, vi = 0;
+                    for (int s = 0; s < g.ksplit; ++s) {
+                        const C2 p = g.P[(size_t)s * slab + (size_t)i + (size_t)j * g.M];
+                        vr += p.x;
+                        vi += p.y;
+                    }
+                    epilogue_store<T, EPI>(g, i, j, 0, vr, vi);
+                }
+            }
+    if (tid == 0) g.cnt[it * g.tiles_n + jt] = 0;
 }
 
 struct Plan { int bm, bn, ksplit, kchunk, tiles_m, tiles_n; };
 
-// Tile/split choice: enough workgroups for two per CU on 256 CUs, K chunks of >= 256.
-Plan make_plan(int M, int N, int K, size_t ws_bytes, int elem_bytes)
+// Tile/split choice: enough workgroups for two per CU on 256 CUs, K slices of at least 256, and
+// the split limited by the partial buffer and the counter array.
+Plan make_plan(int M, int N, int K, const GemmWs& gw, int elem_bytes)
 {
     Plan p;
     p.bm = 64;
@@ -244,8 +280,8 @@ Plan make_plan(int M, int N, int K, size_t ws_bytes, int elem_bytes)
     const long tiles = (long)p.tiles_m * p.tiles_n;
     int ks = 1;
     while (tiles * ks < 512 && (long)K / (2 * ks) >= 256) ks *= 2;
-    while (ks > 1 && (size_t)ks * M * N * (size_t)elem_bytes > ws_bytes) ks /= 2;
-    p.ksplit = ks;
+    if (!gw.ws || !gw.cnt || tiles > gw.ncnt) ks = 1;
+    while (ks > 1 && (size_t)ks * M * N * (size_t)elem_bytes > gw.bytes) ks /= 2;
     int kc = (K + ks - 1) / ks;
     kc = (kc + 15) / 16 * 16;
     p.kchunk = kc > 0 ? kc : 16;
@@ -259,16 +295,11 @@ int run(hipStream_t s, GArgs<T> g, const Plan& p)
     g.kchunk = p.kchunk; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.ksplit = p.ksplit;
     const int nt = p.tiles_m * p.tiles_n * p.ksplit;
     if (nt <= 0) return 0;
-    const bool split = p.ksplit > 1;
-#define LAUNCH(E, BM_, BN_) hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, E, BM_, BN_>), dim3(nt), dim3(256), 0, s, g)
-    if (split) {
-        if (p.bn == 32) LAUNCH(EPI_PARTIAL, 64, 32); else LAUNCH(EPI_PARTIAL, 64, 64);
-        const size_t total = (size_t)g.M * g.N;
-        int blocks = (int)((total + 255) / 256);
-        if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL((k_splitk_reduce<T, EPI>), dim3(blocks), dim3(256), 0, s, g);
+#define LAUNCH(BN_, SP) hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, 64, BN_, SP>), dim3(nt), dim3(256), 0, s, g)
+    if (p.ksplit > 1) {
+        if (p.bn == 32) LAUNCH(32, true); else LAUNCH(64, true);
     } else {
-        if (p.bn == 32) LAUNCH(EPI, 64, 32); else LAUNCH(EPI, 64, 64);
+        if (p.bn == 32) LAUNCH(32, false); else LAUNCH(64, false);
     }
 #undef LAUNCH
     return (int)hipGetLastError();
@@ -278,18 +309,23 @@ int run(hipStream_t s, GArgs<T> g, const Plan& p)
 
 size_t zgemm_ws_bytes(int M, int N, int K, int elem_bytes)
 {
-    Plan p = make_plan(M, N, K, (size_t)-1, elem_bytes);
+    GemmWs probe;
+    probe.ws = (void*)1;
+    probe.bytes = (size_t)-1;
+    probe.cnt = (int*)1;
+    probe.ncnt = 1 << 30;
+    Plan p = make_plan(M, N, K, probe, elem_bytes);
     return (size_t)p.ksplit * M * N * elem_bytes;
 }
 
 int launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, double alpha, const zd* A, int lda,
-                 const zd* B, int ldb, double beta, zd* C, int ldc, void* ws, size_t ws_bytes)
+                 const zd* B, int ldb, double beta, zd* C, int ldc, const GemmWs& gw)
 {
     if (M <= 0 || N <= 0) return 0;
     GArgs<double> g = {};
     g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
-    g.alpha = alpha; g.beta = beta; g.P = (zd*)ws;
-    Plan p = make_plan(M, N, K, ws ? ws_bytes : 0, 16);
+    g.alpha = alpha; g.beta = beta; g.P = (zd*)gw.ws; g.cnt = gw.cnt;
+    Plan p = make_plan(M, N, K, gw, 16);
     if (opa == OP_N && opb == OP_N) return run<double, OP_N, OP_N, EPI_GEMM>(s, g, p);
     if (opa == OP_C && opb == OP_N) return run<double, OP_C, OP_N, EPI_GEMM>(s, g, p);
     if (opa == OP_N && opb == OP_C) return run<double, OP_N, OP_C, EPI_GEMM>(s, g, p);
@@ -297,27 +333,25 @@ int launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, double al
 }
 
 int launch_filter_step_f64(hipStream_t s, int n, int ncols, const zd* H, int ldh, const zd* Yk, int ldyk,
-                           const zd* Yprev, int ldyp, zd* Yout, int ldyo, FilterStep fs, void* ws,
-                           size_t ws_bytes)
+                           const zd* Yprev, int ldyp, zd* Yout, int ldyo, FilterStep fs, const GemmWs& gw)
 {
     if (n <= 0 || ncols <= 0) return 0;
     GArgs<double> g = {};
     g.M = n; g.N = ncols; g.K = n; g.A = H; g.lda = ldh; g.B = Yk; g.ldb = ldyk; g.C = Yout; g.ldc = ldyo;
     g.alpha = fs.alpha; g.beta = fs.beta; g.shift = fs.shift; g.Yk = Yk; g.ldyk = ldyk; g.Yp = Yprev;
-    g.ldyp = ldyp; g.P = (zd*)ws;
-    Plan p = make_plan(n, ncols, n, ws ? ws_bytes : 0, 16);
+    g.ldyp = ldyp; g.P = (zd*)gw.ws; g.cnt = gw.cnt;
+    Plan p = make_plan(n, ncols, n, gw, 16);
     return run<double, OP_N, OP_N, EPI_FILTER>(s, g, p);
 }
 
 int launch_filter_step_f32(hipStream_t s, int n, int ncols, const zf* H, int ldh, const zf* Yk, int ldyk,
-                           const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs, void* ws,
-                           size_t ws_bytes)
+                           const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs, const GemmWs& gw)
 {
     if (n <= 0 || ncols <= 0) return 0;
     GArgs<float> g = {};
     g.M = n; g.N = ncols; g.K = n; g.A = H; g.lda = ldh; g.B = Yk; g.ldb = ldyk; g.C = Yout; g.ldc = ldyo;
     g.alpha = fs.alpha; g.beta = fs.beta; g.shift = fs.shift; g.Yk = Yk; g.ldyk = ldyk; g.Yp = Yprev;
-    g.ldyp = ldyp; g.P = (zf*)ws;
-    Plan p = make_plan(n, ncols, n, ws ? ws_bytes : 0, 8);
+    g.ldyp = ldyp; g.P = (zf*)gw.ws; g.cnt = gw.cnt;
+    Plan p = make_plan(n, ncols, n, gw, 8);
     return run<float, OP_N, OP_N, EPI_FILTER>(s, g, p);
 }

@@ -122,10 +122,11 @@ struct BArgs {
     zf* Yo; int ldyo;
     float alpha, beta, shift;
     zf* P;                  // split-K partials [ksplit][ncols][n]
+    int* cnt;               // split-K arrival counter per output tile (zero before and after)
     int kchunk, tiles_m, tiles_n, ksplit;
 };
 
-template <int NT, bool PARTIAL>
+template <int NT, bool SPLIT>
 __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
 {
     constexpr int BM = 64, BN = 64, BK = 32;
@@ -222,6 +223,28 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
         }
     }
 
+    const size_t slab = (size_t)g.n * g.ncols;
+    if (SPLIT) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wr + bi * 16 + (lane & 15);
+                    const int j = j0 + wc + bj * 16 + (lane >> 4) * 4 + r;
+                    if (i < g.n && j < g.ncols)
+                        g.P[(size_t)ks * slab + (size_t)i + (size_t)j * g.n] =
+                            make_float2(accr[bi][bj][r], acci[bi][bj][r]);
+                }
+        __threadfence();
+        __shared__ int s_last;
+        __syncthreads();
+        if (tid == 0) s_last = (atomicAdd(&g.cnt[it * g.tiles_n + jt], 1) == g.ksplit - 1);
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+    }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -231,35 +254,22 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
                 const int i = i0 + wr + bi * 16 + (lane & 15);
                 const int j = j0 + wc + bj * 16 + (lane >> 4) * 4 + r;
                 if (i >= g.n || j >= g.ncols) continue;
-                const float vr = accr[bi][bj][r], vi = acci[bi][bj][r];
-                if (PARTIAL) {
-                    g.P[(size_t)ks * g.n * g.ncols + (size_t)i + (size_t)j * g.n] = make_float2(vr, vi);
-                } else {
-                    const zf yk = g.Yk[(size_t)i + (size_t)j * g.ldyk];
-                    const zf yp = g.Yp[(size_t)i + (size_t)j * g.ldyp];
-                    g.Yo[(size_t)i + (size_t)j * g.ldyo] =
-                        make_float2(g.alpha * (vr - g.shift * yk.x) + g.beta * yp.x,
-                                    g.alpha * (vi - g.shift * yk.y) + g.beta * yp.y);
+                float vr = accr[bi][bj][r], vi = acci[bi][bj][r];
+                if (SPLIT) {
+                    vr = 0.f;
+                    vi = 0.f;
+                    for (int s2 = 0; s2 < g.ksplit; ++s2) {
+                        const zf p = g.P[(size_t)s2 * slab + (size_t)i + (size_t)j * g.n];
+                        vr += p.x;
+                        vi += p.y;
+                    }
                 }
+                const zf yk = g.Yk[(size_t)i + (size_t)j * g.ldyk];
+                const zf yp = g.Yp[(size_t)i + (size_t)j * g.ldyp];
+                g.Yo[(size_t)i + (size_t)j * g.ldyo] = make_float2(g.alpha * (vr - g.shift * yk.x) + g.beta * yp.x,
+                                                                 g.alpha * (vi - g.shift * yk.y) + g.beta * yp.y);
             }
-}
-
-__global__ void k_bf16_reduce(BArgs g)
-{
-    const size_t total = (size_t)g.n * g.ncols;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % g.n), j = (int)(e / g.n);
-        float vr = 0.f, vi = 0.f;
-        for (int s = 0; s < g.ksplit; ++s) {
-            const zf p = g.P[(size_t)s * total + e];
-            vr += p.x;
-            vi += p.y;
-        }
-        const zf yk = g.Yk[(size_t)i + (size_t)j * g.ldyk];
-        const zf yp = g.Yp[(size_t)i + (size_t)j * g.ldyp];
-        g.Yo[(size_t)i + (size_t)j * g.ldyo] = make_float2(g.alpha * (vr - g.shift * yk.x) + g.beta * yp.x,
-                                                         g.alpha * (vi - g.shift * yk.y) + g.beta * yp.y);
-    }
+    if (SPLIT && tid == 0) g.cnt[it * g.tiles_n + jt] = 0;
 }
 
 inline int grid_for(size_t total)
@@ -291,7 +301,7 @@ int launch_split_h_bf16(hipStream_t s, int n, const zd* H, int ldh, uint16_t* pl
 
 int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hplanes, int /*ldp*/, int nterms,
                             const zf* Yk, int ldyk, const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs,
-                            uint16_t* ysplit, void* ws, size_t ws_bytes)
+                            uint16_t* ysplit, const GemmWs& gw)
 {
     if (n <= 0 || ncols <= 0) return 0;
     if (nterms != 2 && nterms != 3) return (int)hipErrorInvalidValue;
@@ -302,27 +312,28 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
     g.n = n; g.np = np; g.ncols = ncols; g.ncp = ncp; g.nterms = nterms;
     g.Hp = Hplanes; g.Ys = ysplit; g.Yk = Yk; g.ldyk = ldyk; g.Yp = Yprev; g.ldyp = ldyp; g.Yo = Yout; g.ldyo = ldyo;
     g.alpha = (float)fs.alpha; g.beta = (float)fs.beta; g.shift = (float)fs.shift;
-    g.P = (zf*)ws;
+    g.P = (zf*)gw.ws;
+    g.cnt = gw.cnt;
     g.tiles_m = (n + 63) / 64;
     g.tiles_n = (ncols + 63) / 64;
     const long tiles = (long)g.tiles_m * g.tiles_n;
     int ksp = 1;
     while (tiles * ksp < 512 && np / (2 * ksp) >= 512) ksp *= 2;
-    while (ksp > 1 && (size_t)ksp * n * ncols * sizeof(zf) > ws_bytes) ksp /= 2;
+    if (!gw.ws || !gw.cnt || tiles > gw.ncnt) ksp = 1;
+    while (ksp > 1 && (size_t)ksp * n * ncols * sizeof(zf) > gw.bytes) ksp /= 2;
     int kc = (np + ksp - 1) / ksp;
     kc = (kc + 31) / 32 * 32;
     g.kchunk = kc;
     g.ksplit = (np + kc - 1) / kc;
     const int nt = g.tiles_m * g.tiles_n * g.ksplit;
-    const bool part = g.ksplit > 1;
+    const bool split = g.ksplit > 1;
     if (nterms == 2) {
-        if (part) hipLaunchKernelGGL((k_filter_bf16<2, true>), dim3(nt), dim3(256), 0, s, g);
+        if (split) hipLaunchKernelGGL((k_filter_bf16<2, true>), dim3(nt), dim3(256), 0, s, g);
         else hipLaunchKernelGGL((k_filter_bf16<2, false>), dim3(nt), dim3(256), 0, s, g);
     } else {
-        if (part) hipLaunchKernelGGL((k_filter_bf16<3, true>), dim3(nt), dim3(256), 0, s, g);
+        if (split) hipLaunchKernelGGL((k_filter_bf16<3, true>), dim3(nt), dim3(256), 0, s, g);
         else hipLaunchKernelGGL((k_filter_bf16<3, false>), dim3(nt), dim3(256), 0, s, g);
     }
-    if (part) hipLaunchKernelGGL(k_bf16_reduce, dim3(grid_for((size_t)n * ncols)), dim3(256), 0, s, g);
     return (int)hipGetLastError();
 }
 
@@ -330,7 +341,7 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
 // non-increasing, columns finishing on odd steps copied back from T at the end).
 chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int nterms, int ma, zf* Yf, int ldy,
                          zf* Tf, uint16_t* ysplit, const std::vector<int>& deg, double a, double b, double mu1,
-                         int* flag_dev, void* ws, size_t wsb, double& flops, long long& matvecs)
+                         int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs)
 {
     hipStream_t st = h->stream;
     if (ma <= 0 || deg[0] <= 0) return CHFSI_SUCCESS;
@@ -346,8 +357,10 @@ chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int
         const int ldo = (k % 2 == 1) ? n : ldy;
         const zf* yp = (k == 1) ? yk : yo;
         const int ldp = (k == 1) ? ldk : ldo;
-        if (launch_filter_step_bf16(st, n, w, Hb, ldh, nterms, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ysplit, ws, wsb))
+        h->ktimer.begin(st);
+        if (launch_filter_step_bf16(st, n, w, Hb, ldh, nterms, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ysplit, gw))
             return CHFSI_ERR_DEVICE;
+        h->ktimer.end(st);
         flops += 8.0 * (double)n * (double)n * (double)w;
         matvecs += w;
     }

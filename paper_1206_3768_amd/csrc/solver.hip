@@ -79,6 +79,41 @@ void PhaseTimer::collect(double* out /* [NPHASE] ms */)
     for (int i = 0; i < NPHASE; ++i) open[i] = nullptr;
 }
 
+KernelTimer::~KernelTimer()
+{
+    for (auto& e : pool) (void)hipEventDestroy(e);
+}
+
+void KernelTimer::begin(hipStream_t s)
+{
+    if (!enabled) return;
+    while (pool.size() < used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { enabled = false; return; }
+        pool.push_back(e);
+    }
+    (void)hipEventRecord(pool[used], s);
+}
+
+void KernelTimer::end(hipStream_t s)
+{
+    if (!enabled || pool.size() < used + 2) return;
+    (void)hipEventRecord(pool[used + 1], s);
+    used += 2;
+}
+
+double KernelTimer::collect(int* launches)
+{
+    double t = 0;
+    for (size_t i = 0; i + 1 < used; i += 2) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, pool[i], pool[i + 1]) == hipSuccess) t += ms;
+    }
+    if (launches) *launches = (int)(used / 2);
+    used = 0;
+    return t;
+}
+
 const char* chfsi_status_string(chfsi_status s)
 {
     switch (s) {
@@ -125,6 +160,19 @@ chfsi_status chfsi_create(chfsi_handle* out, int device, void* hip_stream)
     if (rocblas_create_handle(&h->rb) != rocblas_status_success) { delete h; return CHFSI_ERR_DEVICE; }
     rocblas_set_stream(h->rb, h->stream);
     rocblas_set_pointer_mode(h->rb, rocblas_pointer_mode_host);
+    h->tile_cnt_len = 1 << 18;
+    if (hipMalloc((void**)&h->tile_cnt, sizeof(int) * h->tile_cnt_len) != hipSuccess) {
+        rocblas_destroy_handle(h->rb);
+        delete h;
+        return CHFSI_ERR_ALLOC;
+    }
+    if (hipMemsetAsync(h->tile_cnt, 0, sizeof(int) * h->tile_cnt_len, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        (void)hipFree(h->tile_cnt);
+        rocblas_destroy_handle(h->rb);
+        delete h;
+        return CHFSI_ERR_DEVICE;
+    }
     *out = h;
     return CHFSI_SUCCESS;
 }
@@ -136,6 +184,7 @@ chfsi_status chfsi_destroy(chfsi_handle h)
     (void)hipStreamSynchronize(h->stream);
     if (h->ws.base) (void)hipFree(h->ws.base);
     if (h->model) (void)hipFree(h->model);
+    if (h->tile_cnt) (void)hipFree(h->tile_cnt);
     if (h->rb) rocblas_destroy_handle(h->rb);
     delete h;
     return CHFSI_SUCCESS;
@@ -280,14 +329,14 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
 // column normalisation; Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SISC 2020).  R's
 // diagonal is real positive in every pass, so Q is the Q factor of Y.
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
-                                 zd* G, zd* Cm, double* dsc, int* info_dev, void* ws, size_t wsb)
+                                 zd* G, zd* Cm, double* dsc, int* info_dev, const GemmWs& gw)
 {
     hipStream_t st = h->stream;
     if (ma <= 0) return CHFSI_SUCCESS;
     if (nl > 0)
         for (int pass = 0; pass < 2; ++pass) {
-            TRY(launch_zgemm(st, OP_C, OP_N, nl, ma, n, 1.0, YL, ldyl, Y, ldy, 0.0, Cm, nl, ws, wsb));
-            TRY(launch_zgemm(st, OP_N, OP_N, n, ma, nl, -1.0, YL, ldyl, Cm, nl, 1.0, Y, ldy, ws, wsb));
+            TRY(launch_zgemm(st, OP_C, OP_N, nl, ma, n, 1.0, YL, ldyl, Y, ldy, 0.0, Cm, nl, gw));
+            TRY(launch_zgemm(st, OP_N, OP_N, n, ma, nl, -1.0, YL, ldyl, Cm, nl, 1.0, Y, ldy, gw));
         }
     TRY(launch_colnorms(st, n, ma, Y, ldy, dsc));
     TRY(launch_scale_cols_inv(st, n, ma, Y, ldy, dsc));
@@ -295,7 +344,7 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
     const double shift = 11.0 * ((double)n * ma + (double)ma * (ma + 1)) * u * (double)ma;
     const rocblas_double_complex one(1.0, 0.0);
     for (int pass = 0; pass < 3; ++pass) {
-        TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, Y, ldy, 0.0, G, ma, ws, wsb));
+        TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, Y, ldy, 0.0, G, ma, gw));
         if (pass == 0) TRY(launch_add_diag_const(st, ma, G, ma, shift));
         TRYRB(rocsolver_zpotrf(h->rb, rocblas_fill_upper, ma, rbz(G), ma, info_dev + pass));
         TRYRB(rocblas_ztrsm(h->rb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
@@ -308,17 +357,17 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
 // phase-normalised W), Y <- Y W, HY <- HY W, then r_j = ||HY_j - theta_j Y_j||.
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY,
                                 zd* T, zd* G, double* theta_dev, double* E, double* r_dev, int* info_dev,
-                                void* ws, size_t wsb, PhaseTimer* tm)
+                                const GemmWs& gw, PhaseTimer* tm)
 {
     hipStream_t st = h->stream;
-    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, n, 1.0, H, ldh, Y, ldy, 0.0, HY, n, ws, wsb));
-    TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, HY, n, 0.0, G, ma, ws, wsb));
+    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, n, 1.0, H, ldh, Y, ldy, 0.0, HY, n, gw));
+    TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, HY, n, 0.0, G, ma, gw));
     TRYRB(rocsolver_zheevd(h->rb, rocblas_evect_original, rocblas_fill_lower, ma, rbz(G), ma, theta_dev, E,
                            info_dev));
     TRY(launch_phase_normalize(st, ma, ma, G, ma));
-    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, 1.0, Y, ldy, G, ma, 0.0, T, n, ws, wsb));
+    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, 1.0, Y, ldy, G, ma, 0.0, T, n, gw));
     TRY(launch_zlacpy(st, n, ma, T, n, Y, ldy));
-    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, 1.0, HY, n, G, ma, 0.0, T, n, ws, wsb));
+    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, 1.0, HY, n, G, ma, 0.0, T, n, gw));
     TRY(launch_zlacpy(st, n, ma, T, n, HY, n));
     if (tm) tm->mark(PH_RESID, st, true);
     TRY(launch_residual_norms(st, n, ma, HY, n, Y, ldy, theta_dev, r_dev));
@@ -360,9 +409,9 @@ void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<F
 template <typename C2, typename HT>
 chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma, C2* Y, int ldy, C2* T, int ldt,
                            const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev,
-                           void* ws, size_t wsb, double& flops, long long& matvecs,
+                           const GemmWs& gw, double& flops, long long& matvecs,
                            int (*step_fn)(hipStream_t, int, int, const HT*, int, const C2*, int, const C2*, int,
-                                          C2*, int, FilterStep, void*, size_t),
+                                          C2*, int, FilterStep, const GemmWs&),
                            int (*copy_fn)(hipStream_t, int, int, const C2*, int, C2*, int, const int*))
 {
     hipStream_t st = h->stream;
@@ -381,7 +430,9 @@ chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma,
         const int ldo = (k % 2 == 1) ? ldt : ldy;
         const C2* yp = (k == 1) ? yk : yo;          // beta == 0 on step 1: any finite input
         const int ldp = (k == 1) ? ldk : ldo;
-        TRY(step_fn(st, n, w, Hm, ldh, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ws, wsb));
+        h->ktimer.begin(st);
+        TRY(step_fn(st, n, w, Hm, ldh, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], gw));
+        h->ktimer.end(st);
         flops += 8.0 * (double)n * (double)n * (double)w;
         matvecs += w;
     }
@@ -399,28 +450,26 @@ chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma,
 }
 
 static int step_f64(hipStream_t s, int n, int w, const zd* H, int ldh, const zd* yk, int ldk, const zd* yp, int ldp,
-                    zd* yo, int ldo, FilterStep fs, void* ws, size_t wsb)
+                    zd* yo, int ldo, FilterStep fs, const GemmWs& gw)
 {
-    return launch_filter_step_f64(s, n, w, H, ldh, yk, ldk, yp, ldp, yo, ldo, fs, ws, wsb);
+    return launch_filter_step_f64(s, n, w, H, ldh, yk, ldk, yp, ldp, yo, ldo, fs, gw);
 }
 static int step_f32(hipStream_t s, int n, int w, const zf* H, int ldh, const zf* yk, int ldk, const zf* yp, int ldp,
-                    zf* yo, int ldo, FilterStep fs, void* ws, size_t wsb)
+                    zf* yo, int ldo, FilterStep fs, const GemmWs& gw)
 {
-    return launch_filter_step_f32(s, n, w, H, ldh, yk, ldk, yp, ldp, yo, ldo, fs, ws, wsb);
+    return launch_filter_step_f32(s, n, w, H, ldh, yk, ldk, yp, ldp, yo, ldo, fs, gw);
 }
 
 chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
-                        size_t wsb, double& flops, long long& matvecs)
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs)
 {
-    return filter_sorted<zd, zd>(h, n, H, ldh, ma, Y, ldy, T, n, deg, a, b, mu1, flag_dev, ws, wsb, flops, matvecs,
+    return filter_sorted<zd, zd>(h, n, H, ldh, ma, Y, ldy, T, n, deg, a, b, mu1, flag_dev, gw, flops, matvecs,
                                  step_f64, launch_copy_cols_flag);
 }
 
 chfsi_status filter_f32(chfsi_handle h, int n, const zf* Hf, int ldh, int ma, zf* Yf, int ldy, zf* Tf,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, void* ws,
-                        size_t wsb, double& flops, long long& matvecs)
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs)
 {
-    return filter_sorted<zf, zf>(h, n, Hf, ldh, ma, Yf, ldy, Tf, n, deg, a, b, mu1, flag_dev, ws, wsb, flops,
+    return filter_sorted<zf, zf>(h, n, Hf, ldh, ma, Yf, ldy, Tf, n, deg, a, b, mu1, flag_dev, gw, flops,
                                  matvecs, step_f32, launch_copy_cols_flag_c);
 }
