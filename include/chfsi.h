@@ -86,8 +86,9 @@ typedef struct {
     double norm_a;                /* largest column 2-norm of A (lower bound of ||A||_2)        */
     int lanczos_steps;            /* Lanczos steps taken                                        */
     int precision_switches;       /* vectors moved from low precision to FP64                   */
-    int filter_launches;          /* filter-step kernel launches                                */
-    double t_filter_kernels;      /* ms: sum of hipEvent-timed filter-step launches             */
+    int filter_launches;          /* filter steps                                               */
+    double t_filter_kernels;      /* ms: hipEvent-timed main filter kernel launches (summed)    */
+    double t_filter_steps;        /* ms: the same launches plus their split-K reduce kernels    */
     int status;                   /* chfsi_status of this solve                                 */
 } chfsi_stats;
 
@@ -144,8 +145,29 @@ chfsi_status chfsi_filter(chfsi_handle h, int n, const void* H, int ldh, void* Y
 
 /* Event timing of the filter-step launches of the last chfsi_solve / chfsi_filter on this handle:
  * *total_ms = sum over launches of the time between hipEvents recorded on the handle's stream just
- * before and just after each launch, *launches = their number (host pointers). */
+ * before and just after each main filter kernel (split-K reduce kernels excluded), *launches =
+ * their number (host pointers). */
 chfsi_status chfsi_filter_kernel_time(chfsi_handle h, double* total_ms, int* launches);
+
+/* Per-launch log of the filter steps of the last chfsi_solve / chfsi_filter: row r is
+ * rows[9 r .. 9 r + 8] = n, block width, precision, bm, bn, ksplit, split mode (0 none, 1 reduce
+ * kernel, 2 fused), main kernel ms, ms including the reduce kernel.  cap = rows the host buffer
+ * holds; *count = rows available (rows == NULL: only *count is set). */
+chfsi_status chfsi_filter_launch_log(chfsi_handle h, double* rows, int cap, int* count);
+
+/* Tile plan of the filter-step kernel: a bm x bn complex output tile per workgroup (32 or 64
+ * each) and the K dimension cut into ksplit slices (1 = none) whose partial tiles are summed in
+ * slice order either by a second kernel (fused = 0) or by the last slice to finish (fused = 1). */
+typedef struct { int bm, bn, ksplit, fused; } chfsi_tile_plan;
+
+/* Project autotuner of the filter-step kernel: times every candidate plan for the n x m filter
+ * step in precision prec (CHFSI_FP64 or CHFSI_FP32) on scratch buffers with hipEvents, stores the
+ * fastest in the handle's plan table (used by every later filter step of that precision and n
+ * whose width is at most m and above the next smaller tuned width) and returns it with its time
+ * per step in ms (both outputs nullable).  Allocates and frees its own scratch. */
+chfsi_status chfsi_autotune_filter(chfsi_handle h, int n, int m, int prec, chfsi_tile_plan* best, double* best_ms);
+/* Sets (plan != NULL) or removes (plan == NULL) the table entry for (n, m, prec) by hand. */
+chfsi_status chfsi_set_filter_plan(chfsi_handle h, int n, int m, int prec, const chfsi_tile_plan* plan);
 
 /* Step-level entry points (the pieces chfsi_solve is made of), for parity tests.
  *  chfsi_reduce:  L L^H = S, H = L^{-1} A L^{-H} (Hermitized).  H, L: n x n device outputs

@@ -51,7 +51,14 @@ class Stats(C.Structure):
                 ("t_back", C.c_double), ("t_total", C.c_double), ("mu1", C.c_double), ("a", C.c_double),
                 ("b", C.c_double), ("norm_a", C.c_double), ("lanczos_steps", C.c_int),
                 ("precision_switches", C.c_int), ("filter_launches", C.c_int), ("t_filter_kernels", C.c_double),
-                ("status", C.c_int)]
+                ("t_filter_steps", C.c_double), ("status", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TilePlan(C.Structure):
+    _fields_ = [("bm", C.c_int), ("bn", C.c_int), ("ksplit", C.c_int), ("fused", C.c_int)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -67,7 +74,8 @@ EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solv
             "chfsi_filter", "chfsi_reduce", "chfsi_lanczos", "chfsi_orthonormalize", "chfsi_rayleigh_ritz",
             "chfsi_zgemm", "chfsi_random_block", "chfsi_set_degree_model", "chfsi_get_trace", "chfsi_mlp_forward",
             "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string",
-            "chfsi_filter_kernel_time"]
+            "chfsi_filter_kernel_time", "chfsi_autotune_filter", "chfsi_set_filter_plan",
+            "chfsi_filter_launch_log"]
 
 
 def load():
@@ -99,6 +107,9 @@ def load():
     lib.chfsi_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i, C.c_float, C.c_float, C.c_float, C.c_float]
     lib.chfsi_mlp_train.argtypes = [vp, vp, i, vp, vp, C.c_float, C.c_float, i, i, C.c_float, u, vp]
     lib.chfsi_filter_kernel_time.argtypes = [vp, vp, vp]
+    lib.chfsi_filter_launch_log.argtypes = [vp, vp, i, vp]
+    lib.chfsi_autotune_filter.argtypes = [vp, i, i, i, C.POINTER(TilePlan), vp]
+    lib.chfsi_set_filter_plan.argtypes = [vp, i, i, i, C.POINTER(TilePlan)]
     lib.chfsi_status_string.argtypes = [i]
     lib.chfsi_status_string.restype = C.c_char_p
     _lib = lib
@@ -230,6 +241,31 @@ class Handle:
         t = np.zeros(1); c = np.zeros(1, dtype=np.int32)
         self._check(self.lib.chfsi_filter_kernel_time(self.h, t.ctypes.data, c.ctypes.data), "chfsi_filter_kernel_time")
         return float(t[0]), int(c[0])
+
+    def filter_launch_log(self) -> np.ndarray:
+        """Rows (n, width, prec, bm, bn, ksplit, mode, main_ms, step_ms) of the last solve/filter."""
+        cnt = np.zeros(1, dtype=np.int32)
+        self._check(self.lib.chfsi_filter_launch_log(self.h, None, 0, cnt.ctypes.data), "chfsi_filter_launch_log")
+        rows = np.zeros((int(cnt[0]), 9))
+        if len(rows):
+            self._check(self.lib.chfsi_filter_launch_log(self.h, rows.ctypes.data, len(rows), cnt.ctypes.data),
+                        "chfsi_filter_launch_log")
+        return rows
+
+    def autotune_filter(self, n: int, m: int, prec: int = FP64):
+        """Times every tile plan of the n x m filter step; returns (plan dict, ms per step)."""
+        p = TilePlan()
+        ms = np.zeros(1)
+        self._check(self.lib.chfsi_autotune_filter(self.h, n, m, prec, C.byref(p), ms.ctypes.data),
+                    "chfsi_autotune_filter")
+        return p.as_dict(), float(ms[0])
+
+    def set_filter_plan(self, n: int, m: int, prec: int, plan: Optional[dict]):
+        if plan is None:
+            self._check(self.lib.chfsi_set_filter_plan(self.h, n, m, prec, None), "chfsi_set_filter_plan")
+            return
+        p = TilePlan(plan["bm"], plan["bn"], plan["ksplit"], plan.get("fused", 0))
+        self._check(self.lib.chfsi_set_filter_plan(self.h, n, m, prec, C.byref(p)), "chfsi_set_filter_plan")
 
     def reduce(self, A, S, H, L):
         self._check(self.lib.chfsi_reduce(self.h, A.shape[-1], _ptr(A), A.shape[-1], _ptr(S), S.shape[-1],

@@ -415,7 +415,7 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
     stt.filter_flops = flops;
     stt.mu1 = mu1; stt.a = a; stt.b = bb;
     stt.precision_switches = switches;
-    stt.t_filter_kernels = h->ktimer.collect(&stt.filter_launches);
+    stt.t_filter_kernels = h->ktimer.collect(&stt.filter_launches, &stt.t_filter_steps);
     h->last_kernel_ms = stt.t_filter_kernels;
     h->last_kernel_launches = stt.filter_launches;
     stt.status = status;
@@ -509,6 +509,15 @@ chfsi_status chfsi_filter(chfsi_handle h, int n, const void* Hv, int ldh, void* 
     TRY(launch_permute_cols(st, n, m, bf.V, n, Y, ldy, bf.iperm));
     TRY(hipStreamSynchronize(st));
     h->last_kernel_ms = h->ktimer.collect(&h->last_kernel_launches);
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_filter_launch_log(chfsi_handle h, double* rows, int cap, int* count)
+{
+    if (!h || !count || cap < 0) return CHFSI_ERR_ARG;
+    const int avail = (int)(h->ktimer.log.size() / 9);
+    *count = avail;
+    if (rows) std::memcpy(rows, h->ktimer.log.data(), sizeof(double) * 9 * std::min(avail, cap));
     return CHFSI_SUCCESS;
 }
 

@@ -34,6 +34,11 @@ struct GemmWs {
     size_t bytes = 0;
     int* cnt = nullptr;
     int ncnt = 0;
+    // forced tile plan (plan_bm == 0: choose automatically): output tile plan_bm x plan_bn
+    // (32 or 64 each), K split plan_ksplit, split mode 1 (partials + reduce kernel) or 2 (fused)
+    int plan_bm = 0, plan_bn = 0, plan_ksplit = 0, plan_mode = 1;
+    hipEvent_t ev_main = nullptr;   // recorded right after the main kernel when set
+    int* plan_used = nullptr;       // when set, receives bm, bn, ksplit, mode of the launch
 };
 
 struct FilterStep {

@@ -35,16 +35,25 @@ struct PhaseTimer {
     void collect(double* out);
 };
 
-// hipEvent pair around every filter-step launch; summed after the solve's final synchronisation
+// hipEvents around every filter step: before the main kernel, right after it (recorded by the
+// launcher through GemmWs::ev_main) and after the step's reduce kernel; summed after the solve's
+// final synchronisation
 struct KernelTimer {
+    struct Rec { int n, ncols, prec; int plan[4]; };
     std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;                    // one per begin/end pair
+    std::vector<double> log;                  // rows of the last collect (see chfsi_filter_launch_log)
     size_t used = 0;
     bool enabled = true;
     ~KernelTimer();
-    void begin(hipStream_t s);
+    // records the start event and returns the event the launcher records after the main kernel;
+    // *plan_slot receives the plan of the launch
+    hipEvent_t begin(hipStream_t s, int n, int ncols, int prec, int** plan_slot);
     void end(hipStream_t s);
-    double collect(int* launches);   // total ms of the recorded launches; resets
+    double collect(int* launches, double* step_ms = nullptr);   // main-kernel ms; resets
 };
+
+struct TuneEntry { int prec, n, m; int bm, bn, ksplit, mode; };
 
 struct chfsi_handle_s {
     int device = 0;
@@ -57,6 +66,7 @@ struct chfsi_handle_s {
     int* tile_cnt = nullptr;       // device: split-K arrival counters, zero between launches
     int tile_cnt_len = 0;
     KernelTimer ktimer;            // per-launch events around filter steps
+    std::vector<TuneEntry> plans;  // autotuned filter-step plans
     double last_kernel_ms = 0;     // filter-step launch time of the last solve / filter call
     int last_kernel_launches = 0;
     bool has_model = false;
@@ -87,6 +97,9 @@ chfsi_status learned_degrees(chfsi_handle h, int ma, const double* theta_dev, co
                              double b, double mu1, double thr, const std::vector<int>& dprev, float* feat,
                              float* dpred, int* iscr, int dmin, int dmax, int* out,
                              const std::function<int(int)>& fallback);
+
+// tuned plan for a filter step (tune.hip); leaves gw unchanged when the table has no entry
+void apply_tuned_plan(chfsi_handle h, int prec, int n, int ncols, GemmWs& gw);
 
 // extra small kernels (blas1.hip)
 int launch_zero_upper(hipStream_t s, int n, zd* L, int ldl);

@@ -4,16 +4,17 @@
 // Complex products run as four real products on v_mfma_f64_16x16x4f64 (FP64) or
 // v_mfma_f32_16x16x4f32 (FP32).  The MFMA is used "transposed": its A operand carries op(B)
 // (row index = output column j) and its B operand carries op(A) (column index = output row i),
-// so that each lane ends up owning 4 output elements of one output row i, and 16 lanes store 16
+// so that each lane ends up owning output elements of one output row i, and 16 lanes store 16
 // consecutive rows of one column: 256 contiguous bytes per store instruction for complex128.
 //
 // Workgroup = 4 waves (256 threads) computing a BM x BN complex output tile, each wave a
 // (BM/2) x (BN/2) sub-tile of 16x16 MFMA blocks.  Operands are staged through LDS in k-stages of
-// 16 complex elements with double buffering (one barrier per stage) and register prefetch of the
-// next stage's global loads.  Tiles are enumerated so that consecutive tiles (same rows of A,
-// neighbouring column tiles) land on the same XCD: the hardware hands workgroup w to XCD w % 8.
-// Split-K writes partial tiles to a workspace; the last K-slice to finish a tile sums the partials
-// in slice order (deterministic) and applies the epilogue, so one launch is one filter step.
+// 16 complex elements, double buffered with one barrier per stage: the global loads of stage s+1
+// are in flight while the MFMAs of stage s run.  Tiles are enumerated so that consecutive tiles
+// (same rows of A, neighbouring column tiles) land on the same XCD: the hardware hands workgroup w
+// to XCD w % 8.  Split-K writes partial tiles to a workspace; the last K-slice to finish a tile
+// sums the partials in slice order (deterministic) and applies the epilogue, so one launch is one
+// filter step.
 #include "common.h"
 
 namespace {
@@ -22,28 +23,21 @@ template <typename T> struct CT;
 template <> struct CT<double> { typedef double2 c; typedef d4 acc; };
 template <> struct CT<float> { typedef float2 c; typedef f4 acc; };
 
-__device__ inline d4 mfma16(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-__device__ inline f4 mfma16(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
 enum { EPI_GEMM = 0, EPI_FILTER = 1 };
 
-template <typename T>
-struct GArgs {
-    typedef typename CT<T>::c C2;
+// scalar arguments (pointers are passed as separate kernel arguments)
+struct GDims {
     int M, N, K;
-    const C2* A; int lda;
-    const C2* B; int ldb;
-    C2* C; int ldc;
+    int lda, ldb, ldc, ldyk, ldyp;
     double alpha, beta, shift;
-    const C2* Yk; int ldyk;
-    const C2* Yp; int ldyp;
-    C2* P;                 // split-K partials: ksplit blocks of M x N (leading dimension M)
-    int* cnt;              // split-K arrival counter per output tile (zero before and after)
     int kchunk, tiles_m, tiles_n, ksplit;
 };
 
 // logical tile of workgroup w such that each XCD owns one contiguous range of tiles
-__device__ inline int xcd_remap(int w, int nt)
+__device__ __forceinline__ int xcd_remap(int w, int nt)
 {
     const int X = 8;
     const int per = nt / X, rem = nt % X;
@@ -51,44 +45,54 @@ __device__ inline int xcd_remap(int w, int nt)
     return x * per + (x < rem ? x : rem) + q;
 }
 
-template <typename C2> __device__ inline C2 cconj(C2 v) { v.y = -v.y; return v; }
+template <typename C2> __device__ __forceinline__ C2 cconj(C2 v) { v.y = -v.y; return v; }
 
 // Row of the 16x16 MFMA result held in register r of lane l.  Measured on gfx950:
 // v_mfma_f32_16x16x4f32 holds row 4 (l/16) + r, v_mfma_f64_16x16x4f64 holds row 4 r + l/16;
 // both hold column l % 16.
-__device__ inline int drow(double, int lane, int r) { return 4 * r + (lane >> 4); }
-__device__ inline int drow(float, int lane, int r) { return 4 * (lane >> 4) + r; }
+__device__ __forceinline__ int drow(double, int lane, int r) { return 4 * r + (lane >> 4); }
+__device__ __forceinline__ int drow(float, int lane, int r) { return 4 * (lane >> 4) + r; }
 
 template <typename T, int EPI>
-__device__ inline void epilogue_store(const GArgs<T>& g, int i, int j, int ks, T vr, T vi)
+__device__ __forceinline__ void epilogue_store(const GDims& g, typename CT<T>::c* C,
+                                               const typename CT<T>::c* Yk, const typename CT<T>::c* Yp,
+                                               int i, int j, T vr, T vi)
 {
     typedef typename CT<T>::c C2;
-    (void)ks;
     if (EPI == EPI_GEMM) {
         const T al = (T)g.alpha, be = (T)g.beta;
         C2 o;
-        o.x = al * vr; o.y = al * vi;
+        o.x = al * vr;
+        o.y = al * vi;
         if (g.beta != 0.0) {
-            C2 c = g.C[(size_t)i + (size_t)j * g.ldc];
-            o.x += be * c.x; o.y += be * c.y;
+            const C2 c = C[(size_t)i + (size_t)j * g.ldc];
+            o.x += be * c.x;
+            o.y += be * c.y;
         }
-        g.C[(size_t)i + (size_t)j * g.ldc] = o;
+        C[(size_t)i + (size_t)j * g.ldc] = o;
     } else {
         const T al = (T)g.alpha, be = (T)g.beta, sh = (T)g.shift;
-        C2 yk = g.Yk[(size_t)i + (size_t)j * g.ldyk];
-        C2 yp = g.Yp[(size_t)i + (size_t)j * g.ldyp];
+        const C2 yk = Yk[(size_t)i + (size_t)j * g.ldyk];
+        const C2 yp = Yp[(size_t)i + (size_t)j * g.ldyp];
         C2 o;
         o.x = al * (vr - sh * yk.x) + be * yp.x;
         o.y = al * (vi - sh * yk.y) + be * yp.y;
-        g.C[(size_t)i + (size_t)j * g.ldc] = o;
+        C[(size_t)i + (size_t)j * g.ldc] = o;
     }
 }
 
-// SPLIT: this launch is one of ksplit K-slices of each output tile.  Every slice writes its partial
-// tile; the last slice to arrive (per-tile counter) sums the ksplit partials in slice order and
-// applies the epilogue, then clears the counter.  The sum order does not depend on arrival order.
-template <typename T, int OPA, int OPB, int EPI, int BM, int BN, bool SPLIT>
-__global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
+// MODE 0: one K-slice, the epilogue is applied directly.
+// MODE 1: this launch is one of ksplit K-slices of each output tile and only writes its partial
+//         tile; k_splitk_reduce (the next launch on the stream) sums the partials in slice order.
+// MODE 2: as 1, but the last slice to arrive (per-tile counter) sums the partials in slice order
+//         and applies the epilogue, then clears the counter.  Needs device-scope fences (an L2
+//         write-back per workgroup on gfx950), so it pays off only for few, long K-slices.
+// Every mode sums in a fixed order, so results do not depend on the arrival order.
+template <typename T, int OPA, int OPB, int EPI, int BM, int BN, int MODE>
+__global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c* __restrict__ A,
+                                               const typename CT<T>::c* __restrict__ B, typename CT<T>::c* C,
+                                               const typename CT<T>::c* Yk, const typename CT<T>::c* Yp,
+                                               typename CT<T>::c* __restrict__ P, int* __restrict__ cnt)
 {
     typedef typename CT<T>::c C2;
     typedef typename CT<T>::acc ACC;
@@ -123,47 +127,41 @@ __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
     C2 ra[NPA], rb[NPB];
     const C2 zero = {0, 0};
 
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int p = 0; p < NPA; ++p) {
-            const int e = tid + 256 * p;
-            if (OPA == OP_N) {
-                const int i = e % BM, k = e / BM, gi = i0 + i, gk = k0 + k;
-                ra[p] = (gi < g.M && gk < ke) ? g.A[(size_t)gi + (size_t)gk * g.lda] : zero;
-            } else {
-                const int k = e % BK, i = e / BK, gi = i0 + i, gk = k0 + k;
-                ra[p] = (gi < g.M && gk < ke) ? cconj(g.A[(size_t)gk + (size_t)gi * g.lda]) : zero;
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < NPB; ++p) {
-            const int e = tid + 256 * p;
-            if (OPB == OP_N) {
-                const int k = e % BK, j = e / BK, gk = k0 + k, gj = j0 + j;
-                rb[p] = (gj < g.N && gk < ke) ? g.B[(size_t)gk + (size_t)gj * g.ldb] : zero;
-            } else {
-                const int j = e % BN, k = e / BN, gk = k0 + k, gj = j0 + j;
-                rb[p] = (gj < g.N && gk < ke) ? cconj(g.B[(size_t)gj + (size_t)gk * g.ldb]) : zero;
-            }
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int p = 0; p < NPA; ++p) {
-            const int e = tid + 256 * p;
-            const int i = (OPA == OP_N) ? e % BM : e / BK;
-            const int k = (OPA == OP_N) ? e / BM : e % BK;
-            As[buf][k * LDA_S + i] = ra[p];
-        }
-#pragma unroll
-        for (int p = 0; p < NPB; ++p) {
-            const int e = tid + 256 * p;
-            const int j = (OPB == OP_N) ? e / BK : e % BN;
-            const int k = (OPB == OP_N) ? e % BK : e / BN;
-            Bs[buf][k * LDB_S + j] = rb[p];
-        }
-    };
-    auto compute = [&](int buf) {
+    // element p of a stage tile handled by this thread: op(A) row ai(p), column ak(p); op(B) row
+    // bk(p), column bj(p).  Consecutive threads walk the contiguous dimension of the stored matrix.
+#define AI(p) ((OPA == OP_N) ? (tid + 256 * (p)) % BM : (tid + 256 * (p)) / BK)
+#define AK(p) ((OPA == OP_N) ? (tid + 256 * (p)) / BM : (tid + 256 * (p)) % BK)
+#define BJ(p) ((OPB == OP_N) ? (tid + 256 * (p)) / BK : (tid + 256 * (p)) % BN)
+#define BKK(p) ((OPB == OP_N) ? (tid + 256 * (p)) % BK : (tid + 256 * (p)) / BN)
+#define GEMM_GLOAD(k0)                                                                                    \
+    {                                                                                                     \
+        _Pragma("unroll") for (int p = 0; p < NPA; ++p) {                                                 \
+            const int gi = i0 + AI(p), gk = (k0) + AK(p);                                                 \
+            const int ci = min(gi, g.M - 1), ck = min(gk, ke - 1);   /* clamped: always in bounds */    \
+            const size_t off = (OPA == OP_N) ? (size_t)ci + (size_t)ck * g.lda : (size_t)ck + (size_t)ci * g.lda; \
+            const C2 v = A[off];                                                                          \
+            ra[p] = (gi < g.M && gk < ke) ? ((OPA == OP_N) ? v : cconj(v)) : zero;                         \
+        }                                                                                                 \
+        _Pragma("unroll") for (int p = 0; p < NPB; ++p) {                                                 \
+            const int gj = j0 + BJ(p), gk = (k0) + BKK(p);                                                \
+            const int cj = min(gj, g.N - 1), ck = min(gk, ke - 1);                                        \
+            const size_t off = (OPB == OP_N) ? (size_t)ck + (size_t)cj * g.ldb : (size_t)cj + (size_t)ck * g.ldb; \
+            const C2 v = B[off];                                                                          \
+            rb[p] = (gj < g.N && gk < ke) ? ((OPB == OP_N) ? v : cconj(v)) : zero;                         \
+        }                                                                                                 \
+    }
+#define GEMM_SSTORE(buf)                                                                                  \
+    {                                                                                                     \
+        _Pragma("unroll") for (int p = 0; p < NPA; ++p) As[buf][AK(p) * LDA_S + AI(p)] = ra[p];           \
+        _Pragma("unroll") for (int p = 0; p < NPB; ++p) Bs[buf][BKK(p) * LDB_S + BJ(p)] = rb[p];          \
+    }
+
+    if (nstages > 0) GEMM_GLOAD(kb);
+    for (int s = 0; s < nstages; ++s) {
+        const int buf = s & 1;
+        GEMM_SSTORE(buf);
+        __syncthreads();
+        if (s + 1 < nstages) GEMM_GLOAD(kb + (s + 1) * BK);
         const C2* as = As[buf];
         const C2* bs = Bs[buf];
 #pragma unroll
@@ -190,22 +188,15 @@ __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
                     acci[bi][bj] = mfma16(b[bj].x, a[bi].y, acci[bi][bj]);
                 }
         }
-    };
-
-    if (nstages > 0) {
-        gload(kb);
-        sstore(0);
-        __syncthreads();
-        for (int s = 0; s < nstages; ++s) {
-            const int buf = s & 1;
-            if (s + 1 < nstages) gload(kb + (s + 1) * BK);
-            compute(buf);
-            if (s + 1 < nstages) sstore(buf ^ 1);
-            __syncthreads();
-        }
     }
+#undef GEMM_GLOAD
+#undef GEMM_SSTORE
+#undef AI
+#undef AK
+#undef BJ
+#undef BKK
 
-    if (!SPLIT) {
+    if (MODE == 0) {
 #pragma unroll
         for (int bi = 0; bi < MI; ++bi)
 #pragma unroll
@@ -214,7 +205,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + wr + bi * 16 + (lane & 15);
                     const int j = j0 + wc + bj * 16 + drow(T(0), lane, r);
-                    if (i < g.M && j < g.N) epilogue_store<T, EPI>(g, i, j, ks, accr[bi][bj][r], acci[bi][bj][r]);
+                    if (i < g.M && j < g.N) epilogue_store<T, EPI>(g, C, Yk, Yp, i, j, accr[bi][bj][r], acci[bi][bj][r]);
                 }
         return;
     }
@@ -232,14 +223,15 @@ __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
                     C2 o;
                     o.x = accr[bi][bj][r];
                     o.y = acci[bi][bj][r];
-                    g.P[(size_t)ks * slab + (size_t)i + (size_t)j * g.M] = o;
+                    P[(size_t)ks * slab + (size_t)i + (size_t)j * g.M] = o;
                 }
             }
+    if (MODE == 1) return;
     __threadfence();
     __shared__ int s_last;
     __syncthreads();
     if (tid == 0) {
-        const int old = atomicAdd(&g.cnt[it * g.tiles_n + jt], 1);
+        const int old = atomicAdd(&cnt[it * g.tiles_n + jt], 1);
         s_last = (old == g.ksplit - 1);
     }
     __syncthreads();
@@ -256,52 +248,106 @@ __global__ __launch_bounds__(256) void k_zgemm(GArgs<T> g)
                 if (i < g.M && j < g.N) {
                     T vr = 0, vi = 0;
                     for (int s = 0; s < g.ksplit; ++s) {
-                        const C2 p = g.P[(size_t)s * slab + (size_t)i + (size_t)j * g.M];
+                        const C2 p = P[(size_t)s * slab + (size_t)i + (size_t)j * g.M];
                         vr += p.x;
                         vi += p.y;
                     }
-                    epilogue_store<T, EPI>(g, i, j, 0, vr, vi);
+                    epilogue_store<T, EPI>(g, C, Yk, Yp, i, j, vr, vi);
                 }
             }
-    if (tid == 0) g.cnt[it * g.tiles_n + jt] = 0;
+    if (tid == 0) cnt[it * g.tiles_n + jt] = 0;
 }
 
-struct Plan { int bm, bn, ksplit, kchunk, tiles_m, tiles_n; };
+// Sums the ksplit partial tiles written by a MODE 1 launch in slice order and applies the epilogue.
+template <typename T, int EPI>
+__global__ __launch_bounds__(256) void k_splitk_reduce(GDims g, typename CT<T>::c* C, const typename CT<T>::c* Yk,
+                                                       const typename CT<T>::c* Yp,
+                                                       const typename CT<T>::c* __restrict__ P)
+{
+    typedef typename CT<T>::c C2;
+    const size_t slab = (size_t)g.M * g.N;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < slab; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % g.M), j = (int)(e / g.M);
+        T vr = 0, vi = 0;
+        for (int s = 0; s < g.ksplit; ++s) {
+            const C2 p = P[(size_t)s * slab + e];
+            vr += p.x;
+            vi += p.y;
+        }
+        epilogue_store<T, EPI>(g, C, Yk, Yp, i, j, vr, vi);
+    }
+}
 
-// Tile/split choice: enough workgroups for two per CU on 256 CUs, K slices of at least 256, and
-// the split limited by the partial buffer and the counter array.
+struct Plan { int bm, bn, ksplit, kchunk, tiles_m, tiles_n, mode; };
+
+// Tile/split choice.  A plan forced by the caller (autotuned) wins if the workspace allows it;
+// otherwise 64 x 64 (64 x 32 for narrow blocks) tiles, and K slices of at least 256 until there
+// are enough workgroups for two per CU on 256 CUs, with the partials summed by a second kernel.
 Plan make_plan(int M, int N, int K, const GemmWs& gw, int elem_bytes)
 {
     Plan p;
     p.bm = 64;
     p.bn = N <= 32 ? 32 : 64;
+    int ks = 1;
+    p.mode = 1;
+    const bool forced = gw.plan_bm > 0;
+    if (forced) {
+        p.bm = gw.plan_bm;
+        p.bn = gw.plan_bn;
+        ks = gw.plan_ksplit > 0 ? gw.plan_ksplit : 1;
+        p.mode = gw.plan_mode;
+    }
     p.tiles_m = (M + p.bm - 1) / p.bm;
     p.tiles_n = (N + p.bn - 1) / p.bn;
     const long tiles = (long)p.tiles_m * p.tiles_n;
-    int ks = 1;
-    while (tiles * ks < 512 && (long)K / (2 * ks) >= 256) ks *= 2;
-    if (!gw.ws || !gw.cnt || tiles > gw.ncnt) ks = 1;
+    if (!forced)
+        while (tiles * ks < 512 && (long)K / (2 * ks) >= 256) ks *= 2;
+    if (!gw.ws || (p.mode == 2 && (!gw.cnt || tiles > gw.ncnt))) ks = 1;
     while (ks > 1 && (size_t)ks * M * N * (size_t)elem_bytes > gw.bytes) ks /= 2;
     int kc = (K + ks - 1) / ks;
     kc = (kc + 15) / 16 * 16;
     p.kchunk = kc > 0 ? kc : 16;
     p.ksplit = K > 0 ? (K + p.kchunk - 1) / p.kchunk : 1;
+    if (p.ksplit <= 1) p.mode = 0;
     return p;
 }
 
+template <typename T, int OPA, int OPB, int EPI, int BM, int BN>
+void launch_tile(hipStream_t s, int nt, int mode, const GDims& g, const typename CT<T>::c* A,
+                 const typename CT<T>::c* B, typename CT<T>::c* C, const typename CT<T>::c* Yk,
+                 const typename CT<T>::c* Yp, typename CT<T>::c* P, int* cnt)
+{
+    if (mode == 0)
+        hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, BM, BN, 0>), dim3(nt), dim3(256), 0, s, g, A, B, C, Yk, Yp, P, cnt);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, BM, BN, 1>), dim3(nt), dim3(256), 0, s, g, A, B, C, Yk, Yp, P, cnt);
+    else
+        hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, BM, BN, 2>), dim3(nt), dim3(256), 0, s, g, A, B, C, Yk, Yp, P, cnt);
+}
+
 template <typename T, int OPA, int OPB, int EPI>
-int run(hipStream_t s, GArgs<T> g, const Plan& p)
+int run(hipStream_t s, GDims g, const Plan& p, const typename CT<T>::c* A, const typename CT<T>::c* B,
+        typename CT<T>::c* C, const typename CT<T>::c* Yk, const typename CT<T>::c* Yp, const GemmWs& gw)
 {
     g.kchunk = p.kchunk; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.ksplit = p.ksplit;
     const int nt = p.tiles_m * p.tiles_n * p.ksplit;
-    if (nt <= 0) return 0;
-#define LAUNCH(BN_, SP) hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, 64, BN_, SP>), dim3(nt), dim3(256), 0, s, g)
-    if (p.ksplit > 1) {
-        if (p.bn == 32) LAUNCH(32, true); else LAUNCH(64, true);
-    } else {
-        if (p.bn == 32) LAUNCH(32, false); else LAUNCH(64, false);
+    if (gw.plan_used) {
+        gw.plan_used[0] = p.bm; gw.plan_used[1] = p.bn; gw.plan_used[2] = p.ksplit; gw.plan_used[3] = p.mode;
     }
-#undef LAUNCH
+    if (nt <= 0) return 0;
+    typedef typename CT<T>::c C2;
+    C2* P = (C2*)gw.ws;
+    if (p.bm == 64 && p.bn == 64) launch_tile<T, OPA, OPB, EPI, 64, 64>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
+    else if (p.bm == 64) launch_tile<T, OPA, OPB, EPI, 64, 32>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
+    else if (p.bn == 64) launch_tile<T, OPA, OPB, EPI, 32, 64>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
+    else launch_tile<T, OPA, OPB, EPI, 32, 32>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
+    if (gw.ev_main) (void)hipEventRecord(gw.ev_main, s);
+    if (p.mode == 1) {
+        const size_t total = (size_t)g.M * g.N;
+        int blocks = (int)((total + 255) / 256);
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL((k_splitk_reduce<T, EPI>), dim3(blocks), dim3(256), 0, s, g, C, Yk, Yp, P);
+    }
     return (int)hipGetLastError();
 }
 
@@ -322,36 +368,34 @@ int launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, double al
                  const zd* B, int ldb, double beta, zd* C, int ldc, const GemmWs& gw)
 {
     if (M <= 0 || N <= 0) return 0;
-    GArgs<double> g = {};
-    g.M = M; g.N = N; g.K = K; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
-    g.alpha = alpha; g.beta = beta; g.P = (zd*)gw.ws; g.cnt = gw.cnt;
+    GDims g = {};
+    g.M = M; g.N = N; g.K = K; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
     Plan p = make_plan(M, N, K, gw, 16);
-    if (opa == OP_N && opb == OP_N) return run<double, OP_N, OP_N, EPI_GEMM>(s, g, p);
-    if (opa == OP_C && opb == OP_N) return run<double, OP_C, OP_N, EPI_GEMM>(s, g, p);
-    if (opa == OP_N && opb == OP_C) return run<double, OP_N, OP_C, EPI_GEMM>(s, g, p);
-    return run<double, OP_C, OP_C, EPI_GEMM>(s, g, p);
+    if (opa == OP_N && opb == OP_N) return run<double, OP_N, OP_N, EPI_GEMM>(s, g, p, A, B, C, nullptr, nullptr, gw);
+    if (opa == OP_C && opb == OP_N) return run<double, OP_C, OP_N, EPI_GEMM>(s, g, p, A, B, C, nullptr, nullptr, gw);
+    if (opa == OP_N && opb == OP_C) return run<double, OP_N, OP_C, EPI_GEMM>(s, g, p, A, B, C, nullptr, nullptr, gw);
+    return run<double, OP_C, OP_C, EPI_GEMM>(s, g, p, A, B, C, nullptr, nullptr, gw);
 }
 
 int launch_filter_step_f64(hipStream_t s, int n, int ncols, const zd* H, int ldh, const zd* Yk, int ldyk,
                            const zd* Yprev, int ldyp, zd* Yout, int ldyo, FilterStep fs, const GemmWs& gw)
 {
     if (n <= 0 || ncols <= 0) return 0;
-    GArgs<double> g = {};
-    g.M = n; g.N = ncols; g.K = n; g.A = H; g.lda = ldh; g.B = Yk; g.ldb = ldyk; g.C = Yout; g.ldc = ldyo;
-    g.alpha = fs.alpha; g.beta = fs.beta; g.shift = fs.shift; g.Yk = Yk; g.ldyk = ldyk; g.Yp = Yprev;
-    g.ldyp = ldyp; g.P = (zd*)gw.ws; g.cnt = gw.cnt;
+    GDims g = {};
+    g.M = n; g.N = ncols; g.K = n; g.lda = ldh; g.ldb = ldyk; g.ldc = ldyo; g.ldyk = ldyk; g.ldyp = ldyp;
+    g.alpha = fs.alpha; g.beta = fs.beta; g.shift = fs.shift;
     Plan p = make_plan(n, ncols, n, gw, 16);
-    return run<double, OP_N, OP_N, EPI_FILTER>(s, g, p);
+    return run<double, OP_N, OP_N, EPI_FILTER>(s, g, p, H, Yk, Yout, Yk, Yprev, gw);
 }
 
 int launch_filter_step_f32(hipStream_t s, int n, int ncols, const zf* H, int ldh, const zf* Yk, int ldyk,
                            const zf* Yprev, int ldyp, zf* Yout, int ldyo, FilterStep fs, const GemmWs& gw)
 {
     if (n <= 0 || ncols <= 0) return 0;
-    GArgs<float> g = {};
-    g.M = n; g.N = ncols; g.K = n; g.A = H; g.lda = ldh; g.B = Yk; g.ldb = ldyk; g.C = Yout; g.ldc = ldyo;
-    g.alpha = fs.alpha; g.beta = fs.beta; g.shift = fs.shift; g.Yk = Yk; g.ldyk = ldyk; g.Yp = Yprev;
-    g.ldyp = ldyp; g.P = (zf*)gw.ws; g.cnt = gw.cnt;
+    GDims g = {};
+    g.M = n; g.N = ncols; g.K = n; g.lda = ldh; g.ldb = ldyk; g.ldc = ldyo; g.ldyk = ldyk; g.ldyp = ldyp;
+    g.alpha = fs.alpha; g.beta = fs.beta; g.shift = fs.shift;
     Plan p = make_plan(n, ncols, n, gw, 8);
-    return run<float, OP_N, OP_N, EPI_FILTER>(s, g, p);
+    return run<float, OP_N, OP_N, EPI_FILTER>(s, g, p, H, Yk, Yout, Yk, Yprev, gw);
 }

@@ -334,6 +334,10 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
         if (split) hipLaunchKernelGGL((k_filter_bf16<3, true>), dim3(nt), dim3(256), 0, s, g);
         else hipLaunchKernelGGL((k_filter_bf16<3, false>), dim3(nt), dim3(256), 0, s, g);
     }
+    if (gw.plan_used) {
+        gw.plan_used[0] = 64; gw.plan_used[1] = 64; gw.plan_used[2] = g.ksplit; gw.plan_used[3] = split ? 2 : 0;
+    }
+    if (gw.ev_main) (void)hipEventRecord(gw.ev_main, s);
     return (int)hipGetLastError();
 }
 
@@ -357,8 +361,9 @@ chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int
         const int ldo = (k % 2 == 1) ? n : ldy;
         const zf* yp = (k == 1) ? yk : yo;
         const int ldp = (k == 1) ? ldk : ldo;
-        h->ktimer.begin(st);
-        if (launch_filter_step_bf16(st, n, w, Hb, ldh, nterms, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ysplit, gw))
+        GemmWs gs = gw;
+        gs.ev_main = h->ktimer.begin(st, n, w, nterms == 2 ? CHFSI_BF16X3 : CHFSI_BF16X6, &gs.plan_used);
+        if (launch_filter_step_bf16(st, n, w, Hb, ldh, nterms, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ysplit, gs))
             return CHFSI_ERR_DEVICE;
         h->ktimer.end(st);
         flops += 8.0 * (double)n * (double)n * (double)w;

@@ -84,32 +84,47 @@ KernelTimer::~KernelTimer()
     for (auto& e : pool) (void)hipEventDestroy(e);
 }
 
-void KernelTimer::begin(hipStream_t s)
+hipEvent_t KernelTimer::begin(hipStream_t s, int n, int ncols, int prec, int** plan_slot)
 {
-    if (!enabled) return;
-    while (pool.size() < used + 2) {
+    if (plan_slot) *plan_slot = nullptr;
+    if (!enabled) return nullptr;
+    while (pool.size() < used + 3) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { enabled = false; return; }
+        if (hipEventCreate(&e) != hipSuccess) { enabled = false; return nullptr; }
         pool.push_back(e);
     }
+    const size_t r = used / 3;
+    if (recs.size() <= r) recs.resize(r + 1);
+    recs[r] = Rec{n, ncols, prec, {0, 0, 0, 0}};
+    if (plan_slot) *plan_slot = recs[r].plan;
     (void)hipEventRecord(pool[used], s);
+    return pool[used + 1];
 }
 
 void KernelTimer::end(hipStream_t s)
 {
-    if (!enabled || pool.size() < used + 2) return;
-    (void)hipEventRecord(pool[used + 1], s);
-    used += 2;
+    if (!enabled || pool.size() < used + 3) return;
+    (void)hipEventRecord(pool[used + 2], s);
+    used += 3;
 }
 
-double KernelTimer::collect(int* launches)
+double KernelTimer::collect(int* launches, double* step_ms)
 {
-    double t = 0;
-    for (size_t i = 0; i + 1 < used; i += 2) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, pool[i], pool[i + 1]) == hipSuccess) t += ms;
+    double t = 0, ts = 0;
+    log.clear();
+    for (size_t i = 0; i + 3 <= used; i += 3) {
+        float m1 = 0, m2 = 0;
+        (void)hipEventElapsedTime(&m1, pool[i], pool[i + 1]);
+        (void)hipEventElapsedTime(&m2, pool[i], pool[i + 2]);
+        t += m1;
+        ts += m2;
+        const Rec& r = recs[i / 3];
+        const double row[9] = {(double)r.n, (double)r.ncols, (double)r.prec, (double)r.plan[0], (double)r.plan[1],
+                               (double)r.plan[2], (double)r.plan[3], (double)m1, (double)m2};
+        log.insert(log.end(), row, row + 9);
     }
-    if (launches) *launches = (int)(used / 2);
+    if (launches) *launches = (int)(used / 3);
+    if (step_ms) *step_ms = ts;
     used = 0;
     return t;
 }
@@ -430,8 +445,11 @@ chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma,
         const int ldo = (k % 2 == 1) ? ldt : ldy;
         const C2* yp = (k == 1) ? yk : yo;          // beta == 0 on step 1: any finite input
         const int ldp = (k == 1) ? ldk : ldo;
-        h->ktimer.begin(st);
-        TRY(step_fn(st, n, w, Hm, ldh, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], gw));
+        GemmWs gs = gw;
+        const int pr = sizeof(C2) == 16 ? CHFSI_FP64 : CHFSI_FP32;
+        apply_tuned_plan(h, pr, n, w, gs);
+        gs.ev_main = h->ktimer.begin(st, n, w, pr, &gs.plan_used);
+        TRY(step_fn(st, n, w, Hm, ldh, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], gs));
         h->ktimer.end(st);
         flops += 8.0 * (double)n * (double)n * (double)w;
         matvecs += w;

@@ -382,3 +382,34 @@ def test_adam_step_parity(hd, orc, torch_dev):
     orc.adam_step(P64, g.astype(np.float64), m64, v64, 3, lr=1e-2)
     assert np.max(np.abs(dP.cpu().numpy() - P64)) <= 1e-5
     assert np.max(np.abs(dm.cpu().numpy() - m64)) <= 1e-6
+
+
+# ---- every tile plan of the filter kernel --------------------------------------------------------
+
+@pytest.mark.parametrize("plan", [dict(bm=64, bn=64, ksplit=1, fused=0), dict(bm=64, bn=64, ksplit=4, fused=0),
+                                  dict(bm=64, bn=64, ksplit=4, fused=1), dict(bm=32, bn=64, ksplit=2, fused=0),
+                                  dict(bm=64, bn=32, ksplit=8, fused=1), dict(bm=32, bn=32, ksplit=1, fused=0),
+                                  dict(bm=32, bn=32, ksplit=16, fused=0), dict(bm=32, bn=32, ksplit=3, fused=1)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-4)])
+def test_filter_every_tile_plan(hd, orc, plan, prec, tol):
+    n, m = 520, 70                      # ragged in both tile sizes
+    H, Y0, a, b, mu1 = _filter_case(n, m)
+    ref = orc.cheb_filter(H, Y0, a, b, mu1, deg=6)
+    hd.set_filter_plan(n, m, prec, plan)
+    try:
+        dY = dev(Y0)
+        hd.filter(dev(H), dY, a, b, mu1, deg=6, prec=prec)
+    finally:
+        hd.set_filter_plan(n, m, prec, None)
+    assert relerr(host(dY), ref) <= tol
+
+
+def test_autotune_filter_returns_a_valid_plan(hd, orc):
+    plan, ms = hd.autotune_filter(256, 40, 0)
+    assert plan["bm"] in (32, 64) and plan["bn"] in (32, 64) and plan["ksplit"] >= 1 and ms > 0
+    H, Y0, a, b, mu1 = _filter_case(256, 40)
+    ref = orc.cheb_filter(H, Y0, a, b, mu1, deg=5)
+    dY = dev(Y0)
+    hd.filter(dev(H), dY, a, b, mu1, deg=5, prec=0)
+    hd.set_filter_plan(256, 40, 0, None)
+    assert relerr(host(dY), ref) <= 1e-12
