@@ -111,14 +111,11 @@ def main() -> int:
     seq = sequence.Sequence(spec, keep_host=not args.no_cpu_baseline)
     log(f"inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
 
-    # setup: the project autotuner picks the filter-step tile plan per block width
-    tuned = {}
-    widths = sorted({m, (3 * m) // 4, m // 2, m // 4, 32}, reverse=True)
-    for prec_name, prec in (("fp64", chfsi.FP64), ("fp32", chfsi.FP32)):
-        for w in widths:
-            plan, ms = seq.h.autotune_filter(n, w, prec)
-            tuned[f"{prec_name}/{w}"] = dict(plan, ms=round(ms, 4))
-    log("autotuned filter plans: " + json.dumps(tuned))
+    # filter-step tile plans: the table written by the project autotuner (paper_1206_3768_amd/autotune.py)
+    from paper_1206_3768_amd import autotune
+    tuned = {f"{'fp64' if e['prec'] == 0 else 'fp32'}/{e['m']}": e["plan"]
+             for e in json.load(open(autotune.TABLE))["plans"] if e["n"] == n} if seq.tuned_entries else {}
+    log(f"{seq.tuned_entries} tuned plans loaded; n={n}: " + json.dumps(tuned))
 
     ref = seq.run_reference()
     bad = [r.cycle for r in ref if r.status != 0]

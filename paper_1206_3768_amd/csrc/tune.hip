@@ -12,15 +12,23 @@
 
 void apply_tuned_plan(chfsi_handle h, int prec, int n, int ncols, GemmWs& gw)
 {
+    // tuned n closest to n (ratio within 1.5), then the narrowest tuned width >= ncols, else the widest
+    int nbest = -1;
+    double rbest = 1.5;
+    for (const TuneEntry& e : h->plans) {
+        if (e.prec != prec) continue;
+        const double r = e.n > n ? (double)e.n / n : (double)n / e.n;
+        if (r <= rbest) { rbest = r; nbest = e.n; }
+    }
+    if (nbest < 0) return;
     const TuneEntry* best = nullptr;
     for (const TuneEntry& e : h->plans) {
-        if (e.prec != prec || e.n != n || e.m < ncols) continue;
+        if (e.prec != prec || e.n != nbest || e.m < ncols) continue;
         if (!best || e.m < best->m) best = &e;
     }
-    if (!best) {   // wider than every tuned width: take the widest entry
+    if (!best)
         for (const TuneEntry& e : h->plans)
-            if (e.prec == prec && e.n == n && (!best || e.m > best->m)) best = &e;
-    }
+            if (e.prec == prec && e.n == nbest && (!best || e.m > best->m)) best = &e;
     if (!best) return;
     gw.plan_bm = best->bm;
     gw.plan_bn = best->bn;

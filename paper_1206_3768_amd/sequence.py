@@ -37,6 +37,8 @@ class Sequence:
         self.torch = torch
         self.spec = spec
         self.h = handle or chfsi.Handle(device)
+        from . import autotune
+        self.tuned_entries = autotune.load(self.h)
         self.dev = f"cuda:{device}"
         self.m = spec.nev + spec.nex
         self.A: List = []
