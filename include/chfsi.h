@@ -52,7 +52,8 @@ typedef enum {
 typedef enum {
     CHFSI_DEG_FIXED = 0,          /* every vector gets `deg`                                    */
     CHFSI_DEG_ANALYTIC = 1,       /* from the Chebyshev growth rate at its Ritz value           */
-    CHFSI_DEG_LEARNED = 2         /* from the degree network set by chfsi_set_degree_model      */
+    CHFSI_DEG_LEARNED = 2,        /* from the degree network set by chfsi_set_degree_model      */
+    CHFSI_DEG_RANDOM = 3          /* uniform in [deg_min, deg_max] (Philox stream 4): traces    */
 } chfsi_degree_policy;
 
 typedef struct {
@@ -208,11 +209,14 @@ chfsi_status chfsi_zgemm(chfsi_handle h, char transa, char transb, int m, int n,
  * NULL clears the model; CHFSI_ERR_ARG if nbytes does not match. */
 chfsi_status chfsi_set_degree_model(chfsi_handle h, const void* blob, size_t nbytes);
 
-/* Copies the trace recorded by the last solve with p->trace = 1 into host_buf.  Each row is
- * CHFSI_TRACE_COLS doubles: loop, column, t = (theta - c)/e, log10 r_before, a, b, degree used,
- * r_after (the same column's residual after the next loop; -1 if none), lock threshold.
+/* Copies the trace recorded by the last solve with p->trace = 1 into host_buf.  One row per active
+ * column and loop, CHFSI_TRACE_COLS doubles: loop, column position, t = (theta - c)/e, log10 r
+ * (residual after this loop), (a - mu1)/(b - mu1), (b - mu1)/(|mu1| + |b|) (with the bounds of the
+ * next filter), degree used in this loop, degree assigned for the next loop, r_after (the residual
+ * at the same position after the next loop; -1 if none), lock threshold.  These are the network's
+ * features (t, log10 r / threshold, the two bound ratios, previous degree) and its label data.
  * With host_buf NULL only *nbytes is set. */
-#define CHFSI_TRACE_COLS 9
+#define CHFSI_TRACE_COLS 10
 chfsi_status chfsi_get_trace(chfsi_handle h, void* host_buf, size_t* nbytes);
 
 /* Degree-network kernels (FP32, device pointers), used by training and by the gradient checks.

@@ -22,8 +22,8 @@ _lib = None
 
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
-DEG_FIXED, DEG_ANALYTIC, DEG_LEARNED = 0, 1, 2
-TRACE_COLS = 9
+DEG_FIXED, DEG_ANALYTIC, DEG_LEARNED, DEG_RANDOM = 0, 1, 2, 3
+TRACE_COLS = 10
 MLP_NPARAM = 8769
 STATUS_NAMES = {0: "success", 1: "invalid argument", 2: "not HPD", 3: "no convergence", 4: "numeric",
                 5: "device", 6: "alloc"}

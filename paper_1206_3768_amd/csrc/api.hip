@@ -107,6 +107,24 @@ chfsi_status prepare(chfsi_handle h, SolveBufs& b, int n, int m, int k, bool gen
     return h->ws.failed ? CHFSI_ERR_ALLOC : CHFSI_SUCCESS;
 }
 
+// uniform degree in [dmin, dmax] from Philox4x64-10, counter (loop, column, 4, 0), key (seed, 0)
+int random_degree(unsigned long long seed, int loop, int col, int dmin, int dmax)
+{
+    uint64_t c[4] = {(uint64_t)loop, (uint64_t)col, 4, 0};
+    uint64_t k0 = seed, k1 = 0;
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B97F4A7C15ULL; k1 += 0xBB67AE8584CAA73BULL; }
+        const unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ULL * c[0];
+        const unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ULL * c[2];
+        const uint64_t y0 = (uint64_t)(p1 >> 64) ^ c[1] ^ k0, y2 = (uint64_t)(p0 >> 64) ^ c[3] ^ k1;
+        c[1] = (uint64_t)p1;
+        c[3] = (uint64_t)p0;
+        c[0] = y0;
+        c[2] = y2;
+    }
+    return dmin + (int)(c[0] % (uint64_t)(dmax - dmin + 1));
+}
+
 int analytic_degree(double theta, double r, double a, double b, double thr, int dmin, int dmax)
 {
     const double c = 0.5 * (a + b), e = 0.5 * (b - a);
@@ -197,7 +215,7 @@ chfsi_status finalize(chfsi_handle h, SolveBufs& b, int n, int m, const zd* A, i
     return CHFSI_SUCCESS;
 }
 
-struct TraceRow { int loop, col; double t, lr, a, b; int d; double r_after, thr; };
+struct TraceRow { int loop, col; double t, lr, a, b; int d_prev, d; double r_after, thr; };
 
 chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* X, int ldx,
                         int x_is_guess, double* lambda, double* resid, const chfsi_params& p, chfsi_stats& stt)
@@ -207,7 +225,7 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
     const int prec = p.filter_precision;
     if (n <= 0 || nev <= 0 || p.nex < 0 || m > n || lda < n || ldx < n || (S && lds < n) || !A || !X || !lambda ||
         !resid || p.deg < 0 || !(p.tol > 0) || p.max_loops < 1 || prec < 0 || prec > 3 || p.deg_min < 0 ||
-        p.deg_max < p.deg_min || p.degree_policy < 0 || p.degree_policy > 2)
+        p.deg_max < p.deg_min || p.degree_policy < 0 || p.degree_policy > 3)
         return CHFSI_ERR_ARG;
     if (p.degree_policy == CHFSI_DEG_LEARNED && !h->has_model) return CHFSI_ERR_ARG;
     int k = p.lanczos_steps;
@@ -286,6 +304,7 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
 
     // --- inner loop of Algorithm 1
     std::vector<int> deg(m, p.deg), lowp(m, prec != CHFSI_FP64 ? 1 : 0);
+    std::vector<int> deg_used(m, p.deg);
     std::vector<double> hth(m), hr(m), rprev(m, -1.0), rho(m);
     std::vector<int> last_row(m, -1);
     std::vector<TraceRow> trace;
@@ -330,6 +349,7 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
             if (!std::isfinite(hth[j]) || !std::isfinite(hr[j])) status = CHFSI_ERR_NUMERIC;
         if (status == CHFSI_ERR_NUMERIC) { tm.mark(PH_LOCK, st, false); break; }
 
+        for (int j = 0; j < ma; ++j) deg_used[nlocked + j] = deg[nlocked + j];   // degrees of this loop
         // trace: close the rows of the previous loop, open rows for this one
         if (p.trace) {
             for (int j = 0; j < ma; ++j) {
@@ -359,6 +379,9 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
         if (p.degree_policy == CHFSI_DEG_ANALYTIC) {
             for (int j = cnt; j < ma; ++j)
                 deg[nlocked + j] = analytic_degree(hth[j], hr[j], a, bb, thr, p.deg_min, p.deg_max);
+        } else if (p.degree_policy == CHFSI_DEG_RANDOM) {
+            for (int j = cnt; j < ma; ++j)
+                deg[nlocked + j] = random_degree(p.seed, it, nlocked + j, p.deg_min, p.deg_max);
         } else if (p.degree_policy == CHFSI_DEG_LEARNED) {
             TRYS(learned_degrees(h, ma - cnt, b.theta + cnt, b.r + cnt, a, bb, mu1, thr,
                                  std::vector<int>(deg.begin() + nl2, deg.end()), b.feat, b.dpred, b.iperm,
@@ -373,7 +396,8 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
                 TraceRow row;
                 row.loop = it; row.col = pos; row.t = (hth[j] - c2) / e2;
                 row.lr = std::log10(std::max(hr[j], 1e-300)); row.a = (a - mu1) / (bb - mu1);
-                row.b = (bb - mu1) / (std::fabs(mu1) + std::fabs(bb)); row.d = deg[pos]; row.r_after = -1.0;
+                row.b = (bb - mu1) / (std::fabs(mu1) + std::fabs(bb)); row.d_prev = deg_used[pos];
+                row.d = deg[pos]; row.r_after = -1.0;
                 row.thr = thr;
                 last_row[pos] = (int)trace.size();
                 trace.push_back(row);
@@ -422,8 +446,8 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
     if (p.trace) {
         h->trace.clear();
         for (auto& r : trace) {
-            const double row[CHFSI_TRACE_COLS] = {(double)r.loop, (double)r.col, r.t, r.lr, r.a, r.b, (double)r.d,
-                                                  r.r_after, r.thr};
+            const double row[CHFSI_TRACE_COLS] = {(double)r.loop, (double)r.col, r.t, r.lr, r.a, r.b,
+                                                  (double)r.d_prev, (double)r.d, r.r_after, r.thr};
             h->trace.insert(h->trace.end(), row, row + CHFSI_TRACE_COLS);
         }
     }

@@ -44,19 +44,44 @@ def _rng(seed: int, stream: int) -> np.random.Generator:
 
 
 def complex_gaussian(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
-    """i.i.d. complex normal entries, real and imaginary parts N(0, 1/2), Fortran order."""
-    z = rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))
-    return np.asfortranarray(z * math.sqrt(0.5))
+    """i.i.d. complex normal entries, real and imaginary parts N(0, 1/2), Fortran order.
+
+    The draws fill the matrix column by column, real then imaginary part of each entry."""
+    buf = np.empty((cols, 2 * rows))
+    rng.standard_normal(out=buf)
+    buf *= math.sqrt(0.5)
+    return buf.view(np.complex128).T          # (rows, cols), Fortran-ordered view
+
+
+def _t(a: np.ndarray):
+    """Fortran-ordered complex matrix -> torch tensor of its transpose (C-contiguous, no copy)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a.T))
+
+
+def _from_t(t) -> np.ndarray:
+    """torch tensor holding a transpose -> Fortran-ordered numpy matrix (no copy)."""
+    return t.numpy().T
+
+
+def _to_fortran(t) -> np.ndarray:
+    """torch matrix -> Fortran-ordered numpy array with the same entries (threaded transpose copy)."""
+    return t.T.contiguous().numpy().T
+
+
+def haar_unitary_t(rng: np.random.Generator, n: int):
+    """Haar-distributed n x n unitary as a torch tensor: QR of a complex Gaussian (an i.i.d. matrix,
+    taken in whichever memory order it was drawn) with R's diagonal made real positive."""
+    import torch
+    z = torch.from_numpy(complex_gaussian(rng, n, n).T)      # C-contiguous; still i.i.d. Gaussian
+    q, r = torch.linalg.qr(z)
+    d = torch.diagonal(r)
+    return q * (d / d.abs())[None, :]
 
 
 def haar_unitary(rng: np.random.Generator, n: int) -> np.ndarray:
-    """Haar-distributed n x n unitary: QR of a complex Gaussian with R's diagonal made real positive."""
-    z = complex_gaussian(rng, n, n)
-    q, r = sla.qr(z, overwrite_a=True, check_finite=False)
-    d = np.diag(r)
-    ph = d / np.abs(d)
-    q *= ph[None, :]
-    return np.asfortranarray(q)
+    """Haar-distributed n x n unitary, Fortran order."""
+    return _to_fortran(haar_unitary_t(rng, n))
 
 
 def split_spectrum(rng: np.random.Generator, n: int, n_low: int) -> np.ndarray:
@@ -68,18 +93,18 @@ def split_spectrum(rng: np.random.Generator, n: int, n_low: int) -> np.ndarray:
 
 def overlap_matrix(rng: np.random.Generator, n: int, rank: int = 64) -> np.ndarray:
     """HPD overlap S = I + G G^H / n with G an n x rank complex Gaussian."""
-    g = complex_gaussian(rng, n, rank)
-    s = g @ g.conj().T
-    s /= n
-    s[np.diag_indices(n)] += 1.0
+    import torch
+    g = torch.from_numpy(complex_gaussian(rng, rank, n).T)   # n x rank, i.i.d.
+    s = (g @ g.conj().T) / n
     s = 0.5 * (s + s.conj().T)
-    return np.asfortranarray(s)
+    s.diagonal().add_(1.0)
+    return _to_fortran(s)
 
 
 def hermitian_noise(rng: np.random.Generator, n: int) -> np.ndarray:
-    """(E + E^H) / 2 with E an i.i.d. complex Gaussian."""
-    e = complex_gaussian(rng, n, n)
-    return np.asfortranarray(0.5 * (e + e.conj().T))
+    """(E + E^H) / 2 with E an i.i.d. complex Gaussian (exactly Hermitian in floating point)."""
+    et = _t(complex_gaussian(rng, n, n))      # E^T
+    return _from_t(0.5 * (et + et.conj().T))   # (E^T + conj(E))/2 = ((E + E^H)/2)^T
 
 
 @dataclasses.dataclass
@@ -112,31 +137,36 @@ class SequenceSpec:
 
 def designed_pencil(spec: SequenceSpec, keep_vectors: bool = True) -> Pencil:
     """Cycle-0 pencil in designed form: exact spectrum and eigenvectors are known."""
+    import torch
     n = spec.n
     lam = split_spectrum(_rng(spec.seed, _STREAM_LAM), n, spec.n_low)
-    q = haar_unitary(_rng(spec.seed, _STREAM_Q), n)
+    q = haar_unitary_t(_rng(spec.seed, _STREAM_Q), n)
+    lt = torch.from_numpy(lam)
     if spec.generalized:
         s = overlap_matrix(_rng(spec.seed, _STREAM_G), n)
-        lchol = sla.cholesky(s, lower=True, check_finite=False)
+        lchol = torch.linalg.cholesky(torch.from_numpy(s))
         lq = lchol @ q
-        a = (lq * lam[None, :]) @ lq.conj().T
-        x = sla.solve_triangular(lchol, q, lower=True, trans="C", check_finite=False) if keep_vectors else None
+        a = (lq * lt[None, :]) @ lq.conj().T
+        x = torch.linalg.solve_triangular(lchol.conj().T, q, upper=True) if keep_vectors else None
     else:
         s = None
-        a = (q * lam[None, :]) @ q.conj().T
+        a = (q * lt[None, :]) @ q.conj().T
         x = q if keep_vectors else None
-    a = np.asfortranarray(0.5 * (a + a.conj().T))
-    return Pencil(A=a, S=s, lam_exact=lam, X_exact=None if x is None else np.asfortranarray(x), cycle=0)
+    a = 0.5 * (a + a.conj().T)
+    return Pencil(A=_to_fortran(a), S=s, lam_exact=lam, X_exact=None if x is None else _to_fortran(x), cycle=0)
 
 
 def sequence(spec: SequenceSpec, keep_vectors: bool = False) -> Iterator[Pencil]:
-    """Yield the pencils of cycles 0 .. spec.cycles-1 (A_{l+1} = A_l + eps_l (E_l + E_l^H)/2)."""
+    """Yield the pencils of cycles 0 .. spec.cycles-1 (A_{l+1} = A_l + eps_l (E_l + E_l^H)/2).
+
+    Every term is exactly Hermitian, so every A_l is exactly Hermitian as well."""
     p = designed_pencil(spec, keep_vectors=keep_vectors)
     yield p
     a = p.A
     for ell in range(1, spec.cycles):
-        a = a + spec.eps(ell - 1) * hermitian_noise(_rng(spec.seed, _STREAM_E0 + ell - 1), spec.n)
-        a = np.asfortranarray(0.5 * (a + a.conj().T))
+        e = hermitian_noise(_rng(spec.seed, _STREAM_E0 + ell - 1), spec.n)
+        e *= spec.eps(ell - 1)
+        a = a + e
         yield Pencil(A=a, S=p.S, lam_exact=None, X_exact=None, cycle=ell)
 
 
@@ -195,8 +225,9 @@ def kpoint_problem(k: int, n: int, seed: int = 0, eps: float = 1e-3) -> KPointPr
     spec = SequenceSpec(n=n, n_low=int(math.ceil(0.05 * n)), generalized=True, cycles=1, eps0=eps,
                         eps_decay=1.0, seed=1000 * (seed + 1) + k, nev=nev, nex=nex, deg=12)
     p = designed_pencil(spec, keep_vectors=True)
-    a = p.A + eps * hermitian_noise(_rng(spec.seed, _STREAM_E0), n)
-    a = np.asfortranarray(0.5 * (a + a.conj().T))
+    e = hermitian_noise(_rng(spec.seed, _STREAM_E0), n)
+    e *= eps
+    a = p.A + e
     m = nev + nex
     return KPointProblem(n=n, nev=nev, nex=nex, A=a, S=p.S, X0=np.asfortranarray(p.X_exact[:, :m]),
                          lam_prev=p.lam_exact[:m].copy())

@@ -1,0 +1,88 @@
+"""GPU: the learned per-vector degree.  Traces from the solver, labels, training with the
+library's own kernels (gradients checked against the CPU oracle in test_gpu_parity), and what the
+trained network gains over the fixed degree."""
+import numpy as np
+import pytest
+
+from paper_1206_3768_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1206_3768_amd import chfsi
+    h = chfsi.Handle(0)
+    yield h
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def small_traces(hd):
+    from paper_1206_3768_amd import degree_model
+    spec = synth.config_learned_degree(seed=3, n=512, cycles=3)
+    return degree_model.generate_traces(hd, spec)
+
+
+def test_traces_have_labels(small_traces):
+    from paper_1206_3768_amd import chfsi, degree_model
+    tr = small_traces
+    assert tr.shape[1] == chfsi.TRACE_COLS and tr.shape[0] > 100
+    assert np.all((tr[:, 6] >= 4) & (tr[:, 6] <= 30)) and np.all((tr[:, 7] >= 4) & (tr[:, 7] <= 30))
+    y, valid = degree_model.labels(tr)
+    assert valid.mean() > 0.5
+    assert np.all((y[valid] >= 4) & (y[valid] <= 30))
+
+
+def test_training_reduces_loss_and_matches_oracle_forward(hd, small_traces, orc):
+    import torch
+    from paper_1206_3768_amd import degree_model
+    y, valid = degree_model.labels(small_traces)
+    X = degree_model.features(small_traces)[valid]
+    P, mean, std, hist = degree_model.train(hd, X, y[valid], epochs=15, batch=64, lr=2e-3)
+    assert hist[-1] < 0.7 * hist[0]
+    Xn = ((X - mean) / std).astype(np.float32)
+    gpu = hd.mlp_forward(torch.from_numpy(P).cuda(), torch.from_numpy(Xn).cuda()).cpu().numpy()
+    ref = orc.mlp_forward(P.astype(np.float64), Xn.astype(np.float64))
+    assert np.max(np.abs(gpu - ref) / ref) <= 1e-5
+
+
+def test_learned_policy_solves_match_fixed_policy(hd, small_traces):
+    from paper_1206_3768_amd import chfsi, degree_model, sequence
+    y, valid = degree_model.labels(small_traces)
+    X = degree_model.features(small_traces)[valid]
+    P, mean, std, _ = degree_model.train(hd, X, y[valid], epochs=10, batch=64, lr=2e-3)
+    hd.set_degree_model(degree_model.make_blob(P, mean, std))
+    seq = sequence.Sequence(synth.config_learned_degree(seed=0, n=512, cycles=3), handle=hd)
+    fixed = degree_model.run_policy(hd, seq, chfsi.DEG_FIXED, deg=12)
+    learned = degree_model.run_policy(hd, seq, chfsi.DEG_LEARNED)
+    assert fixed["ok"] and learned["ok"] and learned["max_resid"] <= 1e-10
+    for a, b in zip(fixed["lam"], learned["lam"]):
+        assert np.all(np.abs(a - b) <= 1e-10 * np.maximum(np.abs(a), 1e-3))
+    hd.set_degree_model(None)
+
+
+def test_trained_network_gains_over_fixed_degree(hd):
+    """The committed network (trained on seeds 1..8 of the n=4096 sequence) against the best fixed
+    degree on held-out seed 0: fewer matrix-vector products and less filter time, same accuracy."""
+    from paper_1206_3768_amd import chfsi, degree_model, sequence
+    blob = degree_model.load()
+    if blob is None:
+        pytest.skip("no trained degree model committed")
+    hd.set_degree_model(blob)
+    seq = sequence.Sequence(synth.config_learned_degree(seed=0, n=4096, cycles=6), handle=hd)
+    best_fixed = None
+    for d in (8, 12, 16, 20, 25):
+        r = degree_model.run_policy(hd, seq, chfsi.DEG_FIXED, deg=d)
+        assert r["ok"]
+        if best_fixed is None or r["filter_ms"] < best_fixed["filter_ms"]:
+            best_fixed = r
+    learned = degree_model.run_policy(hd, seq, chfsi.DEG_LEARNED)
+    hd.set_degree_model(None)
+    assert learned["ok"] and learned["max_resid"] <= 1e-10
+    for a, b in zip(best_fixed["lam"], learned["lam"]):
+        assert np.all(np.abs(a - b) <= 1e-10 * np.maximum(np.abs(a), 1e-3))
+    assert learned["matvecs"] < best_fixed["matvecs"]
