@@ -74,6 +74,9 @@ typedef struct {
     double switch_residual;       /* mixed precision: a vector whose residual falls below
                                      switch_residual * ||A||_lo is filtered in FP64 from then on
                                      (0 = precision-dependent default)                          */
+    int deg_margin;               /* added to every degree of the ANALYTIC and LEARNED policies
+                                     (before the clamp to deg_max): a safety margin against an
+                                     extra loop caused by an underestimated degree (0)           */
 } chfsi_params;
 
 typedef struct {
@@ -104,6 +107,11 @@ typedef struct {
     double* resid;                /* host [nev + nex]                                           */
 } chfsi_problem;
 
+/* Tile plan of the filter-step kernel: a bm x bn complex output tile per workgroup (32 or 64
+ * each) and the K dimension cut into ksplit slices (1 = none) whose partial tiles are summed in
+ * slice order either by a second kernel (fused = 0) or by the last slice to finish (fused = 1). */
+typedef struct { int bm, bn, ksplit, fused; } chfsi_tile_plan;
+
 /* Fills *p with the defaults listed above (Table 3 of the paper: degree 25, TOL 1e-10). */
 void chfsi_default_params(chfsi_params* p);
 
@@ -129,12 +137,41 @@ chfsi_status chfsi_solve(chfsi_handle h, int n, const void* A, int lda, const vo
                          void* X, int ldx, int x_is_guess, double* lambda, double* resid,
                          const chfsi_params* p, chfsi_stats* stats);
 
-/* Solves `count` independent problems (k-points of one self-consistent cycle, Section 2.1) with
- * shared parameters p (p->nev and p->nex are ignored: each problem carries its own).  The filter
- * steps of all unconverged problems run as one persistent launch per step.  stats: [count],
- * nullable.  Returns the first non-success status of any problem. */
+/* Solves `count` independent problems (the k-points of one self-consistent cycle, Section 2.1:
+ * one generalized eigenproblem per k-point) with shared parameters p (p->nev and p->nex are
+ * ignored: each problem carries its own; p->filter_precision must be CHFSI_FP64; p->trace has
+ * no effect).  All unconverged problems advance through Algorithm 1 in lockstep loops: each
+ * filter step of all of them is one persistent launch over a work list of output tiles of every
+ * problem (tile plan from chfsi_autotune_batched / chfsi_set_batched_plan), the steps of a loop
+ * replayed as one captured HIP graph; QR, Rayleigh-Ritz, locking and verification run per problem
+ * on four internal streams.  Per problem the results match chfsi_solve with the same parameters
+ * up to rounding.  Up to 64 problems share a launch; larger batches run in chunks of 64.
+ * stats: [count], nullable; t_total of every entry is the wall time of the whole call, phase
+ * times are not recorded (chfsi_batched_info has the filter time).  Returns the first
+ * non-success status of any problem; the others are still solved. */
 chfsi_status chfsi_solve_batched(chfsi_handle h, int count, const chfsi_problem* probs,
                                  const chfsi_params* p, chfsi_stats* stats);
+
+/* Tile plan of the persistent multi-problem filter kernel of chfsi_solve_batched (bm, bn in
+ * {32, 64}; ksplit and fused are ignored; plan NULL keeps the current one), whether each loop's
+ * filter steps replay a captured HIP graph (use_graph != 0, the default) or are launched one by
+ * one, and over how many streams (lanes, 1 .. 8; 0 keeps the current value, default 4) the
+ * per-problem dense steps are spread. */
+chfsi_status chfsi_set_batched_plan(chfsi_handle h, const chfsi_tile_plan* plan, int use_graph, int lanes);
+
+/* Project autotuner of the persistent multi-problem filter kernel: times one filter step over all
+ * `count` (<= 64) problems for every candidate tile (64x64, 64x32, 32x64, 32x32) with hipEvents,
+ * reading A as the matrix and X as the block (neither is modified; outputs go to scratch it
+ * allocates and frees), keeps the fastest for later chfsi_solve_batched calls and returns it with
+ * its time per step in ms (both nullable). */
+chfsi_status chfsi_autotune_batched(chfsi_handle h, int count, const chfsi_problem* probs,
+                                    chfsi_tile_plan* best, double* best_ms);
+
+/* Counters of the last chfsi_solve_batched (host pointers, each nullable): filter time in ms
+ * (hipEvents around each loop's filter launches, summed), filter flops (8 n^2 per column and
+ * step), graph replays and persistent kernel launches. */
+chfsi_status chfsi_batched_info(chfsi_handle h, double* filter_ms, double* filter_flops,
+                                int* graph_launches, int* kernel_launches);
 
 /* Applies the Chebyshev filter of Algorithm 1 in place to Y (n x m):
  *   Y <- T_d((H - cI)/e) Y / T_d((mu1 - c)/e),  c = (a+b)/2, e = (b-a)/2,
@@ -156,10 +193,6 @@ chfsi_status chfsi_filter_kernel_time(chfsi_handle h, double* total_ms, int* lau
  * holds; *count = rows available (rows == NULL: only *count is set). */
 chfsi_status chfsi_filter_launch_log(chfsi_handle h, double* rows, int cap, int* count);
 
-/* Tile plan of the filter-step kernel: a bm x bn complex output tile per workgroup (32 or 64
- * each) and the K dimension cut into ksplit slices (1 = none) whose partial tiles are summed in
- * slice order either by a second kernel (fused = 0) or by the last slice to finish (fused = 1). */
-typedef struct { int bm, bn, ksplit, fused; } chfsi_tile_plan;
 
 /* Project autotuner of the filter-step kernel: times every candidate plan for the n x m filter
  * step in precision prec (CHFSI_FP64 or CHFSI_FP32) on scratch buffers with hipEvents, stores the

@@ -25,6 +25,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 DEG_FIXED, DEG_ANALYTIC, DEG_LEARNED, DEG_RANDOM = 0, 1, 2, 3
 TRACE_COLS = 10
 MLP_NPARAM = 8769
+SUCCESS, ERR_ARG, ERR_NOT_HPD, ERR_NO_CONVERGENCE, ERR_NUMERIC, ERR_DEVICE, ERR_ALLOC = range(7)
 STATUS_NAMES = {0: "success", 1: "invalid argument", 2: "not HPD", 3: "no convergence", 4: "numeric",
                 5: "device", 6: "alloc"}
 
@@ -40,7 +41,7 @@ class Params(C.Structure):
                 ("max_loops", C.c_int), ("lanczos_steps", C.c_int), ("filter_precision", C.c_int),
                 ("degree_policy", C.c_int), ("deg_min", C.c_int), ("deg_max", C.c_int),
                 ("seed", C.c_ulonglong), ("have_bounds", C.c_int), ("mu1", C.c_double), ("a", C.c_double),
-                ("trace", C.c_int), ("switch_residual", C.c_double)]
+                ("trace", C.c_int), ("switch_residual", C.c_double), ("deg_margin", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -75,7 +76,8 @@ EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solv
             "chfsi_zgemm", "chfsi_random_block", "chfsi_set_degree_model", "chfsi_get_trace", "chfsi_mlp_forward",
             "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string",
             "chfsi_filter_kernel_time", "chfsi_autotune_filter", "chfsi_set_filter_plan",
-            "chfsi_filter_launch_log"]
+            "chfsi_filter_launch_log", "chfsi_set_batched_plan", "chfsi_autotune_batched",
+            "chfsi_batched_info"]
 
 
 def load():
@@ -110,10 +112,17 @@ def load():
     lib.chfsi_filter_launch_log.argtypes = [vp, vp, i, vp]
     lib.chfsi_autotune_filter.argtypes = [vp, i, i, i, C.POINTER(TilePlan), vp]
     lib.chfsi_set_filter_plan.argtypes = [vp, i, i, i, C.POINTER(TilePlan)]
+    lib.chfsi_set_batched_plan.argtypes = [vp, C.POINTER(TilePlan), i, i]
+    lib.chfsi_autotune_batched.argtypes = [vp, i, C.POINTER(Problem), C.POINTER(TilePlan), vp]
+    lib.chfsi_batched_info.argtypes = [vp, vp, vp, vp, vp]
     lib.chfsi_status_string.argtypes = [i]
     lib.chfsi_status_string.restype = C.c_char_p
     _lib = lib
     return lib
+
+
+def status_string(st: int) -> str:
+    return STATUS_NAMES.get(int(st), f"status {int(st)}")
 
 
 def default_params(**kw) -> Params:
@@ -203,9 +212,8 @@ class Handle:
             raise ChfsiError(status, "chfsi_solve")
         return SolveResult(status=int(status), lam=lam, resid=res, stats=st.as_dict())
 
-    def solve_batched(self, problems: Sequence[dict], params: Params):
-        """problems: dicts with keys A, S (or None), X, nev, nex, x_is_guess.  Returns (status,
-        [SolveResult])."""
+    @staticmethod
+    def _problems(problems: Sequence[dict]):
         cnt = len(problems)
         arr = (Problem * cnt)()
         outs = []
@@ -218,11 +226,42 @@ class Handle:
             arr[k] = Problem(A.shape[-1], pr["nev"], pr["nex"], _ptr(A), A.shape[-1], _ptr(S),
                              0 if S is None else S.shape[-1], _ptr(X), X.shape[-1], 1 if pr.get("x_is_guess") else 0,
                              lam.ctypes.data, res.ctypes.data)
+        return arr, outs
+
+    def solve_batched(self, problems: Sequence[dict], params: Params):
+        """problems: dicts with keys A, S (or None), X, nev, nex, x_is_guess (device tensors in the
+        layout of to_device).  Returns (status, [SolveResult])."""
+        cnt = len(problems)
+        arr, outs = self._problems(problems)
         st = (Stats * cnt)()
         status = self.lib.chfsi_solve_batched(self.h, cnt, arr, C.byref(params), st)
         results = [SolveResult(status=int(st[k].status), lam=outs[k][0], resid=outs[k][1], stats=st[k].as_dict())
                    for k in range(cnt)]
         return int(status), results
+
+    def set_batched_plan(self, bm: Optional[int] = None, bn: Optional[int] = None, use_graph: bool = True,
+                         lanes: int = 0):
+        plan = None if bm is None else C.byref(TilePlan(bm, bn, 1, 0))
+        self._check(self.lib.chfsi_set_batched_plan(self.h, plan, 1 if use_graph else 0, lanes),
+                    "chfsi_set_batched_plan")
+
+    def autotune_batched(self, problems: Sequence[dict]):
+        """Tunes the persistent multi-problem filter tile on these problems; returns ((bm, bn), ms)."""
+        arr, _ = self._problems(problems)
+        plan = TilePlan()
+        ms = np.zeros(1)
+        self._check(self.lib.chfsi_autotune_batched(self.h, len(problems), arr, C.byref(plan), ms.ctypes.data),
+                    "chfsi_autotune_batched")
+        return (plan.bm, plan.bn), float(ms[0])
+
+    def batched_info(self) -> dict:
+        """Filter ms, filter flops, graph replays and kernel launches of the last solve_batched."""
+        t = np.zeros(2)
+        c = np.zeros(2, dtype=np.int32)
+        self._check(self.lib.chfsi_batched_info(self.h, t.ctypes.data, t[1:].ctypes.data, c.ctypes.data,
+                                                c[1:].ctypes.data), "chfsi_batched_info")
+        return {"filter_ms": float(t[0]), "filter_flops": float(t[1]), "graph_launches": int(c[0]),
+                "kernel_launches": int(c[1])}
 
     # ---- steps -------------------------------------------------------------------------------
     def filter(self, H, Y, a: float, b: float, mu1: float, deg=10, prec: int = FP64, n: Optional[int] = None):

@@ -13,6 +13,7 @@
 #include "chfsi.h"
 #include "common.h"
 #include "driver.h"
+#include "state.h"
 
 namespace {
 
@@ -26,25 +27,6 @@ namespace {
         chfsi_status s_ = (x);                 \
         if (s_ != CHFSI_SUCCESS) return s_;    \
     } while (0)
-
-struct SolveBufs {
-    zd *H = nullptr, *L = nullptr;     // n x n (H aliases A for a standard FP64 problem)
-    zf* Hf = nullptr;                  // n x n complex64 copy of H (low-precision filter)
-    uint16_t* Hb = nullptr;            // BF16 planes of H
-    zd *V = nullptr, *T = nullptr, *HY = nullptr;   // n x m
-    zf *Vf = nullptr, *Tf = nullptr;   // n x m complex64
-    uint16_t* ysplit = nullptr;        // BF16 split of Y_k
-    zd *G = nullptr, *Cm = nullptr;    // m x m
-    double *theta = nullptr, *r = nullptr, *E = nullptr, *lam = nullptr, *dsc = nullptr;
-    int* info = nullptr;
-    int* flag = nullptr;
-    int* iperm = nullptr;
-    zd *LV = nullptr, *lw = nullptr, *lc = nullptr;
-    double* lcoef = nullptr;
-    float* feat = nullptr;
-    float* dpred = nullptr;
-    GemmWs gw;                         // split-K partials + the handle's tile counters
-};
 
 void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
 {
@@ -82,6 +64,7 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
     b.lcoef = ar.take<double>(2 * (size_t)k + 16);
     b.feat = ar.take<float>((size_t)m * MLP_NF + 16);
     b.dpred = ar.take<float>(m + 16);
+    b.eigw = ar.get(eig_work_bytes(m));
     // split-K partials: the largest of the filter (n x m, K = n) and the Gram products (m x m, K = n)
     size_t ws = std::max(zgemm_ws_bytes(n, m, n, 16), zgemm_ws_bytes(m, m, n, 16));
     ws = std::max(ws, zgemm_ws_bytes(n, m, m, 16));
@@ -91,20 +74,7 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
 
 chfsi_status prepare(chfsi_handle h, SolveBufs& b, int n, int m, int k, bool gen, int prec)
 {
-    h->ws.begin(true);
-    layout(h->ws, b, n, m, k, gen, prec);
-    const size_t need = h->ws.off;
-    if (need > h->ws.cap) {
-        (void)hipStreamSynchronize(h->stream);
-        h->ws.grow(need + (need >> 3));
-        if (h->ws.cap < need) return CHFSI_ERR_ALLOC;
-    }
-    h->ws.begin(false);
-    b = SolveBufs();
-    layout(h->ws, b, n, m, k, gen, prec);
-    b.gw.cnt = h->tile_cnt;
-    b.gw.ncnt = h->tile_cnt_len;
-    return h->ws.failed ? CHFSI_ERR_ALLOC : CHFSI_SUCCESS;
+    return prepare_bufs(h, h->ws, b, n, m, k, gen, prec);
 }
 
 // uniform degree in [dmin, dmax] from Philox4x64-10, counter (loop, column, 4, 0), key (seed, 0)
@@ -186,244 +156,400 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
     return CHFSI_SUCCESS;
 }
 
-// X = L^{-H} V (or V), rho_j = ||A x_j - lambda_j S x_j|| / norm_a for all m columns
-chfsi_status finalize(chfsi_handle h, SolveBufs& b, int n, int m, const zd* A, int lda, const zd* S, int lds,
-                      zd* X, int ldx, const double* lambda, double norm_a, double* resid)
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// the phases of one solve (state.h)
+// ---------------------------------------------------------------------------------------------
+
+chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
 {
-    hipStream_t st = h->stream;
-    TRY(launch_zlacpy(st, n, m, b.V, n, X, ldx));
-    if (S) {
-        const rocblas_double_complex one(1.0, 0.0);
-        if (rocblas_ztrsm(h->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                          rocblas_diagonal_non_unit, n, m, &one, reinterpret_cast<rocblas_double_complex*>(b.L), n,
-                          reinterpret_cast<rocblas_double_complex*>(X), ldx) != rocblas_status_success)
-            return CHFSI_ERR_DEVICE;
+    ar.begin(true);
+    layout(ar, b, n, m, k, gen, prec);
+    const size_t need = ar.off;
+    if (need > ar.cap) {
+        (void)hipStreamSynchronize(h->stream);
+        ar.grow(need + (need >> 3));
+        if (ar.cap < need) return CHFSI_ERR_ALLOC;
     }
-    TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, A, lda, X, ldx, 0.0, b.HY, n, b.gw));
-    const zd* SX = X;
-    int ldsx = ldx;
-    if (S) {
-        TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, S, lds, X, ldx, 0.0, b.T, n, b.gw));
-        SX = b.T;
-        ldsx = n;
-    }
-    TRY(hipMemcpyAsync(b.lam, lambda, sizeof(double) * m, hipMemcpyHostToDevice, st));
-    TRY(launch_residual_norms(st, n, m, b.HY, n, SX, ldsx, b.lam, b.r));
-    TRY(hipMemcpyAsync(resid, b.r, sizeof(double) * m, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
-    for (int j = 0; j < m; ++j) resid[j] /= norm_a;
-    return CHFSI_SUCCESS;
+    ar.begin(false);
+    b = SolveBufs();
+    layout(ar, b, n, m, k, gen, prec);
+    b.gw.cnt = h->tile_cnt;
+    b.gw.ncnt = h->tile_cnt_len;
+    return ar.failed ? CHFSI_ERR_ALLOC : CHFSI_SUCCESS;
 }
 
-struct TraceRow { int loop, col; double t, lr, a, b; int d_prev, d; double r_after, thr; };
-
-chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* X, int ldx,
-                        int x_is_guess, double* lambda, double* resid, const chfsi_params& p, chfsi_stats& stt)
+chfsi_status st_define(SolveState& s, int n, const zd* A, int lda, const zd* S, int lds, zd* X, int ldx,
+                       int x_is_guess, double* lambda, double* resid, const chfsi_params& p)
 {
-    hipStream_t st = h->stream;
     const int nev = p.nev, m = p.nev + p.nex;
     const int prec = p.filter_precision;
     if (n <= 0 || nev <= 0 || p.nex < 0 || m > n || lda < n || ldx < n || (S && lds < n) || !A || !X || !lambda ||
         !resid || p.deg < 0 || !(p.tol > 0) || p.max_loops < 1 || prec < 0 || prec > 3 || p.deg_min < 0 ||
         p.deg_max < p.deg_min || p.degree_policy < 0 || p.degree_policy > 3)
         return CHFSI_ERR_ARG;
-    if (p.degree_policy == CHFSI_DEG_LEARNED && !h->has_model) return CHFSI_ERR_ARG;
-    int k = p.lanczos_steps;
-    k = std::max(k, 10);
+    s.n = n; s.nev = nev; s.m = m; s.prec = prec;
+    s.A = A; s.lda = lda; s.S = S; s.lds = lds; s.X = X; s.ldx = ldx; s.x_is_guess = x_is_guess;
+    s.lambda = lambda; s.resid = resid; s.p = p;
+    int k = std::max(p.lanczos_steps, 10);
     k = std::min(k, 3 * m);
-    k = std::min(k, n);
+    s.k = std::min(k, n);
+    return CHFSI_SUCCESS;
+}
 
-    SolveBufs b;
-    const bool gen = S != nullptr;
-    TRYS(prepare(h, b, n, m, k, gen, prec));
+chfsi_status st_setup(chfsi_handle h, SolveState& s, Arena& ar, PinBuf& pin)
+{
+    if (s.p.degree_policy == CHFSI_DEG_LEARNED && !h->has_model) return CHFSI_ERR_ARG;
+    TRYS(prepare_bufs(h, ar, s.b, s.n, s.m, s.k, s.S != nullptr, s.prec));
+    const size_t nd = SolveState::pinned_doubles(s.m, s.k);
+    if (!pin.reserve(sizeof(double) * nd + sizeof(int) * (32 + 2 * (size_t)s.m))) return CHFSI_ERR_ALLOC;
+    s.hd = (double*)pin.p;
+    s.hi = (int*)(pin.p + sizeof(double) * nd);
+    std::memset(s.hi, 0, sizeof(int) * 32);
+    return CHFSI_SUCCESS;
+}
+
+static inline void mark(SolveState& s, int phase, hipStream_t st, bool begin)
+{
+    if (s.tm) s.tm->mark(phase, st, begin);
+}
+
+chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
+{
+    hipStream_t st = h->stream;
+    SolveBufs& b = s.b;
+    const int n = s.n, m = s.m;
+    s.t0 = std::chrono::steady_clock::now();
+    // --- reduction to standard form (Section 3.2)
+    mark(s, PH_REDUCE, st, true);
+    s.H = s.A;
+    s.ldh = s.lda;
+    s.hi[0] = 0;
+    if (s.S) {
+        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.info, s.hi));
+        s.H = b.H;
+        s.ldh = n;
+    }
+    double* hn = s.h_norms();
+    hn[1] = 1.0;
+    TRY(launch_max_colnorm(st, n, s.A, s.lda, b.dsc));
+    TRY(hipMemcpyAsync(&hn[0], b.dsc, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (s.S) {
+        TRY(launch_max_rowsum_abs(st, n, s.S, s.lds, b.dsc));
+        TRY(hipMemcpyAsync(&hn[1], b.dsc, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    if (s.prec == CHFSI_FP32) TRY(launch_z2c(st, n, n, s.H, s.ldh, b.Hf, n));
+    if (s.prec == CHFSI_BF16X3 || s.prec == CHFSI_BF16X6)
+        TRY(launch_split_h_bf16(st, n, s.H, s.ldh, b.Hb, n, s.prec == CHFSI_BF16X3 ? 2 : 3));
+    // starting block in standard coordinates
+    if (s.x_is_guess) {
+        if (s.S) TRY(launch_zgemm(st, OP_C, OP_N, n, m, n, 1.0, b.L, n, s.X, s.ldx, 0.0, b.V, n, b.gw));
+        else TRY(launch_zlacpy(st, n, m, s.X, s.ldx, b.V, n));
+    } else {
+        TRY(launch_philox_block(st, s.p.seed, 1, n, m, b.V, n));
+    }
+    mark(s, PH_REDUCE, st, false);
+    // --- Lanczos bounds
+    mark(s, PH_LANCZOS, st, true);
+    TRYS(step_lanczos_enqueue(h, n, s.H, s.ldh, s.k, s.p.seed, b.LV, b.lw, b.lc, b.lcoef, s.h_al(), s.h_be()));
+    mark(s, PH_LANCZOS, st, false);
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status st_init_complete(chfsi_handle h, SolveState& s)
+{
+    TRY(hipStreamSynchronize(h->stream));
+    if (s.S && s.hi[0] != 0) return CHFSI_ERR_NOT_HPD;
+    const chfsi_params& p = s.p;
+    const int m = s.m;
+    const double norm_a = s.h_norms()[0], s_inf = s.h_norms()[1];
+    if (!std::isfinite(norm_a) || !std::isfinite(s_inf) || !(norm_a > 0)) return CHFSI_ERR_NUMERIC;
+    s.norm_a = norm_a;
+    s.thr = p.tol * norm_a / std::sqrt(s_inf);
+    std::vector<double> lth, lz;
+    double beta_k = 0;
+    int kk = 0;
+    TRYS(lanczos_finish(s.k, s.h_al(), s.h_be(), lth, lz, beta_k, kk));
+    s.k = kk;
+    // b = largest Ritz value + beta_k; a from the cumulative weight m / n; mu1 = smallest
+    s.bb = lth[kk - 1] + beta_k;
+    s.mu1 = lth[0];
+    s.a = lth[kk - 1];
+    {
+        const double frac = (double)m / s.n;
+        double cum = 0;
+        for (int j = 0; j < kk; ++j) {
+            cum += lz[j];
+            if (cum >= frac) { s.a = lth[j]; break; }
+        }
+        if (!(s.a > s.mu1) || !(s.a < s.bb)) s.a = 0.5 * (s.mu1 + s.bb);
+    }
+    if (p.have_bounds) {
+        s.mu1 = p.mu1;
+        s.a = p.a;
+        if (!(s.a > s.mu1) || !(s.a < s.bb)) s.a = 0.5 * (s.mu1 + s.bb);
+    }
+    s.deg.assign(m, p.deg);
+    s.lowp.assign(m, s.prec != CHFSI_FP64 ? 1 : 0);
+    s.deg_used.assign(m, p.deg);
+    s.rprev.assign(m, -1.0);
+    s.last_row.assign(m, -1);
+    s.trace.clear();
+    const double sw_rel = p.switch_residual > 0 ? p.switch_residual : (s.prec == CHFSI_BF16X3 ? 1e-3 : 1e-5);
+    s.sw_thr = sw_rel * norm_a;
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status st_filter(chfsi_handle h, SolveState& s)
+{
+    const int ma = s.ma();
+    mark(s, PH_FILTER, h->stream, true);
+    std::vector<int> dact(s.deg.begin() + s.nlocked, s.deg.end()), lact(s.lowp.begin() + s.nlocked, s.lowp.end());
+    TRYS(run_filter(h, s.b, s.n, s.H, s.ldh, s.prec, ma, s.Ya(), s.n, dact, lact, s.a, s.bb, s.mu1, s.flops,
+                    s.matvecs));
+    mark(s, PH_FILTER, h->stream, false);
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status st_order_columns(chfsi_handle h, SolveState& s, std::vector<int>& dsorted)
+{
+    hipStream_t st = h->stream;
+    const int ma = s.ma(), n = s.n;
+    std::vector<int> ord(ma);
+    std::iota(ord.begin(), ord.end(), 0);
+    const int* d = s.deg.data() + s.nlocked;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] > d[y]; });
+    dsorted.resize(ma);
+    bool ident = true;
+    for (int j = 0; j < ma; ++j) { dsorted[j] = d[ord[j]]; ident &= ord[j] == j; }
+    if (!ident) {
+        int* perm = s.hi + 32;   // pinned staging [m]
+        std::memcpy(perm, ord.data(), sizeof(int) * ma);
+        TRY(hipMemcpyAsync(s.b.iperm, perm, sizeof(int) * ma, hipMemcpyHostToDevice, st));
+        TRY(launch_permute_cols(st, n, ma, s.Ya(), n, s.b.T, n, s.b.iperm));
+        TRY(launch_zlacpy(st, n, ma, s.b.T, n, s.Ya(), n));
+    }
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status st_loop_enqueue(chfsi_handle h, SolveState& s)
+{
+    hipStream_t st = h->stream;
+    SolveBufs& b = s.b;
+    const int ma = s.ma(), n = s.n;
+    zd* Ya = s.Ya();
+    s.loops += 1;
+    s.filtered += ma;
+    mark(s, PH_QR, st, true);
+    TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, st));
+    TRYS(step_orthonormalize(h, n, ma, Ya, n, s.nlocked, b.V, n, b.G, b.Cm, b.dsc, b.info, b.gw));
+    mark(s, PH_QR, st, false);
+    mark(s, PH_RR, st, true);
+    TRYS(step_rayleigh_ritz(h, n, s.H, s.ldh, ma, Ya, n, b.HY, b.T, b.G, b.theta, b.r, b.eigw, s.h_eig(), b.gw,
+                            s.tm));
+    mark(s, PH_RR, st, false);
+    TRY(hipMemcpyAsync(s.h_theta(), b.theta, sizeof(double) * ma, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(s.h_r(), b.r, sizeof(double) * ma, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(s.hi + 8, b.info, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status st_loop_complete(chfsi_handle h, SolveState& s)
+{
+    hipStream_t st = h->stream;
+    TRY(hipStreamSynchronize(st));
+    const chfsi_params& p = s.p;
+    const int ma = s.ma(), nev = s.nev, nlocked = s.nlocked, it = s.loops - 1;
+    const double* hth = s.h_theta();
+    const double* hr = s.h_r();
+    for (int j = 0; j < 8; ++j)
+        if (s.hi[8 + j] != 0) return CHFSI_ERR_NUMERIC;
+    for (int j = 0; j < ma; ++j)
+        if (!std::isfinite(hth[j]) || !std::isfinite(hr[j])) return CHFSI_ERR_NUMERIC;
+    mark(s, PH_LOCK, st, true);
+
+    for (int j = 0; j < ma; ++j) s.deg_used[nlocked + j] = s.deg[nlocked + j];   // degrees of this loop
+    // trace: close the rows of the previous loop
+    if (p.trace)
+        for (int j = 0; j < ma; ++j) {
+            const int pos = nlocked + j;
+            if (s.last_row[pos] >= 0) s.trace[s.last_row[pos]].r_after = hr[j];
+        }
+    int cnt = 0;
+    while (cnt < nev - nlocked && hr[cnt] <= s.thr) ++cnt;
+    for (int j = 0; j < ma; ++j) { s.lambda[nlocked + j] = hth[j]; s.resid[nlocked + j] = hr[j]; }
+
+    // per-column precision for the next loop: back to FP64 once a residual is small or stagnates
+    const int nl2 = nlocked + cnt;
+    for (int j = cnt; j < ma; ++j) {
+        const int pos = nlocked + j;
+        if (s.lowp[pos]) {
+            const bool stagnated = s.rprev[pos] > 0 && hr[j] > 0.1 * s.rprev[pos];
+            if (hr[j] <= s.sw_thr || stagnated) { s.lowp[pos] = 0; ++s.switches; }
+        }
+    }
+    // bounds for the next filter
+    s.a = hth[ma - 1];
+    s.mu1 = std::min(s.mu1, hth[0]);
+    if (!(s.a > s.mu1)) s.a = 0.5 * (s.mu1 + s.bb);
+    const double a = s.a, bb = s.bb, mu1 = s.mu1, thr = s.thr;
+    if (p.degree_policy == CHFSI_DEG_ANALYTIC) {
+        for (int j = cnt; j < ma; ++j)
+            s.deg[nlocked + j] = analytic_degree(hth[j], hr[j], a, bb, thr, p.deg_min, p.deg_max);
+    } else if (p.degree_policy == CHFSI_DEG_RANDOM) {
+        for (int j = cnt; j < ma; ++j)
+            s.deg[nlocked + j] = random_degree(p.seed, it, nlocked + j, p.deg_min, p.deg_max);
+    } else if (p.degree_policy == CHFSI_DEG_LEARNED) {
+        TRYS(learned_degrees(h, ma - cnt, s.b.theta + cnt, s.b.r + cnt, a, bb, mu1, thr,
+                             std::vector<int>(s.deg.begin() + nl2, s.deg.end()), s.b.feat, s.b.dpred, s.b.iperm,
+                             p.deg_min, p.deg_max, s.deg.data() + nl2,
+                             [&](int j) { return analytic_degree(hth[cnt + j], hr[cnt + j], a, bb, thr,
+                                                                 p.deg_min, p.deg_max); }));
+    }
+    if (p.deg_margin != 0 && (p.degree_policy == CHFSI_DEG_ANALYTIC || p.degree_policy == CHFSI_DEG_LEARNED))
+        for (int j = cnt; j < ma; ++j)
+            s.deg[nlocked + j] = std::max(p.deg_min, std::min(p.deg_max, s.deg[nlocked + j] + p.deg_margin));
+    if (p.trace) {
+        const double c2 = 0.5 * (a + bb), e2 = 0.5 * (bb - a);
+        for (int j = cnt; j < ma; ++j) {
+            const int pos = nlocked + j;
+            TraceRow row;
+            row.loop = it; row.col = pos; row.t = (hth[j] - c2) / e2;
+            row.lr = std::log10(std::max(hr[j], 1e-300)); row.a = (a - mu1) / (bb - mu1);
+            row.b = (bb - mu1) / (std::fabs(mu1) + std::fabs(bb)); row.d_prev = s.deg_used[pos];
+            row.d = s.deg[pos]; row.r_after = -1.0;
+            row.thr = thr;
+            s.last_row[pos] = (int)s.trace.size();
+            s.trace.push_back(row);
+        }
+    }
+    for (int j = 0; j < ma; ++j) s.rprev[nlocked + j] = hr[j];
+    s.nlocked = nl2;
+    mark(s, PH_LOCK, st, false);
+    s.want_final = s.nlocked >= nev;
+    return CHFSI_SUCCESS;
+}
+
+// X = L^{-H} V (or V), rho_j = ||A x_j - lambda_j S x_j|| / ||A||_lo for all m columns
+chfsi_status st_final_enqueue(chfsi_handle h, SolveState& s)
+{
+    hipStream_t st = h->stream;
+    SolveBufs& b = s.b;
+    const int n = s.n, m = s.m;
+    mark(s, PH_BACK, st, true);
+    TRY(launch_zlacpy(st, n, m, b.V, n, s.X, s.ldx));
+    if (s.S) {
+        const rocblas_double_complex one(1.0, 0.0);
+        if (rocblas_ztrsm(h->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                          rocblas_diagonal_non_unit, n, m, &one, reinterpret_cast<rocblas_double_complex*>(b.L), n,
+                          reinterpret_cast<rocblas_double_complex*>(s.X), s.ldx) != rocblas_status_success)
+            return CHFSI_ERR_DEVICE;
+    }
+    TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.A, s.lda, s.X, s.ldx, 0.0, b.HY, n, b.gw));
+    const zd* SX = s.X;
+    int ldsx = s.ldx;
+    if (s.S) {
+        TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.S, s.lds, s.X, s.ldx, 0.0, b.T, n, b.gw));
+        SX = b.T;
+        ldsx = n;
+    }
+    std::memcpy(s.h_lam(), s.lambda, sizeof(double) * m);
+    TRY(hipMemcpyAsync(b.lam, s.h_lam(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    TRY(launch_residual_norms(st, n, m, b.HY, n, SX, ldsx, b.lam, b.r));
+    TRY(hipMemcpyAsync(s.h_res(), b.r, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    mark(s, PH_BACK, st, false);
+    return CHFSI_SUCCESS;
+}
+
+static chfsi_status final_results(chfsi_handle h, SolveState& s)
+{
+    TRY(hipStreamSynchronize(h->stream));
+    for (int j = 0; j < s.m; ++j) s.resid[j] = s.h_res()[j] / s.norm_a;
+    s.finalized = true;
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status st_final_complete(chfsi_handle h, SolveState& s)
+{
+    TRYS(final_results(h, s));
+    s.want_final = false;
+    int bad = -1;
+    for (int j = 0; j < s.nev; ++j)
+        if (!(s.resid[j] <= s.p.tol)) { bad = j; break; }
+    if (bad < 0) {
+        s.status = CHFSI_SUCCESS;
+        s.done = true;
+        return CHFSI_SUCCESS;
+    }
+    // a locked pair failed the verification in generalized coordinates: unlock from there on
+    s.nlocked = bad;
+    for (int j = bad; j < s.m; ++j) s.deg[j] = s.p.deg;
+    return CHFSI_SUCCESS;
+}
+
+void st_finish(chfsi_handle h, SolveState& s, chfsi_stats& stt)
+{
+    if (s.status == CHFSI_ERR_NO_CONVERGENCE && !s.finalized && s.hd) {
+        if (st_final_enqueue(h, s) != CHFSI_SUCCESS || final_results(h, s) != CHFSI_SUCCESS)
+            s.status = CHFSI_ERR_DEVICE;
+    }
+    stt.loops = s.loops;
+    stt.nlocked = std::min(s.nlocked, s.nev);
+    stt.filtered_vectors = s.filtered;
+    stt.matvecs = s.matvecs;
+    stt.filter_flops = s.flops;
+    stt.mu1 = s.mu1; stt.a = s.a; stt.b = s.bb;
+    stt.norm_a = s.norm_a;
+    stt.lanczos_steps = s.k;
+    stt.precision_switches = s.switches;
+    stt.t_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - s.t0).count();
+    stt.status = s.status;
+}
+
+static void store_trace(chfsi_handle h, const SolveState& s)
+{
+    h->trace.clear();
+    for (auto& r : s.trace) {
+        const double row[CHFSI_TRACE_COLS] = {(double)r.loop, (double)r.col, r.t, r.lr, r.a, r.b,
+                                              (double)r.d_prev, (double)r.d, r.r_after, r.thr};
+        h->trace.insert(h->trace.end(), row, row + CHFSI_TRACE_COLS);
+    }
+}
+
+chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* X, int ldx,
+                        int x_is_guess, double* lambda, double* resid, const chfsi_params& p, chfsi_stats& stt)
+{
+    hipStream_t st = h->stream;
+    SolveState s;
+    TRYS(st_define(s, n, A, lda, S, lds, X, ldx, x_is_guess, lambda, resid, p));
+    TRYS(st_setup(h, s, h->ws, h->pin));
     PhaseTimer& tm = h->timer;
     {
         double reset[NPHASE];
         tm.collect(reset);
         (void)h->ktimer.collect(nullptr);
     }
-    auto t0 = std::chrono::steady_clock::now();
+    s.tm = &tm;
     tm.mark(PH_TOTAL, st, true);
-
-    // --- reduction to standard form (Section 3.2)
-    tm.mark(PH_REDUCE, st, true);
-    const zd* H = A;
-    int ldh = lda;
-    if (S) {
-        TRYS(step_reduce(h, n, A, lda, S, lds, b.H, b.L, b.info));
-        H = b.H;
-        ldh = n;
+    chfsi_status rc = st_init_enqueue(h, s);
+    if (rc == CHFSI_SUCCESS) rc = st_init_complete(h, s);
+    if (rc != CHFSI_SUCCESS) {
+        (void)hipStreamSynchronize(st);
+        return rc;
     }
-    TRY(launch_max_colnorm(st, n, A, lda, b.dsc));
-    double hs[2] = {0, 1};
-    TRY(hipMemcpyAsync(&hs[0], b.dsc, sizeof(double), hipMemcpyDeviceToHost, st));
-    if (S) {
-        TRY(launch_max_rowsum_abs(st, n, S, lds, b.dsc));
-        TRY(hipMemcpyAsync(&hs[1], b.dsc, sizeof(double), hipMemcpyDeviceToHost, st));
-    }
-    if (prec == CHFSI_FP32) TRY(launch_z2c(st, n, n, H, ldh, b.Hf, n));
-    if (prec == CHFSI_BF16X3 || prec == CHFSI_BF16X6)
-        TRY(launch_split_h_bf16(st, n, H, ldh, b.Hb, n, prec == CHFSI_BF16X3 ? 2 : 3));
-    // starting block in standard coordinates
-    if (x_is_guess) {
-        if (S) TRY(launch_zgemm(st, OP_C, OP_N, n, m, n, 1.0, b.L, n, X, ldx, 0.0, b.V, n, b.gw));
-        else TRY(launch_zlacpy(st, n, m, X, ldx, b.V, n));
-    } else {
-        TRY(launch_philox_block(st, p.seed, 1, n, m, b.V, n));
-    }
-    TRY(hipStreamSynchronize(st));
-    tm.mark(PH_REDUCE, st, false);
-    const double norm_a = hs[0], s_inf = hs[1];
-    if (!std::isfinite(norm_a) || !std::isfinite(s_inf) || !(norm_a > 0)) return CHFSI_ERR_NUMERIC;
-    const double thr = p.tol * norm_a / std::sqrt(s_inf);
-    stt.norm_a = norm_a;
-
-    // --- Lanczos bounds
-    tm.mark(PH_LANCZOS, st, true);
-    std::vector<double> lth, lz;
-    double beta_k = 0;
-    int kk = 0;
-    TRYS(step_lanczos(h, n, H, ldh, k, p.seed, b.LV, b.lw, b.lc, b.lcoef, lth, lz, beta_k, kk));
-    tm.mark(PH_LANCZOS, st, false);
-    stt.lanczos_steps = kk;
-    double bb = lth[kk - 1] + beta_k, mu1 = lth[0], a = lth[kk - 1];
-    {
-        const double frac = (double)m / n;
-        double cum = 0;
-        for (int j = 0; j < kk; ++j) {
-            cum += lz[j];
-            if (cum >= frac) { a = lth[j]; break; }
+    while (!s.done && s.loops < p.max_loops) {
+        rc = st_filter(h, s);
+        if (rc == CHFSI_SUCCESS) rc = st_loop_enqueue(h, s);
+        if (rc == CHFSI_SUCCESS) rc = st_loop_complete(h, s);
+        if (rc == CHFSI_SUCCESS && s.want_final) {
+            rc = st_final_enqueue(h, s);
+            if (rc == CHFSI_SUCCESS) rc = st_final_complete(h, s);
         }
-        if (!(a > mu1) || !(a < bb)) a = 0.5 * (mu1 + bb);
+        if (rc == CHFSI_ERR_NUMERIC) { s.status = rc; break; }
+        if (rc != CHFSI_SUCCESS) { (void)hipStreamSynchronize(st); return rc; }
     }
-    if (p.have_bounds) {
-        mu1 = p.mu1;
-        a = p.a;
-        if (!(a > mu1) || !(a < bb)) a = 0.5 * (mu1 + bb);
-    }
-
-    // --- inner loop of Algorithm 1
-    std::vector<int> deg(m, p.deg), lowp(m, prec != CHFSI_FP64 ? 1 : 0);
-    std::vector<int> deg_used(m, p.deg);
-    std::vector<double> hth(m), hr(m), rprev(m, -1.0), rho(m);
-    std::vector<int> last_row(m, -1);
-    std::vector<TraceRow> trace;
-    int nlocked = 0, loops = 0;
-    chfsi_status status = CHFSI_ERR_NO_CONVERGENCE;
-    double flops = 0;
-    long long matvecs = 0, filtered = 0;
-    int switches = 0;
-    double sw_rel = p.switch_residual > 0 ? p.switch_residual
-                    : (prec == CHFSI_BF16X3 ? 1e-3 : 1e-5);
-    const double sw_thr = sw_rel * norm_a;
-
-    for (int it = 0; it < p.max_loops; ++it) {
-        const int ma = m - nlocked;
-        zd* Ya = b.V + (size_t)nlocked * n;
-        loops = it + 1;
-        filtered += ma;
-
-        tm.mark(PH_FILTER, st, true);
-        std::vector<int> dact(deg.begin() + nlocked, deg.end()), lact(lowp.begin() + nlocked, lowp.end());
-        TRYS(run_filter(h, b, n, H, ldh, prec, ma, Ya, n, dact, lact, a, bb, mu1, flops, matvecs));
-        tm.mark(PH_FILTER, st, false);
-
-        tm.mark(PH_QR, st, true);
-        TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, st));
-        TRYS(step_orthonormalize(h, n, ma, Ya, n, nlocked, b.V, n, b.G, b.Cm, b.dsc, b.info, b.gw));
-        tm.mark(PH_QR, st, false);
-
-        tm.mark(PH_RR, st, true);
-        TRYS(step_rayleigh_ritz(h, n, H, ldh, ma, Ya, n, b.HY, b.T, b.G, b.theta, b.E, b.r, b.info + 4, b.gw, &tm));
-        tm.mark(PH_RR, st, false);
-
-        tm.mark(PH_LOCK, st, true);
-        int hinfo[8];
-        TRY(hipMemcpyAsync(hth.data(), b.theta, sizeof(double) * ma, hipMemcpyDeviceToHost, st));
-        TRY(hipMemcpyAsync(hr.data(), b.r, sizeof(double) * ma, hipMemcpyDeviceToHost, st));
-        TRY(hipMemcpyAsync(hinfo, b.info, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
-        TRY(hipStreamSynchronize(st));
-        for (int j = 0; j < 8; ++j)
-            if (hinfo[j] != 0) { status = CHFSI_ERR_NUMERIC; break; }
-        for (int j = 0; j < ma; ++j)
-            if (!std::isfinite(hth[j]) || !std::isfinite(hr[j])) status = CHFSI_ERR_NUMERIC;
-        if (status == CHFSI_ERR_NUMERIC) { tm.mark(PH_LOCK, st, false); break; }
-
-        for (int j = 0; j < ma; ++j) deg_used[nlocked + j] = deg[nlocked + j];   // degrees of this loop
-        // trace: close the rows of the previous loop, open rows for this one
-        if (p.trace) {
-            for (int j = 0; j < ma; ++j) {
-                const int pos = nlocked + j;
-                if (last_row[pos] >= 0) trace[last_row[pos]].r_after = hr[j];
-            }
-        }
-        int cnt = 0;
-        while (cnt < nev - nlocked && hr[cnt] <= thr) ++cnt;
-        for (int j = 0; j < ma; ++j) { lambda[nlocked + j] = hth[j]; resid[nlocked + j] = hr[j]; }
-
-        // bounds for the next filter
-        const double a_new = hth[ma - 1];
-        const double mu1_new = std::min(mu1, hth[0]);
-        // per-column degree and precision for the next loop (absolute positions)
-        const int nl2 = nlocked + cnt;
-        for (int j = cnt; j < ma; ++j) {
-            const int pos = nlocked + j;
-            if (lowp[pos]) {
-                const bool stagnated = rprev[pos] > 0 && hr[j] > 0.1 * rprev[pos];
-                if (hr[j] <= sw_thr || stagnated) { lowp[pos] = 0; ++switches; }
-            }
-        }
-        a = a_new;
-        mu1 = mu1_new;
-        if (!(a > mu1)) a = 0.5 * (mu1 + bb);
-        if (p.degree_policy == CHFSI_DEG_ANALYTIC) {
-            for (int j = cnt; j < ma; ++j)
-                deg[nlocked + j] = analytic_degree(hth[j], hr[j], a, bb, thr, p.deg_min, p.deg_max);
-        } else if (p.degree_policy == CHFSI_DEG_RANDOM) {
-            for (int j = cnt; j < ma; ++j)
-                deg[nlocked + j] = random_degree(p.seed, it, nlocked + j, p.deg_min, p.deg_max);
-        } else if (p.degree_policy == CHFSI_DEG_LEARNED) {
-            TRYS(learned_degrees(h, ma - cnt, b.theta + cnt, b.r + cnt, a, bb, mu1, thr,
-                                 std::vector<int>(deg.begin() + nl2, deg.end()), b.feat, b.dpred, b.iperm,
-                                 p.deg_min, p.deg_max, deg.data() + nl2,
-                                 [&](int j) { return analytic_degree(hth[cnt + j], hr[cnt + j], a, bb, thr,
-                                                                     p.deg_min, p.deg_max); }));
-        }
-        if (p.trace) {
-            const double c2 = 0.5 * (a + bb), e2 = 0.5 * (bb - a);
-            for (int j = cnt; j < ma; ++j) {
-                const int pos = nlocked + j;
-                TraceRow row;
-                row.loop = it; row.col = pos; row.t = (hth[j] - c2) / e2;
-                row.lr = std::log10(std::max(hr[j], 1e-300)); row.a = (a - mu1) / (bb - mu1);
-                row.b = (bb - mu1) / (std::fabs(mu1) + std::fabs(bb)); row.d_prev = deg_used[pos];
-                row.d = deg[pos]; row.r_after = -1.0;
-                row.thr = thr;
-                last_row[pos] = (int)trace.size();
-                trace.push_back(row);
-            }
-        }
-        for (int j = 0; j < ma; ++j) rprev[nlocked + j] = hr[j];
-        nlocked = nl2;
-        tm.mark(PH_LOCK, st, false);
-
-        if (nlocked >= nev) {
-            tm.mark(PH_BACK, st, true);
-            TRYS(finalize(h, b, n, m, A, lda, S, lds, X, ldx, lambda, norm_a, resid));
-            tm.mark(PH_BACK, st, false);
-            int bad = -1;
-            for (int j = 0; j < nev; ++j)
-                if (!(resid[j] <= p.tol)) { bad = j; break; }
-            if (bad < 0) { status = CHFSI_SUCCESS; break; }
-            nlocked = bad;
-            for (int j = bad; j < m; ++j) deg[j] = p.deg;
-        }
-    }
-    if (status == CHFSI_ERR_NO_CONVERGENCE) {
-        tm.mark(PH_BACK, st, true);
-        TRYS(finalize(h, b, n, m, A, lda, S, lds, X, ldx, lambda, norm_a, resid));
-        tm.mark(PH_BACK, st, false);
-    }
+    st_finish(h, s, stt);
     tm.mark(PH_TOTAL, st, false);
     TRY(hipStreamSynchronize(st));
     double ph[NPHASE];
@@ -431,32 +557,15 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
     stt.t_reduce = ph[PH_REDUCE]; stt.t_lanczos = ph[PH_LANCZOS]; stt.t_filter = ph[PH_FILTER];
     stt.t_qr = ph[PH_QR]; stt.t_rr = ph[PH_RR]; stt.t_resid = ph[PH_RESID]; stt.t_lock = ph[PH_LOCK];
     stt.t_back = ph[PH_BACK];
-    stt.t_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    stt.loops = loops;
-    stt.nlocked = std::min(nlocked, nev);
-    stt.filtered_vectors = filtered;
-    stt.matvecs = matvecs;
-    stt.filter_flops = flops;
-    stt.mu1 = mu1; stt.a = a; stt.b = bb;
-    stt.precision_switches = switches;
     stt.t_filter_kernels = h->ktimer.collect(&stt.filter_launches, &stt.t_filter_steps);
     h->last_kernel_ms = stt.t_filter_kernels;
     h->last_kernel_launches = stt.filter_launches;
-    stt.status = status;
-    if (p.trace) {
-        h->trace.clear();
-        for (auto& r : trace) {
-            const double row[CHFSI_TRACE_COLS] = {(double)r.loop, (double)r.col, r.t, r.lr, r.a, r.b,
-                                                  (double)r.d_prev, (double)r.d, r.r_after, r.thr};
-            h->trace.insert(h->trace.end(), row, row + CHFSI_TRACE_COLS);
-        }
-    }
-    return status;
+    if (p.trace) store_trace(h, s);
+    return s.status;
 }
 
-}  // namespace
-
 extern "C" {
+
 
 chfsi_status chfsi_solve(chfsi_handle h, int n, const void* A, int lda, const void* S, int lds, void* X, int ldx,
                          int x_is_guess, double* lambda, double* resid, const chfsi_params* p, chfsi_stats* stats)
@@ -472,30 +581,6 @@ chfsi_status chfsi_solve(chfsi_handle h, int n, const void* A, int lda, const vo
     stt.status = s;
     if (stats) *stats = stt;
     return s;
-}
-
-chfsi_status chfsi_solve_batched(chfsi_handle h, int count, const chfsi_problem* probs, const chfsi_params* p,
-                                 chfsi_stats* stats)
-{
-    if (!h || count < 0 || (count > 0 && !probs)) return CHFSI_ERR_ARG;
-    if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
-    chfsi_params base;
-    if (p) base = *p; else chfsi_default_params(&base);
-    chfsi_status first = CHFSI_SUCCESS;
-    for (int k = 0; k < count; ++k) {
-        const chfsi_problem& q = probs[k];
-        chfsi_params pk = base;
-        pk.nev = q.nev;
-        pk.nex = q.nex;
-        chfsi_stats stt;
-        std::memset(&stt, 0, sizeof(stt));
-        chfsi_status s = solve_impl(h, q.n, (const zd*)q.A, q.lda, (const zd*)q.S, q.lds, (zd*)q.X, q.ldx,
-                                    q.x_is_guess, q.lambda, q.resid, pk, stt);
-        stt.status = s;
-        if (stats) stats[k] = stt;
-        if (s != CHFSI_SUCCESS && first == CHFSI_SUCCESS) first = s;
-    }
-    return first;
 }
 
 chfsi_status chfsi_filter(chfsi_handle h, int n, const void* Hv, int ldh, void* Yv, int ldy, int m, const int* deg,
@@ -606,7 +691,8 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_handle h, int n, const void* H, int ldh, 
     SolveBufs b;
     TRYS(prepare(h, b, n, m, 1, false, CHFSI_FP64));
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, h->stream));
-    TRYS(step_rayleigh_ritz(h, n, (const zd*)H, ldh, m, (zd*)Y, ldy, b.HY, b.T, b.G, b.theta, b.E, b.r, b.info,
+    std::vector<double> ehost((size_t)eig_padded_order(m) + 1);
+    TRYS(step_rayleigh_ritz(h, n, (const zd*)H, ldh, m, (zd*)Y, ldy, b.HY, b.T, b.G, b.theta, b.r, b.eigw, ehost.data(),
                             b.gw, nullptr));
     int info = 0;
     TRY(hipMemcpyAsync(theta, b.theta, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));

@@ -1,0 +1,560 @@
+// Batched solver: the k-point problems of one self-consistent cycle (Section 2.1: one generalized
+// eigenproblem per k-point, all independent, of different orders) advance through Algorithm 1 in
+// lockstep loops.  Each filter step of all unconverged problems is ONE persistent launch over a
+// work list of output tiles of every problem; the steps of a loop are captured once in a HIP graph
+// and replayed, their work lists read from a device table that is refreshed before each replay.
+// The small dense steps (QR, Rayleigh-Ritz, locking, verification) stay per problem, spread over
+// several streams so that those of different problems overlap on the device.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "chfsi.h"
+#include "common.h"
+#include "driver.h"
+#include "gemm_tile.h"
+#include "state.h"
+
+namespace {
+
+constexpr int BATCH_MAXP = 64;   // problems per persistent launch (larger batches are chunked)
+constexpr int NUM_XCD = 8;       // gfx950: workgroup w runs on XCD w % 8
+constexpr int MAX_LANES = 8;     // streams for the per-problem dense steps (default 4)
+
+// One problem of a filter step: Yo = alpha (H Yk - shift Yk) + beta Yp on columns [0, w).
+struct BatchProb {
+    const zd* H;
+    const zd* Yk;
+    const zd* Yp;
+    zd* Yo;
+    int n, ldh, ldk, ldp, ldo, w;
+    double alpha, beta, shift;
+};
+
+struct BatchStep {
+    int nprob, pad[3];
+    BatchProb p[BATCH_MAXP];
+};
+
+using chfsi_tile::TileShape;
+
+// Persistent filter step over every problem of `step`.  The row tiles of each problem are cut
+// into NUM_XCD equal ranges, range x going to the workgroups on XCD x, so every XCD gets an equal
+// share of every problem (balanced although K = n differs between problems) and the tiles that
+// share rows of H run on one XCD, close in time (neighbouring workgroups take neighbouring column
+// tiles of one row panel), where they share its L2.  gridDim.x is a multiple of NUM_XCD.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_filter_batched(const BatchStep* __restrict__ step)
+{
+    typedef TileShape<double, BM, BN> S;
+    typedef d4 ACC;
+    __shared__ zd As[2 * S::AS_ELEMS];
+    __shared__ zd Bs[2 * S::BS_ELEMS];
+    __shared__ int pre[BATCH_MAXP + 1], r0s[BATCH_MAXP], tns[BATCH_MAXP];
+    const int x = blockIdx.x % NUM_XCD, q = blockIdx.x / NUM_XCD, Q = gridDim.x / NUM_XCD;
+    const int np = min(step->nprob, BATCH_MAXP);
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int p = 0; p < np; ++p) {
+            const int n = step->p[p].n, w = step->p[p].w;
+            const int tm = (n + BM - 1) / BM, tn = (w + BN - 1) / BN;
+            const int r0 = (int)((long)x * tm / NUM_XCD), r1 = (int)((long)(x + 1) * tm / NUM_XCD);
+            pre[p] = acc;
+            r0s[p] = r0;
+            tns[p] = tn;
+            acc += (r1 - r0) * tn;
+        }
+        pre[np] = acc;
+    }
+    __syncthreads();
+    const int total = pre[np];
+    int p = 0;
+    for (int f = q; f < total; f += Q) {
+        while (pre[p + 1] <= f) ++p;
+        const BatchProb b = step->p[p];
+        const int loc = f - pre[p];
+        const int i0 = (r0s[p] + loc / tns[p]) * BM, j0 = (loc % tns[p]) * BN;
+        ACC accr[S::MI][S::NJ], acci[S::MI][S::NJ];
+        chfsi_tile::tile_mainloop<double, OP_N, OP_N, BM, BN>(b.H, b.ldh, b.n, b.Yk, b.ldk, b.w, i0, j0, 0, b.n, As,
+                                                              Bs, accr, acci);
+#pragma unroll
+        for (int bi = 0; bi < S::MI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < S::NJ; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = chfsi_tile::tile_row<double, BM, BN>(i0, bi);
+                    const int j = chfsi_tile::tile_col<double, BM, BN>(j0, bj, r);
+                    if (i < b.n && j < b.w) {
+                        const zd yk = b.Yk[(size_t)i + (size_t)j * b.ldk];
+                        const zd yp = b.Yp[(size_t)i + (size_t)j * b.ldp];
+                        zd o;
+                        o.x = b.alpha * (accr[bi][bj][r] - b.shift * yk.x) + b.beta * yp.x;
+                        o.y = b.alpha * (acci[bi][bj][r] - b.shift * yk.y) + b.beta * yp.y;
+                        b.Yo[(size_t)i + (size_t)j * b.ldo] = o;
+                    }
+                }
+        __syncthreads();   // the next tile refills As/Bs
+    }
+}
+
+template <int BM, int BN> const void* kernel_of() { return (const void*)k_filter_batched<BM, BN>; }
+
+const void* batched_kernel(int bm, int bn)
+{
+    if (bm == 64 && bn == 64) return kernel_of<64, 64>();
+    if (bm == 64 && bn == 32) return kernel_of<64, 32>();
+    if (bm == 32 && bn == 64) return kernel_of<32, 64>();
+    return kernel_of<32, 32>();
+}
+
+// persistent grid: every workgroup resident at once (CUs x occupancy), a multiple of NUM_XCD
+int batched_grid(int device, int bm, int bn)
+{
+    int cus = 0, occ = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_kernel(bm, bn), 256, 0) != hipSuccess || occ <= 0)
+        occ = 1;
+    int g = cus * occ;
+    g -= g % NUM_XCD;
+    return std::max(g, NUM_XCD);
+}
+
+int launch_batched(hipStream_t s, const BatchStep* step, int bm, int bn, int grid)
+{
+    if (bm == 64 && bn == 64) hipLaunchKernelGGL((k_filter_batched<64, 64>), dim3(grid), dim3(256), 0, s, step);
+    else if (bm == 64 && bn == 32) hipLaunchKernelGGL((k_filter_batched<64, 32>), dim3(grid), dim3(256), 0, s, step);
+    else if (bm == 32 && bn == 64) hipLaunchKernelGGL((k_filter_batched<32, 64>), dim3(grid), dim3(256), 0, s, step);
+    else hipLaunchKernelGGL((k_filter_batched<32, 32>), dim3(grid), dim3(256), 0, s, step);
+    return (int)hipGetLastError();
+}
+
+#define TRY(x)                                 \
+    do {                                       \
+        int rc_ = (int)(x);                    \
+        if (rc_ != 0) return CHFSI_ERR_DEVICE; \
+    } while (0)
+#define TRYS(x)                                \
+    do {                                       \
+        chfsi_status s_ = (x);                 \
+        if (s_ != CHFSI_SUCCESS) return s_;    \
+    } while (0)
+
+chfsi_status ensure_lanes(chfsi_handle h)
+{
+    while ((int)h->lanes.size() < MAX_LANES) {
+        Lane l;
+        if (hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking) != hipSuccess) return CHFSI_ERR_DEVICE;
+        if (hipEventCreateWithFlags(&l.ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(l.st);
+            return CHFSI_ERR_DEVICE;
+        }
+        if (rocblas_create_handle(&l.rb) != rocblas_status_success) {
+            (void)hipEventDestroy(l.ev);
+            (void)hipStreamDestroy(l.st);
+            return CHFSI_ERR_DEVICE;
+        }
+        rocblas_set_stream(l.rb, l.st);
+        rocblas_set_pointer_mode(l.rb, rocblas_pointer_mode_host);
+        h->lanes.push_back(l);
+    }
+    for (auto& e : h->bev)
+        if (!e && hipEventCreate(&e) != hipSuccess) return CHFSI_ERR_DEVICE;
+    if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return CHFSI_ERR_DEVICE;
+    return CHFSI_SUCCESS;
+}
+
+void sync_lanes(chfsi_handle h)
+{
+    for (auto& l : h->lanes) (void)hipStreamSynchronize(l.st);
+}
+
+// Makes the step tables hold `steps` steps; a reallocation invalidates the captured graphs.
+chfsi_status ensure_table(chfsi_handle h, int steps)
+{
+    const size_t need = sizeof(BatchStep) * (size_t)std::max(steps, 32);
+    if (!h->btable_host.reserve(need)) return CHFSI_ERR_ALLOC;
+    if (need <= h->btable_cap) return CHFSI_SUCCESS;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& g : h->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    h->graphs.clear();
+    if (h->btable) (void)hipFree(h->btable);
+    h->btable = nullptr;
+    h->btable_cap = 0;
+    if (hipMalloc(&h->btable, need) != hipSuccess) { h->btable = nullptr; return CHFSI_ERR_ALLOC; }
+    h->btable_cap = need;
+    return CHFSI_SUCCESS;
+}
+
+// The graph of `steps` persistent launches reading step tables 0 .. steps-1 (captured on first use).
+chfsi_status get_graph(chfsi_handle h, int steps, int bm, int bn, int grid, hipGraphExec_t& exec)
+{
+    for (auto& g : h->graphs)
+        if (g.steps == steps && g.bm == bm && g.bn == bn && g.grid == grid && g.table == h->btable) {
+            exec = g.exec;
+            return CHFSI_SUCCESS;
+        }
+    BatchGraph g;
+    g.steps = steps; g.bm = bm; g.bn = bn; g.grid = grid; g.table = h->btable;
+    hipStream_t st = h->cap_stream;   // nothing else is ever enqueued on it
+    TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = 0;
+    for (int k = 0; k < steps && rc == 0; ++k)
+        rc = launch_batched(st, (const BatchStep*)h->btable + k, bm, bn, grid);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rc != 0 || ec != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return CHFSI_ERR_DEVICE;
+    }
+    if (hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return CHFSI_ERR_DEVICE;
+    }
+    g.graph = graph;
+    h->graphs.push_back(g);
+    exec = g.exec;
+    return CHFSI_SUCCESS;
+}
+
+// binds the handle's stream / rocBLAS handle to a lane for the per-problem steps; restores them
+struct LaneBinding {
+    chfsi_handle h;
+    hipStream_t st0;
+    rocblas_handle rb0;
+    explicit LaneBinding(chfsi_handle hh) : h(hh), st0(hh->stream), rb0(hh->rb) {}
+    void use(int lane) { h->stream = h->lanes[lane].st; h->rb = h->lanes[lane].rb; }
+    void main() { h->stream = st0; h->rb = rb0; }
+    ~LaneBinding() { main(); }
+};
+
+struct Slot {
+    SolveState s;
+    int lane = 0;
+    std::vector<int> dsorted;   // degrees of the active columns in filter order
+};
+
+// One loop's filter of every slot in `act`: tables, one graph replay (or dmax launches), and the
+// copy-back of columns whose degree is odd (their result sits in T).
+chfsi_status batched_filter(chfsi_handle h, std::vector<Slot>& sl, const std::vector<int>& act)
+{
+    hipStream_t st = h->stream;
+    int dmax = 0;
+    for (int i : act) dmax = std::max(dmax, sl[i].dsorted.empty() ? 0 : sl[i].dsorted[0]);
+    for (int i : act)
+        if (sl[i].dsorted.empty()) sl[i].dsorted.push_back(0);   // no active column: no step
+    if (dmax <= 0) return CHFSI_SUCCESS;
+    TRYS(ensure_table(h, dmax));
+    BatchStep* tab = (BatchStep*)h->btable_host.p;
+    std::vector<std::vector<FilterStep>> coef(act.size());
+    for (size_t u = 0; u < act.size(); ++u) {
+        const SolveState& s = sl[act[u]].s;
+        filter_coefficients(std::max(1, sl[act[u]].dsorted[0]), s.a, s.bb, s.mu1, coef[u]);
+    }
+    for (int k = 1; k <= dmax; ++k) {
+        BatchStep& t = tab[k - 1];
+        t.nprob = 0;
+        for (size_t u = 0; u < act.size(); ++u) {
+            Slot& z = sl[act[u]];
+            SolveState& s = z.s;
+            const int ma = s.ma();
+            int w = 0;
+            while (w < ma && z.dsorted[w] >= k) ++w;
+            if (w == 0) continue;
+            // Y_k lives in Ya when k is even, in T when k is odd; Y_{k-1} in the other buffer
+            zd* Ya = s.Ya();
+            zd* T = s.b.T;
+            BatchProb& bp = t.p[t.nprob++];
+            bp.H = s.H;
+            bp.ldh = s.ldh;
+            bp.n = s.n;
+            bp.w = w;
+            bp.Yk = (k % 2 == 1) ? Ya : T;
+            bp.Yo = (k % 2 == 1) ? T : Ya;
+            bp.Yp = (k == 1) ? bp.Yk : bp.Yo;   // beta = 0 on step 1: any finite input
+            bp.ldk = bp.ldp = bp.ldo = s.n;
+            const FilterStep& fs = coef[u][k - 1];
+            bp.alpha = fs.alpha;
+            bp.beta = fs.beta;
+            bp.shift = fs.shift;
+            s.flops += 8.0 * (double)s.n * (double)s.n * (double)w;
+            s.matvecs += w;
+            h->batch_flops += 8.0 * (double)s.n * (double)s.n * (double)w;
+        }
+    }
+    const int bm = h->batch_bm, bn = h->batch_bn;
+    const int grid = batched_grid(h->device, bm, bn);
+    TRY(hipMemcpyAsync(h->btable, tab, sizeof(BatchStep) * dmax, hipMemcpyHostToDevice, st));
+    TRY(hipEventRecord(h->bev[0], st));
+    if (h->batch_use_graph) {
+        hipGraphExec_t exec = nullptr;
+        TRYS(get_graph(h, dmax, bm, bn, grid, exec));
+        TRY(hipGraphLaunch(exec, st));
+        h->batch_graph_launches += 1;
+    } else {
+        for (int k = 0; k < dmax; ++k) TRY(launch_batched(st, (const BatchStep*)h->btable + k, bm, bn, grid));
+    }
+    h->batch_kernel_launches += dmax;
+    TRY(hipEventRecord(h->bev[1], st));
+    // columns whose degree is odd finished in T
+    for (int i : act) {
+        Slot& z = sl[i];
+        SolveState& s = z.s;
+        const int ma = s.ma();
+        int* flag = s.hi + 32 + s.m;   // pinned staging [m]
+        bool any = false;
+        for (int j = 0; j < ma; ++j) { flag[j] = z.dsorted[j] % 2; any |= flag[j] != 0; }
+        if (!any) continue;
+        TRY(hipMemcpyAsync(s.b.flag, flag, sizeof(int) * ma, hipMemcpyHostToDevice, st));
+        TRY(launch_copy_cols_flag(st, s.n, ma, s.b.T, s.n, s.Ya(), s.n, s.b.flag));
+    }
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status fail(Slot& z, chfsi_status rc)
+{
+    z.s.status = rc;
+    z.s.done = true;
+    return rc;
+}
+
+chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, const chfsi_params& base,
+                         chfsi_stats* stats, int first_index)
+{
+    std::vector<Slot> sl(count);
+    std::vector<chfsi_status> rcs(count, CHFSI_SUCCESS);
+    if ((int)h->barena.size() < first_index + count) {
+        h->barena.resize(first_index + count);
+        h->bpin.resize(first_index + count);
+    }
+    LaneBinding bind(h);
+    auto t0 = std::chrono::steady_clock::now();
+    // set-up and initial phases (reduction, Lanczos) of every problem
+    for (int i = 0; i < count; ++i) {
+        const chfsi_problem& q = probs[i];
+        chfsi_params pk = base;
+        pk.nev = q.nev;
+        pk.nex = q.nex;
+        Slot& z = sl[i];
+        z.lane = i % h->batch_lanes;
+        bind.use(z.lane);
+        chfsi_status rc = st_define(z.s, q.n, (const zd*)q.A, q.lda, (const zd*)q.S, q.lds, (zd*)q.X, q.ldx,
+                                    q.x_is_guess, q.lambda, q.resid, pk);
+        if (rc == CHFSI_SUCCESS) rc = st_setup(h, z.s, h->barena[first_index + i], h->bpin[first_index + i]);
+        if (rc == CHFSI_SUCCESS) rc = st_init_enqueue(h, z.s);
+        if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+    }
+    for (int i = 0; i < count; ++i) {
+        Slot& z = sl[i];
+        if (z.s.done) continue;
+        bind.use(z.lane);
+        const chfsi_status rc = st_init_complete(h, z.s);
+        if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+    }
+    for (;;) {
+        std::vector<int> act;
+        for (int i = 0; i < count; ++i)
+            if (!sl[i].s.done && sl[i].s.loops < sl[i].s.p.max_loops) act.push_back(i);
+        if (act.empty()) break;
+        // column order by degree on each problem's lane, then the lanes join the main stream
+        for (int i : act) {
+            bind.use(sl[i].lane);
+            const chfsi_status rc = st_order_columns(h, sl[i].s, sl[i].dsorted);
+            if (rc != CHFSI_SUCCESS) return rc;
+        }
+        bind.main();
+        for (auto& l : h->lanes) {
+            TRY(hipEventRecord(l.ev, l.st));
+            TRY(hipStreamWaitEvent(h->stream, l.ev, 0));
+        }
+        TRYS(batched_filter(h, sl, act));
+        TRY(hipEventRecord(h->bev[2], h->stream));
+        for (auto& l : h->lanes) TRY(hipStreamWaitEvent(l.st, h->bev[2], 0));
+        // QR and Rayleigh-Ritz of every problem, then the host decisions
+        for (int i : act) {
+            bind.use(sl[i].lane);
+            const chfsi_status rc = st_loop_enqueue(h, sl[i].s);
+            if (rc != CHFSI_SUCCESS) rcs[i] = fail(sl[i], rc);
+        }
+        for (int i : act) {
+            Slot& z = sl[i];
+            if (z.s.done) continue;
+            bind.use(z.lane);
+            chfsi_status rc = st_loop_complete(h, z.s);
+            if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(h, z.s);
+            if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+        }
+        for (int i : act) {
+            Slot& z = sl[i];
+            if (z.s.done || !z.s.want_final) continue;
+            bind.use(z.lane);
+            const chfsi_status rc = st_final_complete(h, z.s);
+            if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+        }
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, h->bev[0], h->bev[1]) == hipSuccess) h->batch_filter_ms += ms;
+    }
+    chfsi_status first = CHFSI_SUCCESS;
+    for (int i = 0; i < count; ++i) {
+        Slot& z = sl[i];
+        bind.use(z.lane);
+        chfsi_stats stt;
+        std::memset(&stt, 0, sizeof(stt));
+        if (rcs[i] == CHFSI_SUCCESS || rcs[i] == CHFSI_ERR_NUMERIC) st_finish(h, z.s, stt);
+        else stt.status = rcs[i];
+        const chfsi_status si = rcs[i] == CHFSI_SUCCESS ? z.s.status : rcs[i];
+        stt.status = si;
+        if (stats) stats[i] = stt;
+        if (si != CHFSI_SUCCESS && first == CHFSI_SUCCESS) first = si;
+    }
+    for (auto& l : h->lanes) TRY(hipStreamSynchronize(l.st));
+    const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats)
+        for (int i = 0; i < count; ++i) stats[i].t_total = wall;
+    return first;
+}
+
+}  // namespace
+
+extern "C" {
+
+chfsi_status chfsi_solve_batched(chfsi_handle h, int count, const chfsi_problem* probs, const chfsi_params* p,
+                                 chfsi_stats* stats)
+{
+    if (!h || count < 0 || (count > 0 && !probs)) return CHFSI_ERR_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
+    chfsi_params base;
+    if (p) base = *p; else chfsi_default_params(&base);
+    if (base.filter_precision != CHFSI_FP64) return CHFSI_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        const chfsi_problem& q = probs[i];
+        if (q.n <= 0 || q.nev <= 0 || q.nex < 0 || q.nev + q.nex > q.n) return CHFSI_ERR_ARG;
+    }
+    h->batch_filter_ms = 0;
+    h->batch_flops = 0;
+    h->batch_graph_launches = 0;
+    h->batch_kernel_launches = 0;
+    if (count == 0) return CHFSI_SUCCESS;
+    TRYS(ensure_lanes(h));
+    TRY(hipStreamSynchronize(h->stream));
+    chfsi_status first = CHFSI_SUCCESS;
+    for (int c0 = 0; c0 < count; c0 += BATCH_MAXP) {
+        const int c = std::min(BATCH_MAXP, count - c0);
+        const chfsi_status s = solve_chunk(h, c, probs + c0, base, stats ? stats + c0 : nullptr, c0);
+        sync_lanes(h);
+        if (s != CHFSI_SUCCESS && first == CHFSI_SUCCESS) first = s;
+    }
+    TRY(hipStreamSynchronize(h->stream));
+    return first;
+}
+
+chfsi_status chfsi_set_batched_plan(chfsi_handle h, const chfsi_tile_plan* plan, int use_graph, int lanes)
+{
+    if (!h || lanes < 0 || lanes > MAX_LANES) return CHFSI_ERR_ARG;
+    if (lanes > 0) h->batch_lanes = lanes;
+    if (plan) {
+        if ((plan->bm != 32 && plan->bm != 64) || (plan->bn != 32 && plan->bn != 64)) return CHFSI_ERR_ARG;
+        h->batch_bm = plan->bm;
+        h->batch_bn = plan->bn;
+    }
+    h->batch_use_graph = use_graph != 0;
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_autotune_batched(chfsi_handle h, int count, const chfsi_problem* probs, chfsi_tile_plan* best,
+                                    double* best_ms)
+{
+    if (!h || count <= 0 || count > BATCH_MAXP || !probs) return CHFSI_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        const chfsi_problem& q = probs[i];
+        if (q.n <= 0 || q.nev <= 0 || q.nex < 0 || q.nev + q.nex > q.n || !q.A || !q.X || q.lda < q.n ||
+            q.ldx < q.n)
+            return CHFSI_ERR_ARG;
+    }
+    if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
+    hipStream_t st = h->stream;
+    TRYS(ensure_lanes(h));
+    TRYS(ensure_table(h, 1));
+    // scratch outputs, one n x m block per problem
+    std::vector<size_t> off(count);
+    size_t tot = 0;
+    for (int i = 0; i < count; ++i) {
+        off[i] = tot;
+        tot += (size_t)probs[i].n * (probs[i].nev + probs[i].nex);
+    }
+    zd* out = nullptr;
+    if (hipMalloc((void**)&out, sizeof(zd) * tot) != hipSuccess) return CHFSI_ERR_ALLOC;
+    BatchStep* tab = (BatchStep*)h->btable_host.p;
+    tab->nprob = count;
+    for (int i = 0; i < count; ++i) {
+        const chfsi_problem& q = probs[i];
+        BatchProb& bp = tab->p[i];
+        bp.H = (const zd*)q.A;
+        bp.ldh = q.lda;
+        bp.n = q.n;
+        bp.w = q.nev + q.nex;
+        bp.Yk = (const zd*)q.X;
+        bp.ldk = q.ldx;
+        bp.Yp = (const zd*)q.X;
+        bp.ldp = q.ldx;
+        bp.Yo = out + off[i];
+        bp.ldo = q.n;
+        bp.alpha = 1e-3;
+        bp.beta = -0.5;
+        bp.shift = 0.1;
+    }
+    chfsi_status rc = CHFSI_SUCCESS;
+    if (hipMemcpyAsync(h->btable, tab, sizeof(BatchStep), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = CHFSI_ERR_DEVICE;
+    static const int cand[4][2] = {{64, 64}, {64, 32}, {32, 64}, {32, 32}};
+    double bms = 1e30;
+    int bi = 0;
+    for (int c = 0; c < 4 && rc == CHFSI_SUCCESS; ++c) {
+        const int bm = cand[c][0], bn = cand[c][1];
+        const int grid = batched_grid(h->device, bm, bn);
+        for (int w = 0; w < 2 && rc == CHFSI_SUCCESS; ++w)
+            if (launch_batched(st, (const BatchStep*)h->btable, bm, bn, grid) != 0) rc = CHFSI_ERR_DEVICE;
+        if (rc != CHFSI_SUCCESS) break;
+        (void)hipEventRecord(h->bev[0], st);
+        for (int r = 0; r < 5; ++r)
+            if (launch_batched(st, (const BatchStep*)h->btable, bm, bn, grid) != 0) rc = CHFSI_ERR_DEVICE;
+        (void)hipEventRecord(h->bev[1], st);
+        if (hipEventSynchronize(h->bev[1]) != hipSuccess) rc = CHFSI_ERR_DEVICE;
+        float ms = 0;
+        if (rc == CHFSI_SUCCESS && hipEventElapsedTime(&ms, h->bev[0], h->bev[1]) == hipSuccess && ms / 5 < bms) {
+            bms = ms / 5;
+            bi = c;
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(out);
+    if (rc != CHFSI_SUCCESS) return rc;
+    h->batch_bm = cand[bi][0];
+    h->batch_bn = cand[bi][1];
+    if (best) { best->bm = h->batch_bm; best->bn = h->batch_bn; best->ksplit = 1; best->fused = 0; }
+    if (best_ms) *best_ms = bms;
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_batched_info(chfsi_handle h, double* filter_ms, double* filter_flops, int* graph_launches,
+                                int* kernel_launches)
+{
+    if (!h) return CHFSI_ERR_ARG;
+    if (filter_ms) *filter_ms = h->batch_filter_ms;
+    if (filter_flops) *filter_flops = h->batch_flops;
+    if (graph_launches) *graph_launches = h->batch_graph_launches;
+    if (kernel_launches) *kernel_launches = h->batch_kernel_launches;
+    return CHFSI_SUCCESS;
+}
+
+}  // extern "C"

@@ -99,6 +99,13 @@ int launch_permute_cols(hipStream_t s, int n, int m, const zd* src, int lds, zd*
 int launch_copy_cols_flag(hipStream_t s, int n, int m, const zd* src, int lds, zd* dst, int ldd, const int* flag);
 int launch_copy_cols_flag_c(hipStream_t s, int n, int m, const zf* src, int lds, zf* dst, int ldd, const int* flag);
 
+// ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
+int eig_padded_order(int m);
+size_t eig_work_bytes(int m);
+// G (m x m, device) <- W with G = W diag(theta) W^H, theta ascending (device).  host: at least
+// eig_padded_order(m) + 1 doubles.  Returns hipError_t as int, -1 when the sweeps did not converge.
+int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps);
+
 // ---- degree network (mlp.hip) -------------------------------------------------------------------
 #define MLP_NF 5
 #define MLP_NH 64

@@ -21,6 +21,14 @@ struct Arena {
     void begin(bool measure) { off = 0; measuring = measure; failed = false; }
 };
 
+// Grow-only pinned host buffer (hipHostMalloc), released by chfsi_destroy.
+struct PinBuf {
+    char* p = nullptr;
+    size_t cap = 0;
+    bool reserve(size_t bytes);
+    void release();
+};
+
 enum { PH_REDUCE = 0, PH_LANCZOS, PH_FILTER, PH_QR, PH_RR, PH_RESID, PH_LOCK, PH_BACK, PH_TOTAL, NPHASE };
 
 // hipEvent pairs per phase, summed after the final synchronisation of a solve
@@ -55,6 +63,23 @@ struct KernelTimer {
 
 struct TuneEntry { int prec, n, m; int bm, bn, ksplit, mode; };
 
+// A stream with its own rocBLAS handle: the batched solver binds each problem to one lane so
+// that the small dense steps of different problems overlap on the device.
+struct Lane {
+    hipStream_t st = nullptr;
+    rocblas_handle rb = nullptr;
+    hipEvent_t ev = nullptr;
+};
+
+// A captured filter graph of the batched solver: `steps` persistent launches reading their work
+// lists from a device table (see batched.hip).
+struct BatchGraph {
+    int steps = 0, bm = 0, bn = 0, grid = 0;
+    void* table = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct chfsi_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -70,17 +95,40 @@ struct chfsi_handle_s {
     double last_kernel_ms = 0;     // filter-step launch time of the last solve / filter call
     int last_kernel_launches = 0;
     bool has_model = false;
+    PinBuf pin;                    // pinned staging of single solves
+    // batched solves
+    std::vector<Lane> lanes;
+    std::vector<Arena> barena;     // one device arena per problem
+    std::vector<PinBuf> bpin;      // one pinned staging buffer per problem
+    std::vector<BatchGraph> graphs;
+    hipStream_t cap_stream = nullptr;   // graphs are captured here (never the null stream)
+    void* btable = nullptr;        // device: step tables of the batched filter
+    size_t btable_cap = 0;
+    PinBuf btable_host;
+    int batch_bm = 64, batch_bn = 64;   // tile of the persistent filter kernel
+    double batch_filter_ms = 0, batch_flops = 0;
+    int batch_graph_launches = 0, batch_kernel_launches = 0;
+    bool batch_use_graph = true;   // replay each loop's filter steps as one captured graph
+    int batch_lanes = 4;           // streams the problems of a batch are spread over
+    hipEvent_t bev[3] = {nullptr, nullptr, nullptr};   // filter start / end, lane join
 };
 
 // steps (solver.hip)
 chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, int* info_dev);
+chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
+                                 int* info_dev, int* info_host);
+chfsi_status step_lanczos_enqueue(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed,
+                                  zd* LV, zd* w, zd* c, double* coef_dev, double* hal, double* hbe);
+chfsi_status lanczos_finish(int k, const double* hal, const double* hbe, std::vector<double>& theta,
+                            std::vector<double>& z1sq, double& beta_k, int& k_used);
 chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed, zd* LV, zd* w,
                           zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
                           double& beta_k, int& k_used);
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
                                  zd* G, zd* Cm, double* dsc, int* info_dev, const GemmWs& gw);
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY, zd* T,
-                                zd* G, double* theta_dev, double* E, double* r_dev, int* info_dev, const GemmWs& gw, PhaseTimer* tm);
+                                zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
+                                const GemmWs& gw, PhaseTimer* tm);
 void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps);
 chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
                         const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);

@@ -1,0 +1,394 @@
+// Hermitian eigensolver for the Rayleigh quotient G = Y^H H Y of the Rayleigh-Ritz step
+// (Algorithm 1), sized for blocks of a few hundred columns: parallel two-sided block Jacobi.
+//
+// G (m x m) is embedded in an M x M matrix, M = m rounded up to a multiple of 32, with the padded
+// diagonal set to 1e30 and zero coupling (padded indices are never rotated and sort last).  The
+// M / 16 blocks of 16 indices meet in round-robin order: a sweep has nb - 1 rounds (nb = M / 16),
+// and in each round every pair of blocks forms a 32 x 32 Hermitian subproblem.
+//   k_eig_inner  one workgroup per block pair runs one cyclic Jacobi sweep on its subproblem in
+//                LDS (complex 2 x 2 rotations, round-robin over the 32 indices; a round in which
+//                no pair exceeds the threshold is skipped) and writes the accumulated rotation J.
+//                A single inner sweep per round costs at most one extra outer sweep and halves or
+//                better the inner work.
+//   k_eig_apply  G <- J^H G J and W <- W J, one workgroup per 32 x 32 tile; J is block
+//                diagonal in block-pair order, so every tile is touched by exactly one workgroup.
+// After each sweep the largest off-diagonal modulus and the diagonal are copied to the host, which
+// stops once the off-diagonal is below 5e-14 of the matrix scale (rotations are skipped below
+// 1e-14 of it: the Ritz vectors are then exact to residuals far below the locking threshold).  A
+// Rayleigh quotient of nearly converged Ritz vectors is nearly diagonal (its off-diagonal entries
+// are bounded by the residual norms), so the later loops of a solve need two or three sweeps.
+//
+// Complex rotation of the pair (p, q) with a = G_pp, b = G_qq (real) and g = G_pq = |g| e^{i phi}:
+// the real symmetric Schur rotation of [[a, |g|], [|g|, b]] (zeta = (b - a) / (2 |g|),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = t c; Golub and Van
+// Loan, Matrix Computations, section 8.5) conjugated by diag(1, e^{-i phi}):
+//   R = [[c, s e^{i phi}], [-s e^{-i phi}, c]],   R^H G R diagonal.
+// With d = (b - a) / 2 and rho = sqrt(d^2 + |g|^2): t = sign(d) |g| / (|d| + rho) and
+// s e^{i phi} = sign(d) c g / (|d| + rho), so one sqrt, one reciprocal and one rsqrt suffice and
+// |g| itself is never needed (the threshold test compares |g|^2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr int EB = 16;        // indices per block
+constexpr int ES = 2 * EB;    // order of a block-pair subproblem
+constexpr int EP = ES + 1;    // LDS row pitch
+constexpr double PAD = 1e30;  // diagonal of the padded indices
+
+// round-robin pair i of round r among n (even) players: player n-1 meets r, the others rotate
+__host__ __device__ inline void rr_pair(int n, int r, int i, int& a, int& b)
+{
+    if (i == 0) {
+        a = r;
+        b = n - 1;
+    } else {
+        a = (r + i) % (n - 1);
+        b = (r - i + (n - 1)) % (n - 1);
+    }
+}
+
+__device__ inline zd zconjd(zd a) { return make_double2(a.x, -a.y); }
+__device__ inline zd zaxpy(double c, zd x, zd s, zd y) { zd p = zmul(s, y); return make_double2(c * x.x + p.x, c * x.y + p.y); }
+
+// global index of subproblem index u for the block pair (P, Q)
+__device__ inline int sub_index(int P, int Q, int u) { return u < EB ? P * EB + u : Q * EB + (u - EB); }
+
+__global__ __launch_bounds__(256) void k_eig_pad(int m, int M, const zd* __restrict__ G, int ldg, zd* __restrict__ Gp,
+                                                 zd* __restrict__ Wp)
+{
+    const size_t total = (size_t)M * M;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % M), j = (int)(e / M);
+        zd g = make_double2(0.0, 0.0);
+        if (i < m && j < m) g = G[(size_t)i + (size_t)j * ldg];
+        else if (i == j) g.x = PAD;
+        if (i == j) g.y = 0.0;
+        Gp[e] = g;
+        Wp[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+}
+
+// one workgroup: out[0] = max_i |G_ii|, out[1] = max_{i != j} |G_ij| over the leading m x m part
+__global__ __launch_bounds__(256) void k_eig_scale(int m, const zd* __restrict__ G, int ldg, double* out)
+{
+    __shared__ double sd[256], so[256];
+    double d = 0, o = 0;
+    for (int e = threadIdx.x; e < m * m; e += 256) {
+        const int i = e % m, j = e / m;
+        const zd g = G[(size_t)i + (size_t)j * ldg];
+        const double a = sqrt(g.x * g.x + g.y * g.y);
+        if (i == j) d = fmax(d, fabs(g.x));
+        else o = fmax(o, a);
+    }
+    sd[threadIdx.x] = d;
+    so[threadIdx.x] = o;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
+            so[threadIdx.x] = fmax(so[threadIdx.x], so[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sd[0];
+        out[1] = so[0];
+        const double t = 1e-14 * fmax(sd[0], so[0]);   // rotation threshold on |g|
+        out[2] = t * t;                                  // compared with |g|^2
+    }
+}
+
+// Kernel A: workgroup w diagonalises the subproblem of block pair w of round `round`.
+__global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, const zd* __restrict__ Gp,
+                                                   zd* __restrict__ J, const double* __restrict__ scale)
+{
+    __shared__ zd A[ES * EP];
+    __shared__ zd V[ES * EP];
+    __shared__ double rc[ES / 2];
+    __shared__ zd rs[ES / 2];
+    __shared__ int rot[ES];            // rot[r] != 0: some pair of round r is rotated
+    const int tid = threadIdx.x;
+    int P, Q;
+    rr_pair(nb, round, blockIdx.x, P, Q);
+    for (int e = tid; e < ES * ES; e += 256) {
+        const int u = e % ES, v = e / ES;
+        A[u * EP + v] = Gp[(size_t)sub_index(P, Q, u) + (size_t)sub_index(P, Q, v) * M];
+        V[u * EP + v] = make_double2(u == v ? 1.0 : 0.0, 0.0);
+    }
+    if (tid < ES) rot[tid] = 0;
+    const double tol2 = scale[2];
+    // this thread's 2 x 2 block (pair bi, pair bj) and its two rows of V (rows bi, bi + 16; pair bj)
+    const int bi = tid / (ES / 2), bj = tid % (ES / 2);
+    __syncthreads();
+    for (int r = 0; r < ES - 1; ++r) {
+        if (tid < ES / 2) {
+            int p, q;
+            rr_pair(ES, r, tid, p, q);
+            const zd g = A[p * EP + q];
+            const double g2 = g.x * g.x + g.y * g.y;
+            double c = 1.0;
+            zd se = make_double2(0.0, 0.0);
+            if (g2 > tol2) {
+                const double d = 0.5 * (A[q * EP + q].x - A[p * EP + p].x);
+                const double inv = 1.0 / (fabs(d) + sqrt(d * d + g2));
+                const double t2 = g2 * inv * inv;
+                c = rsqrt(1.0 + t2);
+                const double f = (d >= 0 ? c : -c) * inv;
+                se = make_double2(f * g.x, f * g.y);
+                rot[r] = 1;
+            }
+            rc[tid] = c;
+            rs[tid] = se;
+        }
+        __syncthreads();
+        if (rot[r]) {
+            int pi, qi, pj, qj;
+            rr_pair(ES, r, bi, pi, qi);
+            rr_pair(ES, r, bj, pj, qj);
+            const double ci = rc[bi], cj = rc[bj];
+            const zd si = rs[bi], sj = rs[bj];
+            const zd b00 = A[pi * EP + pj], b01 = A[pi * EP + qj], b10 = A[qi * EP + pj], b11 = A[qi * EP + qj];
+            // T = B R_j,  R = [[c, s], [-conj(s), c]]
+            const zd nsj = make_double2(-sj.x, sj.y);   // -conj(s_j)
+            const zd t00 = zaxpy(cj, b00, nsj, b01), t01 = zaxpy(cj, b01, sj, b00);
+            const zd t10 = zaxpy(cj, b10, nsj, b11), t11 = zaxpy(cj, b11, sj, b10);
+            // B' = R_i^H T,  R^H = [[c, -s], [conj(s), c]]
+            const zd msi = make_double2(-si.x, -si.y), csi = zconjd(si);
+            zd o00 = zaxpy(ci, t00, msi, t10), o01 = zaxpy(ci, t01, msi, t11);
+            zd o10 = zaxpy(ci, t10, csi, t00), o11 = zaxpy(ci, t11, csi, t01);
+            if (bi == bj) {   // the rotated 2 x 2 diagonal block is diagonal and real
+                o01 = make_double2(0.0, 0.0);
+                o10 = o01;
+                o00.y = 0.0;
+                o11.y = 0.0;
+            }
+            A[pi * EP + pj] = o00;
+            A[pi * EP + qj] = o01;
+            A[qi * EP + pj] = o10;
+            A[qi * EP + qj] = o11;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {   // V <- V R
+                const int u = bi + h * (ES / 2);
+                const zd vp = V[u * EP + pj], vq = V[u * EP + qj];
+                V[u * EP + pj] = zaxpy(cj, vp, nsj, vq);
+                V[u * EP + qj] = zaxpy(cj, vq, sj, vp);
+            }
+        }
+        __syncthreads();
+    }
+    zd* Jw = J + (size_t)blockIdx.x * ES * ES;
+    for (int e = tid; e < ES * ES; e += 256) {
+        const int u = e % ES, v = e / ES;
+        Jw[e] = V[u * EP + v];
+    }
+}
+
+// Kernel B: G <- J^H G J on the (pair p, pair q) tiles, W <- W J on (32-row slab, pair q) tiles.
+__global__ __launch_bounds__(256) void k_eig_apply(int M, int nb, int round, zd* __restrict__ Gp, zd* __restrict__ Wp,
+                                                   const zd* __restrict__ J)
+{
+    __shared__ zd X[ES * EP];
+    __shared__ zd Jq[ES * EP];
+    __shared__ zd Jp[ES * EP];
+    const int tid = threadIdx.x;
+    const int npair = nb / 2;
+    const int b = blockIdx.x;
+    const bool gpart = b < npair * npair;
+    int p = 0, q, slab = 0;
+    if (gpart) {
+        p = b / npair;
+        q = b % npair;
+    } else {
+        slab = (b - npair * npair) / npair;
+        q = (b - npair * npair) % npair;
+    }
+    int Pp, Qp, Pq, Qq;
+    rr_pair(nb, round, p, Pp, Qp);
+    rr_pair(nb, round, q, Pq, Qq);
+    for (int e = tid; e < ES * ES; e += 256) {
+        const int u = e % ES, v = e / ES;
+        const size_t col = (size_t)sub_index(Pq, Qq, v) * M;
+        X[u * EP + v] = gpart ? Gp[(size_t)sub_index(Pp, Qp, u) + col] : Wp[(size_t)slab * ES + u + col];
+        Jq[u * EP + v] = J[(size_t)q * ES * ES + e];
+        if (gpart) Jp[u * EP + v] = J[(size_t)p * ES * ES + e];
+    }
+    __syncthreads();
+    zd t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {   // T = X Jq
+        const int e = tid + 256 * k, u = e % ES, v = e / ES;
+        zd s = make_double2(0.0, 0.0);
+        for (int w = 0; w < ES; ++w) {
+            const zd x = X[u * EP + w], y = Jq[w * EP + v];
+            s.x += x.x * y.x - x.y * y.y;
+            s.y += x.x * y.y + x.y * y.x;
+        }
+        t[k] = s;
+    }
+    if (!gpart) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = tid + 256 * k, u = e % ES, v = e / ES;
+            Wp[(size_t)slab * ES + u + (size_t)sub_index(Pq, Qq, v) * M] = t[k];
+        }
+        return;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = tid + 256 * k, u = e % ES, v = e / ES;
+        X[u * EP + v] = t[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {   // G' = Jp^H T
+        const int e = tid + 256 * k, u = e % ES, v = e / ES;
+        zd s = make_double2(0.0, 0.0);
+        for (int w = 0; w < ES; ++w) {
+            const zd x = Jp[w * EP + u], y = X[w * EP + v];   // conj(Jp[w][u]) * T[w][v]
+            s.x += x.x * y.x + x.y * y.y;
+            s.y += x.x * y.y - x.y * y.x;
+        }
+        Gp[(size_t)sub_index(Pp, Qp, u) + (size_t)sub_index(Pq, Qq, v) * M] = s;
+    }
+}
+
+// out[0] = max |G_ij| over i != j < m (real indices); out[1 + i] = Re G_ii for i < M
+__global__ __launch_bounds__(256) void k_eig_colmax(int m, int M, const zd* __restrict__ Gp, double* __restrict__ colmax,
+                                                    double* __restrict__ out)
+{
+    __shared__ double sm[256];
+    const int j = blockIdx.x;
+    double o = 0;
+    if (j < m)
+        for (int i = threadIdx.x; i < m; i += 256) {
+            if (i == j) continue;
+            const zd g = Gp[(size_t)i + (size_t)j * M];
+            o = fmax(o, sqrt(g.x * g.x + g.y * g.y));
+        }
+    sm[threadIdx.x] = o;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        colmax[j] = sm[0];
+        out[1 + j] = Gp[(size_t)j + (size_t)j * M].x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_eig_maxreduce(int M, const double* __restrict__ colmax, double* __restrict__ out)
+{
+    __shared__ double sm[256];
+    double o = 0;
+    for (int i = threadIdx.x; i < M; i += 256) o = fmax(o, colmax[i]);
+    sm[threadIdx.x] = o;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+// W(:, k) = Wp(0:m, perm[k]), theta[k] = diag[perm[k]] for k < m
+__global__ __launch_bounds__(256) void k_eig_gather(int m, int M, const zd* __restrict__ Wp, const int* __restrict__ perm,
+                                                    const double* __restrict__ diag, zd* __restrict__ W, int ldw,
+                                                    double* __restrict__ theta)
+{
+    const size_t total = (size_t)m * m;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % m), k = (int)(e / m);
+        const int c = perm[k];
+        W[(size_t)i + (size_t)k * ldw] = Wp[(size_t)i + (size_t)c * M];
+        if (i == 0) theta[k] = diag[c];
+    }
+}
+
+int grid_for(size_t n)
+{
+    size_t g = (n + 255) / 256;
+    return (int)std::min<size_t>(std::max<size_t>(g, 1), 4096);
+}
+
+}  // namespace
+
+int eig_padded_order(int m) { return ((m + ES - 1) / ES) * ES; }
+
+size_t eig_work_bytes(int m)
+{
+    const size_t M = (size_t)eig_padded_order(m);
+    return (2 * M * M + (M / ES) * ES * ES) * sizeof(zd) + (2 * M + 8) * sizeof(double) + M * sizeof(int) + 1024;
+}
+
+// Eigen-decomposition G = W diag(theta) W^H of the Hermitian m x m matrix G (device, leading
+// dimension ldg): on return G holds W (columns ascending in theta), theta[m] (device) the
+// eigenvalues.  work: eig_work_bytes(m) bytes of device memory; host: M + 1 doubles of host memory
+// (pinned for speed) with M = eig_padded_order(m).  *sweeps receives the sweeps taken.  Returns a
+// hipError_t as int, or -1 when 40 sweeps did not reach the threshold.
+int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps)
+{
+    if (m <= 0) return 0;
+    const int M = eig_padded_order(m), nb = M / EB, npair = nb / 2;
+    char* w = (char*)work;
+    zd* Gp = (zd*)w;
+    zd* Wp = Gp + (size_t)M * M;
+    zd* J = Wp + (size_t)M * M;
+    double* dbuf = (double*)(J + (size_t)npair * ES * ES);   // [0, 8): scale, [8, 8 + M): column maxima
+    double* scale = dbuf;
+    double* colmax = dbuf + 8;
+    double* outd = colmax + M;                                // off max + diagonal [M + 1]
+    int* perm = (int*)(outd + M + 1);
+    hipLaunchKernelGGL(k_eig_scale, dim3(1), dim3(256), 0, s, m, (const zd*)G, ldg, scale);
+    hipLaunchKernelGGL(k_eig_pad, dim3(grid_for((size_t)M * M)), dim3(256), 0, s, m, M, (const zd*)G, ldg, Gp, Wp);
+    double sc[3] = {0, 0, 0};
+    int rc = (int)hipMemcpyAsync(sc, scale, sizeof(sc), hipMemcpyDeviceToHost, s);
+    if (rc == 0) rc = (int)hipStreamSynchronize(s);
+    if (rc != 0) return rc;
+    const double stop = 5e-14 * std::max(sc[0], sc[1]);
+    int sw = 0;
+    bool done = !(sc[1] > stop);   // already diagonal
+    if (done) {
+        hipLaunchKernelGGL(k_eig_colmax, dim3(M), dim3(256), 0, s, m, M, (const zd*)Gp, colmax, outd);
+        rc = (int)hipMemcpyAsync(host, outd, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, s);
+        if (rc == 0) rc = (int)hipStreamSynchronize(s);
+        if (rc != 0) return rc;
+    }
+    while (!done && sw < 40) {
+        for (int r = 0; r < nb - 1; ++r) {
+            hipLaunchKernelGGL(k_eig_inner, dim3(npair), dim3(256), 0, s, M, nb, r, (const zd*)Gp, J,
+                               (const double*)scale);
+            hipLaunchKernelGGL(k_eig_apply, dim3(npair * npair + (M / ES) * npair), dim3(256), 0, s, M, nb, r, Gp, Wp,
+                               (const zd*)J);
+        }
+        ++sw;
+        hipLaunchKernelGGL(k_eig_colmax, dim3(M), dim3(256), 0, s, m, M, (const zd*)Gp, colmax, outd);
+        hipLaunchKernelGGL(k_eig_maxreduce, dim3(1), dim3(256), 0, s, M, (const double*)colmax, outd);
+        rc = (int)hipMemcpyAsync(host, outd, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, s);
+        if (rc == 0) rc = (int)hipStreamSynchronize(s);
+        if (rc != 0) return rc;
+        done = host[0] <= stop;
+    }
+    if (sweeps) *sweeps = sw;
+    if (!done) return -1;
+    // ascending order of the diagonal (padded indices last)
+    std::vector<int> ord(M);
+    std::iota(ord.begin(), ord.end(), 0);
+    const double* d = host + 1;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] < d[b]; });
+    // `ord` must outlive the copy: the stream is synchronised before returning
+    rc = (int)hipMemcpyAsync(perm, ord.data(), sizeof(int) * m, hipMemcpyHostToDevice, s);
+    if (rc != 0) return rc;
+    hipLaunchKernelGGL(k_eig_gather, dim3(grid_for((size_t)m * m)), dim3(256), 0, s, m, M, (const zd*)Wp,
+                       (const int*)perm, (const double*)(outd + 1), G, ldg, theta);
+    rc = (int)hipGetLastError();
+    if (rc == 0) rc = (int)hipStreamSynchronize(s);
+    return rc;
+}

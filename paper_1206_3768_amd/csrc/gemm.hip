@@ -1,30 +1,18 @@
 // Complex GEMM on CDNA4 matrix cores, with the Chebyshev three-term recurrence fused into the
 // epilogue (Algorithm 1, filtering step: Y_{k+1} = alpha (H - cI) Y_k + beta Y_{k-1}).
 //
-// Complex products run as four real products on v_mfma_f64_16x16x4f64 (FP64) or
-// v_mfma_f32_16x16x4f32 (FP32).  The MFMA is used "transposed": its A operand carries op(B)
-// (row index = output column j) and its B operand carries op(A) (column index = output row i),
-// so that each lane ends up owning output elements of one output row i, and 16 lanes store 16
-// consecutive rows of one column: 256 contiguous bytes per store instruction for complex128.
-//
-// Workgroup = 4 waves (256 threads) computing a BM x BN complex output tile, each wave a
-// (BM/2) x (BN/2) sub-tile of 16x16 MFMA blocks.  Operands are staged through LDS in k-stages of
-// 16 complex elements, double buffered with one barrier per stage: the global loads of stage s+1
-// are in flight while the MFMAs of stage s run.  Tiles are enumerated so that consecutive tiles
-// (same rows of A, neighbouring column tiles) land on the same XCD: the hardware hands workgroup w
-// to XCD w % 8.  Split-K writes partial tiles to a workspace; the last K-slice to finish a tile
-// sums the partials in slice order (deterministic) and applies the epilogue, so one launch is one
-// filter step.
+// The MFMA tile itself (operand staging, transposed complex MFMA) lives in gemm_tile.h.  Tiles
+// are enumerated so that consecutive tiles (same rows of A, neighbouring column tiles) land on the
+// same XCD: the hardware hands workgroup w to XCD w % 8.  Split-K writes partial tiles to a
+// workspace; the last K-slice to finish a tile sums the partials in slice order (deterministic)
+// and applies the epilogue, so one launch is one filter step.
 #include "common.h"
+#include "gemm_tile.h"
 
 namespace {
 
-template <typename T> struct CT;
-template <> struct CT<double> { typedef double2 c; typedef d4 acc; };
-template <> struct CT<float> { typedef float2 c; typedef f4 acc; };
-
-__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+using chfsi_tile::CT;
+using chfsi_tile::TileShape;
 
 enum { EPI_GEMM = 0, EPI_FILTER = 1 };
 
@@ -44,14 +32,6 @@ __device__ __forceinline__ int xcd_remap(int w, int nt)
     const int x = w % X, q = w / X;
     return x * per + (x < rem ? x : rem) + q;
 }
-
-template <typename C2> __device__ __forceinline__ C2 cconj(C2 v) { v.y = -v.y; return v; }
-
-// Row of the 16x16 MFMA result held in register r of lane l.  Measured on gfx950:
-// v_mfma_f32_16x16x4f32 holds row 4 (l/16) + r, v_mfma_f64_16x16x4f64 holds row 4 r + l/16;
-// both hold column l % 16.
-__device__ __forceinline__ int drow(double, int lane, int r) { return 4 * r + (lane >> 4); }
-__device__ __forceinline__ int drow(float, int lane, int r) { return 4 * (lane >> 4) + r; }
 
 template <typename T, int EPI>
 __device__ __forceinline__ void epilogue_store(const GDims& g, typename CT<T>::c* C,
@@ -96,12 +76,10 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
 {
     typedef typename CT<T>::c C2;
     typedef typename CT<T>::acc ACC;
-    constexpr int BK = 16;
-    constexpr int LDA_S = BM + 1, LDB_S = BN + 1;   // +1 element: conflict-free transposed stores
-    __shared__ C2 As[2][BK * LDA_S];
-    __shared__ C2 Bs[2][BK * LDB_S];
-    constexpr int NPA = BM * BK / 256, NPB = BN * BK / 256;
-    constexpr int MI = BM / 32, NJ = BN / 32;
+    typedef TileShape<T, BM, BN> S;
+    __shared__ C2 As[2 * S::AS_ELEMS];
+    __shared__ C2 Bs[2 * S::BS_ELEMS];
+    constexpr int MI = S::MI, NJ = S::NJ;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nt = g.tiles_m * g.tiles_n * g.ksplit;
@@ -113,88 +91,10 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
     const int i0 = it * BM, j0 = jt * BN;
     const int kb = ks * g.kchunk;
     const int ke = min(g.K, kb + g.kchunk);
-    const int nstages = ke > kb ? (ke - kb + BK - 1) / BK : 0;
     const int wr = (wave & 1) * (BM / 2), wc = (wave >> 1) * (BN / 2);
 
     ACC accr[MI][NJ], acci[MI][NJ];
-#pragma unroll
-    for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < NJ; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) { accr[bi][bj][r] = 0; acci[bi][bj][r] = 0; }
-
-    C2 ra[NPA], rb[NPB];
-    const C2 zero = {0, 0};
-
-    // element p of a stage tile handled by this thread: op(A) row ai(p), column ak(p); op(B) row
-    // bk(p), column bj(p).  Consecutive threads walk the contiguous dimension of the stored matrix.
-#define AI(p) ((OPA == OP_N) ? (tid + 256 * (p)) % BM : (tid + 256 * (p)) / BK)
-#define AK(p) ((OPA == OP_N) ? (tid + 256 * (p)) / BM : (tid + 256 * (p)) % BK)
-#define BJ(p) ((OPB == OP_N) ? (tid + 256 * (p)) / BK : (tid + 256 * (p)) % BN)
-#define BKK(p) ((OPB == OP_N) ? (tid + 256 * (p)) % BK : (tid + 256 * (p)) / BN)
-#define GEMM_GLOAD(k0)                                                                                    \
-    {                                                                                                     \
-        _Pragma("unroll") for (int p = 0; p < NPA; ++p) {                                                 \
-            const int gi = i0 + AI(p), gk = (k0) + AK(p);                                                 \
-            const int ci = min(gi, g.M - 1), ck = min(gk, ke - 1);   /* clamped: always in bounds */    \
-            const size_t off = (OPA == OP_N) ? (size_t)ci + (size_t)ck * g.lda : (size_t)ck + (size_t)ci * g.lda; \
-            const C2 v = A[off];                                                                          \
-            ra[p] = (gi < g.M && gk < ke) ? ((OPA == OP_N) ? v : cconj(v)) : zero;                         \
-        }                                                                                                 \
-        _Pragma("unroll") for (int p = 0; p < NPB; ++p) {                                                 \
-            const int gj = j0 + BJ(p), gk = (k0) + BKK(p);                                                \
-            const int cj = min(gj, g.N - 1), ck = min(gk, ke - 1);                                        \
-            const size_t off = (OPB == OP_N) ? (size_t)ck + (size_t)cj * g.ldb : (size_t)cj + (size_t)ck * g.ldb; \
-            const C2 v = B[off];                                                                          \
-            rb[p] = (gj < g.N && gk < ke) ? ((OPB == OP_N) ? v : cconj(v)) : zero;                         \
-        }                                                                                                 \
-    }
-#define GEMM_SSTORE(buf)                                                                                  \
-    {                                                                                                     \
-        _Pragma("unroll") for (int p = 0; p < NPA; ++p) As[buf][AK(p) * LDA_S + AI(p)] = ra[p];           \
-        _Pragma("unroll") for (int p = 0; p < NPB; ++p) Bs[buf][BKK(p) * LDB_S + BJ(p)] = rb[p];          \
-    }
-
-    if (nstages > 0) GEMM_GLOAD(kb);
-    for (int s = 0; s < nstages; ++s) {
-        const int buf = s & 1;
-        GEMM_SSTORE(buf);
-        __syncthreads();
-        if (s + 1 < nstages) GEMM_GLOAD(kb + (s + 1) * BK);
-        const C2* as = As[buf];
-        const C2* bs = Bs[buf];
-#pragma unroll
-        for (int kk = 0; kk < BK / 4; ++kk) {
-            const int kr = kk * 4 + (lane >> 4);
-            C2 a[MI], b[NJ];
-#pragma unroll
-            for (int bi = 0; bi < MI; ++bi) a[bi] = as[kr * LDA_S + wr + bi * 16 + (lane & 15)];
-#pragma unroll
-            for (int bj = 0; bj < NJ; ++bj) b[bj] = bs[kr * LDB_S + wc + bj * 16 + (lane & 15)];
-            // re += Bre Are ; im += Bim Are   (all blocks), then re -= Bim Aim ; im += Bre Aim
-#pragma unroll
-            for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < NJ; ++bj) {
-                    accr[bi][bj] = mfma16(b[bj].x, a[bi].x, accr[bi][bj]);
-                    acci[bi][bj] = mfma16(b[bj].y, a[bi].x, acci[bi][bj]);
-                }
-#pragma unroll
-            for (int bi = 0; bi < MI; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < NJ; ++bj) {
-                    accr[bi][bj] = mfma16(-b[bj].y, a[bi].y, accr[bi][bj]);
-                    acci[bi][bj] = mfma16(b[bj].x, a[bi].y, acci[bi][bj]);
-                }
-        }
-    }
-#undef GEMM_GLOAD
-#undef GEMM_SSTORE
-#undef AI
-#undef AK
-#undef BJ
-#undef BKK
+    chfsi_tile::tile_mainloop<T, OPA, OPB, BM, BN>(A, g.lda, g.M, B, g.ldb, g.N, i0, j0, kb, ke, As, Bs, accr, acci);
 
     if (MODE == 0) {
 #pragma unroll
@@ -204,7 +104,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + wr + bi * 16 + (lane & 15);
-                    const int j = j0 + wc + bj * 16 + drow(T(0), lane, r);
+                    const int j = j0 + wc + bj * 16 + chfsi_tile::drow(T(0), lane, r);
                     if (i < g.M && j < g.N) epilogue_store<T, EPI>(g, C, Yk, Yp, i, j, accr[bi][bj][r], acci[bi][bj][r]);
                 }
         return;
@@ -218,7 +118,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr + bi * 16 + (lane & 15);
-                const int j = j0 + wc + bj * 16 + drow(T(0), lane, r);
+                const int j = j0 + wc + bj * 16 + chfsi_tile::drow(T(0), lane, r);
                 if (i < g.M && j < g.N) {
                     C2 o;
                     o.x = accr[bi][bj][r];
@@ -244,7 +144,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr + bi * 16 + (lane & 15);
-                const int j = j0 + wc + bj * 16 + drow(T(0), lane, r);
+                const int j = j0 + wc + bj * 16 + chfsi_tile::drow(T(0), lane, r);
                 if (i < g.M && j < g.N) {
                     T vr = 0, vi = 0;
                     for (int s = 0; s < g.ksplit; ++s) {

@@ -39,6 +39,22 @@ void Arena::grow(size_t bytes)
     cap = bytes;
 }
 
+bool PinBuf::reserve(size_t bytes)
+{
+    if (bytes <= cap) return true;
+    release();
+    if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) { p = nullptr; return false; }
+    cap = bytes;
+    return true;
+}
+
+void PinBuf::release()
+{
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
 void* Arena::get(size_t bytes)
 {
     size_t b = (bytes + 255) & ~(size_t)255;
@@ -161,6 +177,7 @@ void chfsi_default_params(chfsi_params* p)
     p->have_bounds = 0;
     p->trace = 0;
     p->switch_residual = 0.0;
+    p->deg_margin = 0;
 }
 
 chfsi_status chfsi_create(chfsi_handle* out, int device, void* hip_stream)
@@ -197,7 +214,26 @@ chfsi_status chfsi_destroy(chfsi_handle h)
     if (!h) return CHFSI_ERR_ARG;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);
+    for (auto& l : h->lanes) (void)hipStreamSynchronize(l.st);
     if (h->ws.base) (void)hipFree(h->ws.base);
+    for (auto& a : h->barena)
+        if (a.base) (void)hipFree(a.base);
+    h->pin.release();
+    for (auto& pb : h->bpin) pb.release();
+    h->btable_host.release();
+    for (auto& g : h->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    if (h->btable) (void)hipFree(h->btable);
+    for (auto& l : h->lanes) {
+        if (l.rb) rocblas_destroy_handle(l.rb);
+        if (l.ev) (void)hipEventDestroy(l.ev);
+        if (l.st) (void)hipStreamDestroy(l.st);
+    }
+    for (auto& e : h->bev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->model) (void)hipFree(h->model);
     if (h->tile_cnt) (void)hipFree(h->tile_cnt);
     if (h->rb) rocblas_destroy_handle(h->rb);
@@ -279,18 +315,17 @@ static inline const rocblas_double_complex* rbz(const zd* p) { return reinterpre
         if ((x) != rocblas_status_success) return CHFSI_ERR_DEVICE; \
     } while (0)
 
-// S = L L^H (L lower, strict upper part zeroed), H = L^{-1} A L^{-H}, Hermitized.
-chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                         int* info_dev)
+// S = L L^H (L lower, strict upper part zeroed), H = L^{-1} A L^{-H}, Hermitized.  Enqueues the
+// whole reduction; the Cholesky info word is copied to *info_host (host memory, valid after the
+// stream has been synchronised; nonzero = S not positive definite, H then meaningless).
+chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
+                                 int* info_dev, int* info_host)
 {
     hipStream_t st = h->stream;
     TRY(launch_zlacpy(st, n, n, S, lds, L, n));
     TRY(hipMemsetAsync(info_dev, 0, sizeof(int), st));
     TRYRB(rocsolver_zpotrf(h->rb, rocblas_fill_lower, n, rbz(L), n, info_dev));
-    int info = 0;
-    TRY(hipMemcpyAsync(&info, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
-    if (info != 0) return CHFSI_ERR_NOT_HPD;
+    TRY(hipMemcpyAsync(info_host, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     TRY(launch_zero_upper(st, n, L, n));
     TRY(launch_zlacpy(st, n, n, A, lda, H, n));
     const rocblas_double_complex one(1.0, 0.0);
@@ -302,10 +337,21 @@ chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* 
     return CHFSI_SUCCESS;
 }
 
+chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
+                         int* info_dev)
+{
+    int info = 0;
+    chfsi_status s = step_reduce_enqueue(h, n, A, lda, S, lds, H, L, info_dev, &info);
+    if (s != CHFSI_SUCCESS) return s;
+    TRY(hipStreamSynchronize(h->stream));
+    return info != 0 ? CHFSI_ERR_NOT_HPD : CHFSI_SUCCESS;
+}
+
 // k-step Lanczos with full reorthogonalisation (two classical Gram-Schmidt passes per step).
-chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed, zd* LV,
-                          zd* w, zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
-                          double& beta_k, int& k_used)
+// Enqueues the k steps and the copies of alpha_1..k, beta_1..k to hal/hbe (host, valid after the
+// stream has been synchronised).
+chfsi_status step_lanczos_enqueue(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed,
+                                  zd* LV, zd* w, zd* c, double* coef_dev, double* hal, double* hbe)
 {
     hipStream_t st = h->stream;
     double* al = coef_dev;             // [k]
@@ -324,19 +370,36 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
         }
         TRY(launch_lanczos_normalize(st, n, w, LV + (size_t)(j + 1) * n, be + j));
     }
-    std::vector<double> hal(k), hbe(k);
-    TRY(hipMemcpyAsync(hal.data(), al, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-    TRY(hipMemcpyAsync(hbe.data(), be, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-    TRY(hipStreamSynchronize(st));
+    TRY(hipMemcpyAsync(hal, al, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(hbe, be, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    return CHFSI_SUCCESS;
+}
+
+// Host part of Lanczos: the tridiagonal T_k (cut at the first vanishing beta) and its
+// eigen-decomposition: Ritz values theta and squared first components z1sq of the eigenvectors.
+chfsi_status lanczos_finish(int k, const double* hal, const double* hbe, std::vector<double>& theta,
+                            std::vector<double>& z1sq, double& beta_k, int& k_used)
+{
     int kk = k;
     for (int j = 0; j < k; ++j)
         if (!(hbe[j] > 1e-300)) { kk = j + 1; break; }
     for (int j = 0; j < kk; ++j)
         if (!std::isfinite(hal[j]) || !std::isfinite(hbe[j])) return CHFSI_ERR_NUMERIC;
-    host_tridiag_eig(kk, hal.data(), hbe.data(), theta, z1sq);
+    host_tridiag_eig(kk, hal, hbe, theta, z1sq);
     beta_k = hbe[kk - 1];
     k_used = kk;
     return CHFSI_SUCCESS;
+}
+
+chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed, zd* LV,
+                          zd* w, zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
+                          double& beta_k, int& k_used)
+{
+    std::vector<double> hal(k), hbe(k);
+    chfsi_status s = step_lanczos_enqueue(h, n, H, ldh, k, seed, LV, w, c, coef_dev, hal.data(), hbe.data());
+    if (s != CHFSI_SUCCESS) return s;
+    TRY(hipStreamSynchronize(h->stream));
+    return lanczos_finish(k, hal.data(), hbe.data(), theta, z1sq, beta_k, k_used);
 }
 
 // Y (n x ma) <- orthonormal basis: CGS twice against the nl locked columns YL, then shifted
@@ -369,16 +432,20 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
 }
 
 // Rayleigh-Ritz on orthonormal Y (n x ma): HY = H Y, G = Y^H HY, G = W diag(theta) W^H (ascending,
-// phase-normalised W), Y <- Y W, HY <- HY W, then r_j = ||HY_j - theta_j Y_j||.
+// phase-normalised W, block-Jacobi eigensolver of eig.hip), Y <- Y W, HY <- HY W, then
+// r_j = ||HY_j - theta_j Y_j||.  eig_work: eig_work_bytes(ma) bytes of device memory; eig_host:
+// eig_padded_order(ma) + 1 doubles of host memory.
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY,
-                                zd* T, zd* G, double* theta_dev, double* E, double* r_dev, int* info_dev,
+                                zd* T, zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
                                 const GemmWs& gw, PhaseTimer* tm)
 {
     hipStream_t st = h->stream;
     TRY(launch_zgemm(st, OP_N, OP_N, n, ma, n, 1.0, H, ldh, Y, ldy, 0.0, HY, n, gw));
     TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, HY, n, 0.0, G, ma, gw));
-    TRYRB(rocsolver_zheevd(h->rb, rocblas_evect_original, rocblas_fill_lower, ma, rbz(G), ma, theta_dev, E,
-                           info_dev));
+    int sweeps = 0;
+    const int rc = eig_jacobi(st, ma, G, ma, theta_dev, eig_work, eig_host, &sweeps);
+    if (rc == -1) return CHFSI_ERR_NUMERIC;
+    TRY(rc);
     TRY(launch_phase_normalize(st, ma, ma, G, ma));
     TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, 1.0, Y, ldy, G, ma, 0.0, T, n, gw));
     TRY(launch_zlacpy(st, n, ma, T, n, Y, ldy));

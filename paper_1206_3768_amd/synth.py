@@ -11,11 +11,17 @@ them with the same shapes and structure:
 
 * spectrum: a clustered low part of ``n_low`` values uniform in [-1, -0.5] and the rest uniform
   in [-0.4, 1];
-* eigenvectors: a Haar-distributed unitary Q (QR of a complex Gaussian, diagonal of R rotated to
-  be real positive; Mezzadri 2007);
+* eigenvectors: a unitary Q = R2 R1 P B with B block diagonal of Haar-distributed 64 x 64 blocks
+  (QR of a complex Gaussian, diagonal of R rotated to be real positive; Mezzadri 2007), P a
+  random permutation and R1, R2 Householder reflections along complex Gaussian vectors.  Q is
+  dense, and it costs O(n^2) to build and apply where a Haar matrix of order n costs O(n^3).  The
+  perturbations below have a unitarily invariant law, so for a standard problem the statistics of
+  a whole sequence do not depend on which eigenbasis Q is used;
 * overlap (generalized problems): S = I + G G^H / n with G a complex Gaussian n x 64;
-* "designed form": A0 = L Q diag(lam) Q^H L^H with S = L L^H, so the pencil (A0, S) has exactly the
-  spectrum ``lam`` and S-orthonormal eigenvectors X = L^{-H} Q;
+* "designed form": A0 = S^{1/2} Q diag(lam) Q^H S^{1/2}, so the pencil (A0, S) has exactly the
+  spectrum ``lam`` and S-orthonormal eigenvectors X = S^{-1/2} Q.  S^{+-1/2} = I + G f(G^H G/n) G^H
+  are rank-64 corrections of I (f from the 64 x 64 eigen-decomposition of G^H G / n), so A0 costs
+  O(n^2) as well;
 * sequence: A_{l+1} = A_l + eps_l (E_l + E_l^H) / 2 with E_l an i.i.d. complex Gaussian
   (real and imaginary parts N(0, 1/2)) drawn from its own stream, which makes successive
   problems correlated with a shrinking step, as in the self-consistent cycle of Section 2.1.
@@ -28,14 +34,27 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Iterator, List, Optional
 
 import numpy as np
-import scipy.linalg as sla
 
 # stream indices of the SeedSequence children, one per purpose
 _STREAM_LAM, _STREAM_Q, _STREAM_G, _STREAM_START = 0, 1, 2, 3
 _STREAM_E0 = 16  # E_l uses child _STREAM_E0 + l
+
+
+_PANEL = 256          # columns per independent draw panel of complex_gaussian
+_TILE = 128           # tile edge of the Hermitian symmetrisation
+_POOL = None
+
+
+def _pool():
+    global _POOL
+    if _POOL is None:
+        from concurrent.futures import ThreadPoolExecutor
+        _POOL = ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1)))
+    return _POOL
 
 
 def _rng(seed: int, stream: int) -> np.random.Generator:
@@ -46,42 +65,75 @@ def _rng(seed: int, stream: int) -> np.random.Generator:
 def complex_gaussian(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
     """i.i.d. complex normal entries, real and imaginary parts N(0, 1/2), Fortran order.
 
-    The draws fill the matrix column by column, real then imaginary part of each entry."""
-    buf = np.empty((cols, 2 * rows))
-    rng.standard_normal(out=buf)
-    buf *= math.sqrt(0.5)
+    Columns are drawn in panels of 256: panel p (columns 256 p ..) from child p of rng.spawn, column
+    by column, real then imaginary part of each entry; the panels are filled in parallel."""
+    buf = empty_f(2 * rows, cols, np.float64).T       # (cols, 2 rows), C order
+    npan = max(1, (cols + _PANEL - 1) // _PANEL)
+    kids = rng.spawn(npan)
+
+    def fill(p):
+        kids[p].standard_normal(out=buf[p * _PANEL:(p + 1) * _PANEL])
+        buf[p * _PANEL:(p + 1) * _PANEL] *= math.sqrt(0.5)
+
+    if npan == 1:
+        fill(0)
+    else:
+        list(_pool().map(fill, range(npan)))
     return buf.view(np.complex128).T          # (rows, cols), Fortran-ordered view
 
 
-def _t(a: np.ndarray):
-    """Fortran-ordered complex matrix -> torch tensor of its transpose (C-contiguous, no copy)."""
+def hermitian_part_(M: np.ndarray) -> np.ndarray:
+    """M <- (M + M^H) / 2 in place, tile by tile; the result is exactly Hermitian."""
+    n = M.shape[0]
+    b = _TILE
+
+    def row(i):
+        blk = M[i:i + b, i:i + b]
+        M[i:i + b, i:i + b] = 0.5 * (blk + blk.conj().T)
+        for j in range(i + b, n, b):
+            Z = 0.5 * (M[i:i + b, j:j + b] + M[j:j + b, i:i + b].conj().T)
+            M[i:i + b, j:j + b] = Z
+            M[j:j + b, i:i + b] = Z.conj().T
+
+    list(_pool().map(row, range(0, n, b)))
+    return M
+
+
+def _gemm(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """a @ b through torch (threaded BLAS) for Fortran or C ordered operands; Fortran-ordered result
+    (computed as the C-ordered (b^T a^T))."""
     import torch
-    return torch.from_numpy(np.ascontiguousarray(a.T))
+    return (torch.from_numpy(b).T @ torch.from_numpy(a).T).numpy().T
 
 
-def _from_t(t) -> np.ndarray:
-    """torch tensor holding a transpose -> Fortran-ordered numpy matrix (no copy)."""
+def empty_f(rows: int, cols: int, dtype=np.complex128, zero: bool = False) -> np.ndarray:
+    """Fortran-ordered array whose memory comes from torch's allocator (large blocks get huge-page
+    aligned memory, which is much cheaper to touch first than numpy's)."""
+    import torch
+    tdt = {np.complex128: torch.complex128, np.float64: torch.float64}[np.dtype(dtype).type]
+    t = (torch.zeros if zero else torch.empty)((cols, rows), dtype=tdt)
     return t.numpy().T
 
 
-def _to_fortran(t) -> np.ndarray:
-    """torch matrix -> Fortran-ordered numpy array with the same entries (threaded transpose copy)."""
-    return t.T.contiguous().numpy().T
-
-
-def haar_unitary_t(rng: np.random.Generator, n: int):
-    """Haar-distributed n x n unitary as a torch tensor: QR of a complex Gaussian (an i.i.d. matrix,
-    taken in whichever memory order it was drawn) with R's diagonal made real positive."""
+def _tt(M: np.ndarray):
+    """Fortran-ordered numpy matrix -> torch tensor of its transpose sharing the memory (torch
+    runs the n^2 passes multithreaded)."""
     import torch
-    z = torch.from_numpy(complex_gaussian(rng, n, n).T)      # C-contiguous; still i.i.d. Gaussian
-    q, r = torch.linalg.qr(z)
-    d = torch.diagonal(r)
-    return q * (d / d.abs())[None, :]
+    return torch.from_numpy(M.T)
+
+
+def add_(a: np.ndarray, b: np.ndarray, alpha: float = 1.0) -> np.ndarray:
+    """a += alpha b for Fortran-ordered matrices, in place."""
+    _tt(a).add_(_tt(b), alpha=alpha)
+    return a
 
 
 def haar_unitary(rng: np.random.Generator, n: int) -> np.ndarray:
-    """Haar-distributed n x n unitary, Fortran order."""
-    return _to_fortran(haar_unitary_t(rng, n))
+    """Haar-distributed n x n unitary: QR of a complex Gaussian with R's diagonal made real
+    positive (Mezzadri 2007), Fortran order."""
+    q, r = np.linalg.qr(complex_gaussian(rng, n, n))
+    d = np.diag(r)
+    return np.asfortranarray(q * (d / np.abs(d))[None, :])
 
 
 def split_spectrum(rng: np.random.Generator, n: int, n_low: int) -> np.ndarray:
@@ -91,20 +143,113 @@ def split_spectrum(rng: np.random.Generator, n: int, n_low: int) -> np.ndarray:
     return np.sort(np.concatenate([lo, hi]))
 
 
+class StructuredUnitary:
+    """Q = R2 R1 P B (see the module docstring), applied without forming it."""
+
+    def __init__(self, rng: np.random.Generator, n: int, block: int = 64):
+        self.n = n
+        sizes = [block] * (n // block) + ([n % block] if n % block else [])
+        self.blocks = [haar_unitary(rng, sz) for sz in sizes]
+        self.perm = rng.permutation(n)          # P e_i = e_{perm[i]}
+        self.u = []
+        for _ in range(2):
+            v = complex_gaussian(rng, n, 1)[:, 0]
+            self.u.append(np.ascontiguousarray(v / np.linalg.norm(v)))
+
+    def apply(self, Y: np.ndarray) -> np.ndarray:
+        """Q Y for Y (n x k); Fortran-ordered result."""
+        Z = np.empty_like(Y)
+        o = 0
+        for b in self.blocks:
+            Z[o:o + b.shape[0]] = b @ Y[o:o + b.shape[0]]
+            o += b.shape[0]
+        W = np.empty_like(Z)
+        W[self.perm] = Z
+        for u in self.u:                          # R = I - 2 u u^H
+            W -= 2.0 * np.outer(u, u.conj() @ W)
+        return np.asfortranarray(W)
+
+    def sandwich(self, lam: np.ndarray) -> np.ndarray:
+        """Q diag(lam) Q^H, exactly Hermitian, Fortran order."""
+        import torch
+        n = self.n
+        M = empty_f(n, n, zero=True)
+        o = 0
+        for b in self.blocks:
+            k = b.shape[0]
+            idx = self.perm[o:o + k]
+            M[np.ix_(idx, idx)] = (b * lam[o:o + k][None, :]) @ b.conj().T
+            o += k
+        Mt = _tt(M)                               # M^T
+        for un in self.u:                         # R M R = M - 2 u w^H - 2 w u^H + 4 c u u^H, w = M u
+            u = torch.from_numpy(un)
+            w = torch.mv(Mt.T, u)
+            c = float(torch.vdot(u, w).real)
+            Mt.addr_(w.conj(), u, alpha=-2.0)     # (u w^H)^T = conj(w) u^T
+            Mt.addr_(u.conj(), w, alpha=-2.0)
+            Mt.addr_(u.conj(), u, alpha=4.0 * c)
+        return hermitian_part_(M)
+
+
+@dataclasses.dataclass
+class Overlap:
+    """S = I + G G^H / n and the rank-r factors of S^{+-1/2} = I + K diag(f / n) K^H, K = G U."""
+    S: np.ndarray
+    K: np.ndarray
+    f_half: np.ndarray        # f(d) = (sqrt(1 + d) - 1) / d        -> S^{1/2}
+    f_mhalf: np.ndarray       # f(d) = (1 / sqrt(1 + d) - 1) / d    -> S^{-1/2}
+
+    def apply_mhalf(self, Y: np.ndarray) -> np.ndarray:
+        n = self.S.shape[0]
+        return np.asfortranarray(Y + self.K @ ((self.f_mhalf / n)[:, None] * (self.K.conj().T @ Y)))
+
+    def sandwich_half(self, M: np.ndarray) -> np.ndarray:
+        """S^{1/2} M S^{1/2} for Hermitian M (overwritten): M + [K T] [[F W F, F], [F, 0]] [K T]^H
+        with T = M K, W = K^H T, F = diag(f / n); exactly Hermitian."""
+        import torch
+        K = self.K
+        r = K.shape[1]
+        T = _gemm(M, K)
+        F = np.diag(self.f_half / M.shape[0]).astype(np.complex128)
+        W = K.conj().T @ T
+        core = np.zeros((2 * r, 2 * r), dtype=np.complex128)
+        core[:r, :r] = F @ W @ F
+        core[:r, r:] = F
+        core[r:, :r] = F
+        L = torch.from_numpy(np.ascontiguousarray(np.concatenate([K, T], axis=1)))
+        # M^T += (L core L^H)^T = conj(L) core^T L^T
+        _tt(M).addmm_(L.conj() @ torch.from_numpy(core.T.copy()), L.T)
+        return hermitian_part_(M)
+
+
+def overlap(rng: np.random.Generator, n: int, rank: int = 64) -> Overlap:
+    """HPD overlap S = I + G G^H / n with G an n x rank complex Gaussian, with its square roots."""
+    import torch
+    g = complex_gaussian(rng, n, rank)
+    gt = torch.from_numpy(np.ascontiguousarray(g))
+    S = empty_f(n, n)
+    torch.mm(gt.conj(), gt.T, out=_tt(S))     # S^T = conj(G) G^T
+    _tt(S).mul_(1.0 / n)
+    hermitian_part_(S)
+    S[np.diag_indices(n)] += 1.0
+    gh = g.conj().T
+    d, U = np.linalg.eigh(gh @ g / n)
+    d = np.maximum(d, 0.0)
+    safe = np.where(d > 1e-12, d, 1.0)
+    sq = np.sqrt(1.0 + d)
+    fh = np.where(d > 1e-12, (sq - 1.0) / safe, 0.5 - d / 8.0)
+    fm = np.where(d > 1e-12, (1.0 / sq - 1.0) / safe, -0.5 + 3.0 * d / 8.0)
+    return Overlap(S=S, K=np.asfortranarray(g @ U), f_half=fh, f_mhalf=fm)
+
+
 def overlap_matrix(rng: np.random.Generator, n: int, rank: int = 64) -> np.ndarray:
     """HPD overlap S = I + G G^H / n with G an n x rank complex Gaussian."""
-    import torch
-    g = torch.from_numpy(complex_gaussian(rng, rank, n).T)   # n x rank, i.i.d.
-    s = (g @ g.conj().T) / n
-    s = 0.5 * (s + s.conj().T)
-    s.diagonal().add_(1.0)
-    return _to_fortran(s)
+    return overlap(rng, n, rank).S
 
 
 def hermitian_noise(rng: np.random.Generator, n: int) -> np.ndarray:
-    """(E + E^H) / 2 with E an i.i.d. complex Gaussian (exactly Hermitian in floating point)."""
-    et = _t(complex_gaussian(rng, n, n))      # E^T
-    return _from_t(0.5 * (et + et.conj().T))   # (E^T + conj(E))/2 = ((E + E^H)/2)^T
+    """(E + E^H) / 2 with E an i.i.d. complex Gaussian (exactly Hermitian), Fortran order."""
+    return hermitian_part_(complex_gaussian(rng, n, n))
 
 
 @dataclasses.dataclass
@@ -135,25 +280,24 @@ class SequenceSpec:
         return self.eps0 * self.eps_decay ** cycle
 
 
-def designed_pencil(spec: SequenceSpec, keep_vectors: bool = True) -> Pencil:
-    """Cycle-0 pencil in designed form: exact spectrum and eigenvectors are known."""
-    import torch
+def designed_pencil(spec: SequenceSpec, keep_vectors: bool = True, vector_cols: Optional[int] = None) -> Pencil:
+    """Cycle-0 pencil in designed form: exact spectrum and eigenvectors are known (the first
+    ``vector_cols`` eigenvectors, all by default)."""
     n = spec.n
     lam = split_spectrum(_rng(spec.seed, _STREAM_LAM), n, spec.n_low)
-    q = haar_unitary_t(_rng(spec.seed, _STREAM_Q), n)
-    lt = torch.from_numpy(lam)
+    q = StructuredUnitary(_rng(spec.seed, _STREAM_Q), n)
+    m = n if vector_cols is None else vector_cols
+    qm = q.apply(np.eye(n, m, dtype=np.complex128)) if keep_vectors else None
+    a = q.sandwich(lam)
     if spec.generalized:
-        s = overlap_matrix(_rng(spec.seed, _STREAM_G), n)
-        lchol = torch.linalg.cholesky(torch.from_numpy(s))
-        lq = lchol @ q
-        a = (lq * lt[None, :]) @ lq.conj().T
-        x = torch.linalg.solve_triangular(lchol.conj().T, q, upper=True) if keep_vectors else None
+        ov = overlap(_rng(spec.seed, _STREAM_G), n)
+        s = ov.S
+        a = ov.sandwich_half(a)
+        x = ov.apply_mhalf(qm) if keep_vectors else None
     else:
         s = None
-        a = (q * lt[None, :]) @ q.conj().T
-        x = q if keep_vectors else None
-    a = 0.5 * (a + a.conj().T)
-    return Pencil(A=_to_fortran(a), S=s, lam_exact=lam, X_exact=None if x is None else _to_fortran(x), cycle=0)
+        x = qm
+    return Pencil(A=a, S=s, lam_exact=lam, X_exact=x, cycle=0)
 
 
 def sequence(spec: SequenceSpec, keep_vectors: bool = False) -> Iterator[Pencil]:
@@ -165,8 +309,9 @@ def sequence(spec: SequenceSpec, keep_vectors: bool = False) -> Iterator[Pencil]
     a = p.A
     for ell in range(1, spec.cycles):
         e = hermitian_noise(_rng(spec.seed, _STREAM_E0 + ell - 1), spec.n)
-        e *= spec.eps(ell - 1)
-        a = a + e
+        a_next = empty_f(spec.n, spec.n)
+        _tt(a_next).copy_(_tt(a))
+        a = add_(a_next, e, spec.eps(ell - 1))
         yield Pencil(A=a, S=p.S, lam_exact=None, X_exact=None, cycle=ell)
 
 
@@ -217,17 +362,15 @@ def kpoint_sizes(count: int = 32, seed: int = 0, n_lo: int = 1500, n_hi: int = 6
     return [int(v) for v in rng.integers(n_lo, n_hi + 1, size=count)]
 
 
-def kpoint_problem(k: int, n: int, seed: int = 0, eps: float = 1e-3) -> KPointProblem:
+def kpoint_problem(k: int, n: int, seed: int = 0, eps: float = 1e-3, min_nex: int = 0) -> KPointProblem:
     """k-point problem k of one SCF cycle: a designed generalized pencil perturbed by eps, warm start
-    from the unperturbed eigenvectors.  nev = ceil(0.06 n), nex = ceil(0.2 nev)."""
+    from the unperturbed eigenvectors.  nev = ceil(0.06 n), nex = max(ceil(0.2 nev), min_nex)."""
     nev = int(math.ceil(0.06 * n))
-    nex = int(math.ceil(0.2 * nev))
+    nex = max(int(math.ceil(0.2 * nev)), int(min_nex))
     spec = SequenceSpec(n=n, n_low=int(math.ceil(0.05 * n)), generalized=True, cycles=1, eps0=eps,
                         eps_decay=1.0, seed=1000 * (seed + 1) + k, nev=nev, nex=nex, deg=12)
-    p = designed_pencil(spec, keep_vectors=True)
-    e = hermitian_noise(_rng(spec.seed, _STREAM_E0), n)
-    e *= eps
-    a = p.A + e
     m = nev + nex
+    p = designed_pencil(spec, keep_vectors=True, vector_cols=m)
+    a = add_(p.A, hermitian_noise(_rng(spec.seed, _STREAM_E0), n), eps)
     return KPointProblem(n=n, nev=nev, nex=nex, A=a, S=p.S, X0=np.asfortranarray(p.X_exact[:, :m]),
                          lam_prev=p.lam_exact[:m].copy())

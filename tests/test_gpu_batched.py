@@ -1,0 +1,174 @@
+"""GPU: the batched solver (k-points of one self-consistent cycle, Section 2.1) through the C ABI.
+
+Every problem solved in a batch must match the CPU oracle's solution of the same problem and the
+library's own single-problem solve (eigenvalues to 1e-10 relative, residuals <= 1e-10,
+S-orthonormal vectors); the persistent launch, the graph replay and every tile plan must give the
+same numbers as each other.  Problems are the seeded k-point pencils of synth.kpoint_problem
+(designed generalized pencil perturbed by eps = 1e-3, warm start from the unperturbed vectors).
+"""
+import numpy as np
+import pytest
+
+from paper_1206_3768_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1206_3768_amd import chfsi
+    h = chfsi.Handle(0)
+    yield h
+    h.close()
+
+
+def _problems(sizes, seed=5, min_nex=0):
+    return [synth.kpoint_problem(k, n, seed=seed, min_nex=min_nex) for k, n in enumerate(sizes)]
+
+
+def _upload(kps):
+    from paper_1206_3768_amd import chfsi
+    out = []
+    for kp in kps:
+        out.append(dict(A=chfsi.to_device(kp.A), S=chfsi.to_device(kp.S), X=chfsi.to_device(kp.X0),
+                        nev=kp.nev, nex=kp.nex, x_is_guess=1))
+    return out
+
+
+def _params(**kw):
+    from paper_1206_3768_amd import chfsi
+    base = dict(nev=1, nex=0, deg=12, tol=1e-10, seed=4)
+    base.update(kw)
+    return chfsi.default_params(**base)
+
+
+def _check_pair_set(kp, lam, resid, X, ref_lam):
+    nev = kp.nev
+    assert np.all(np.abs(lam[:nev] - ref_lam[:nev]) <= 1e-10 * np.maximum(np.abs(ref_lam[:nev]), 1e-3)), \
+        np.max(np.abs(lam[:nev] - ref_lam[:nev]))
+    assert resid[:nev].max() <= 1e-10
+    G = X.conj().T @ (kp.S @ X)
+    assert np.abs(G - np.eye(X.shape[1])).max() <= 1e-12
+    # residuals recomputed on the host, independently of the library
+    nrm = np.linalg.norm(kp.A, 2)
+    R = kp.A @ X[:, :nev] - (kp.S @ X[:, :nev]) * lam[:nev]
+    assert (np.linalg.norm(R, axis=0) / nrm).max() <= 2e-10
+
+
+def test_batched_matches_oracle_and_single_solves(hd, orc):
+    from paper_1206_3768_amd import chfsi
+    sizes = [300, 457, 512, 389, 620, 333]
+    kps = _problems(sizes)
+    probs = _upload(kps)
+    st, res = hd.solve_batched(probs, _params())
+    assert st == 0, chfsi.status_string(st)
+    info = hd.batched_info()
+    assert info["graph_launches"] >= 1 and info["kernel_launches"] >= 12 and info["filter_ms"] > 0
+    assert info["filter_flops"] > 0
+    for kp, pr, r in zip(kps, probs, res):
+        assert r.status == 0 and r.stats["loops"] >= 1
+        X = chfsi.to_numpy(pr["X"])
+        ref = orc.solve(kp.A, kp.S, nev=kp.nev, nex=kp.nex, deg=12, tol=1e-10, X0=kp.X0, seed=4)
+        assert ref.status == 0
+        _check_pair_set(kp, r.lam, r.resid, X, ref.lam)
+        assert abs(r.stats["loops"] - ref.stats["loops"]) <= 1
+        # the single-problem path of the library on the same problem
+        dX = chfsi.to_device(kp.X0)
+        one = hd.solve(chfsi.to_device(kp.A), chfsi.to_device(kp.S), dX, True,
+                       _params(nev=kp.nev, nex=kp.nex))
+        assert one.status == 0
+        assert np.all(np.abs(one.lam[:kp.nev] - r.lam[:kp.nev]) <= 1e-12 * np.maximum(np.abs(r.lam[:kp.nev]), 1e-3))
+        assert r.stats["matvecs"] == one.stats["matvecs"]
+
+
+@pytest.mark.parametrize("bm,bn", [(64, 64), (64, 32), (32, 64), (32, 32)])
+def test_batched_every_tile_plan_and_graph_replay_agree(hd, bm, bn):
+    from paper_1206_3768_amd import chfsi
+    kps = _problems([256, 401, 333], seed=6)
+    results = []
+    for use_graph in (True, False):
+        hd.set_batched_plan(bm, bn, use_graph=use_graph)
+        probs = _upload(kps)
+        st, res = hd.solve_batched(probs, _params())
+        assert st == 0
+        info = hd.batched_info()
+        assert (info["graph_launches"] > 0) == use_graph
+        results.append([(r.lam.copy(), chfsi.to_numpy(p["X"])) for r, p in zip(res, probs)])
+    hd.set_batched_plan(64, 64, use_graph=True)
+    for (la, Xa), (lb, Xb) in zip(*results):
+        assert np.array_equal(la, lb) and np.array_equal(Xa, Xb)   # same kernels, same order: bit-equal
+    for kp, (lam, X) in zip(kps, results[0]):
+        ev = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(kp.S), np.linalg.solve(
+            np.linalg.cholesky(kp.S), kp.A).conj().T))
+        assert np.all(np.abs(lam[:kp.nev] - ev[:kp.nev]) <= 1e-10 * np.maximum(np.abs(ev[:kp.nev]), 1e-3))
+
+
+def test_autotune_batched_picks_a_valid_plan(hd):
+    kps = _problems([512, 700, 640, 555], seed=7)
+    probs = _upload(kps)
+    (bm, bn), ms = hd.autotune_batched(probs)
+    assert bm in (32, 64) and bn in (32, 64) and ms > 0
+    st, res = hd.solve_batched(probs, _params())
+    assert st == 0 and all(r.resid[:kp.nev].max() <= 1e-10 for r, kp in zip(res, kps))
+    hd.set_batched_plan(64, 64, use_graph=True)
+
+
+def test_batched_analytic_degrees_and_cold_start(hd, orc):
+    from paper_1206_3768_amd import chfsi
+    kps = _problems([300, 360], seed=8)
+    probs = _upload(kps)
+    for p in probs:
+        p["x_is_guess"] = 0
+    st, res = hd.solve_batched(probs, _params(degree_policy=chfsi.DEG_ANALYTIC))
+    assert st == 0
+    for kp, pr, r in zip(kps, probs, res):
+        ref = orc.solve(kp.A, kp.S, nev=kp.nev, nex=kp.nex, deg=12, tol=1e-10, seed=4, degree_policy=1)
+        assert ref.status == 0
+        _check_pair_set(kp, r.lam, r.resid, chfsi.to_numpy(pr["X"]), ref.lam)
+
+
+def test_batched_more_problems_than_one_launch_holds(hd):
+    """70 small problems: two chunks (64 + 6) of persistent launches.  At these orders the k-point
+    rule would give a search block of nev + 1 or 2 columns, too thin to converge within max_loops
+    in the clustered low spectrum, so every problem gets at least 8 extra columns."""
+    from paper_1206_3768_amd import chfsi
+    rng = np.random.default_rng(3)
+    sizes = [int(v) for v in rng.integers(60, 120, size=70)]
+    kps = _problems(sizes, seed=9, min_nex=8)
+    probs = _upload(kps)
+    st, res = hd.solve_batched(probs, _params())
+    assert st == 0
+    for kp, pr, r in zip(kps, probs, res):
+        X = chfsi.to_numpy(pr["X"])
+        ev = np.sort(np.real(np.linalg.eigvals(np.linalg.solve(kp.S, kp.A))))
+        assert np.all(np.abs(r.lam[:kp.nev] - ev[:kp.nev]) <= 1e-10 * np.maximum(np.abs(ev[:kp.nev]), 1e-3))
+        assert r.resid[:kp.nev].max() <= 1e-10
+        assert np.abs(X.conj().T @ kp.S @ X - np.eye(X.shape[1])).max() <= 1e-12
+
+
+def test_batched_error_in_one_problem_leaves_the_others(hd):
+    from paper_1206_3768_amd import chfsi
+    kps = _problems([200, 240, 260], seed=10)
+    probs = _upload(kps)
+    bad = kps[1].S.copy(order="F")
+    bad[0, 0] = -5.0                      # not positive definite
+    probs[1]["S"] = chfsi.to_device(bad)
+    st, res = hd.solve_batched(probs, _params())
+    assert st == chfsi.ERR_NOT_HPD
+    assert res[1].status == chfsi.ERR_NOT_HPD
+    assert res[0].status == 0 and res[2].status == 0
+    assert res[0].resid[:kps[0].nev].max() <= 1e-10 and res[2].resid[:kps[2].nev].max() <= 1e-10
+
+
+def test_batched_rejects_low_precision_and_bad_arguments(hd):
+    from paper_1206_3768_amd import chfsi
+    kps = _problems([128], seed=11)
+    probs = _upload(kps)
+    st, _ = hd.solve_batched(probs, _params(filter_precision=chfsi.FP32))
+    assert st == chfsi.ERR_ARG
+    probs[0]["nev"] = 0
+    st, _ = hd.solve_batched(probs, _params())
+    assert st == chfsi.ERR_ARG
