@@ -155,7 +155,7 @@ chfsi_status chfsi_solve_batched(chfsi_handle h, int count, const chfsi_problem*
 /* Tile plan of the persistent multi-problem filter kernel of chfsi_solve_batched (bm, bn in
  * {32, 64}; ksplit and fused are ignored; plan NULL keeps the current one), whether each loop's
  * filter steps replay a captured HIP graph (use_graph != 0, the default) or are launched one by
- * one, and over how many streams (lanes, 1 .. 8; 0 keeps the current value, default 4) the
+ * one, and over how many streams (lanes, 1 .. 8; 0 keeps the current value, default 1) the
  * per-problem dense steps are spread. */
 chfsi_status chfsi_set_batched_plan(chfsi_handle h, const chfsi_tile_plan* plan, int use_graph, int lanes);
 

@@ -227,7 +227,7 @@ chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
     s.ldh = s.lda;
     s.hi[0] = 0;
     if (s.S) {
-        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.info, s.hi));
+        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.info, s.hi, b.gw));
         s.H = b.H;
         s.ldh = n;
     }
@@ -644,7 +644,7 @@ chfsi_status chfsi_reduce(chfsi_handle h, int n, const void* A, int lda, const v
     if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
     SolveBufs b;
     TRYS(prepare(h, b, 1, 1, 1, false, CHFSI_FP64));
-    TRYS(step_reduce(h, n, (const zd*)A, lda, (const zd*)S, lds, (zd*)H, (zd*)L, b.info));
+    TRYS(step_reduce(h, n, (const zd*)A, lda, (const zd*)S, lds, (zd*)H, (zd*)L, b.info, b.gw));
     TRY(hipStreamSynchronize(h->stream));
     return CHFSI_SUCCESS;
 }
@@ -691,7 +691,7 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_handle h, int n, const void* H, int ldh, 
     SolveBufs b;
     TRYS(prepare(h, b, n, m, 1, false, CHFSI_FP64));
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, h->stream));
-    std::vector<double> ehost((size_t)eig_padded_order(m) + 1);
+    std::vector<double> ehost(eig_host_doubles(m));
     TRYS(step_rayleigh_ritz(h, n, (const zd*)H, ldh, m, (zd*)Y, ldy, b.HY, b.T, b.G, b.theta, b.r, b.eigw, ehost.data(),
                             b.gw, nullptr));
     int info = 0;

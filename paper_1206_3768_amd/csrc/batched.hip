@@ -25,7 +25,7 @@ namespace {
 
 constexpr int BATCH_MAXP = 64;   // problems per persistent launch (larger batches are chunked)
 constexpr int NUM_XCD = 8;       // gfx950: workgroup w runs on XCD w % 8
-constexpr int MAX_LANES = 8;     // streams for the per-problem dense steps (default 4)
+constexpr int MAX_LANES = 8;     // streams for the per-problem dense steps (default 1)
 
 // One problem of a filter step: Yo = alpha (H Yk - shift Yk) + beta Yp on columns [0, w).
 struct BatchProb {

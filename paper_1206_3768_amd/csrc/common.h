@@ -99,11 +99,17 @@ int launch_permute_cols(hipStream_t s, int n, int m, const zd* src, int lds, zd*
 int launch_copy_cols_flag(hipStream_t s, int n, int m, const zd* src, int lds, zd* dst, int ldd, const int* flag);
 int launch_copy_cols_flag_c(hipStream_t s, int n, int m, const zf* src, int lds, zf* dst, int ldd, const int* flag);
 
+// ---- Cholesky factorisation (chol.hip) -----------------------------------------------------------
+// A = L L^H in place (lower triangle read and written), blocked with 64-column panels; *info
+// (device, zero on entry) receives the first non-positive pivot, 1-based.
+int chol_lower(hipStream_t s, int n, zd* A, int lda, int* info, const GemmWs& gw);
+
 // ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
 int eig_padded_order(int m);
 size_t eig_work_bytes(int m);
+size_t eig_host_doubles(int m);
 // G (m x m, device) <- W with G = W diag(theta) W^H, theta ascending (device).  host: at least
-// eig_padded_order(m) + 1 doubles.  Returns hipError_t as int, -1 when the sweeps did not converge.
+// eig_host_doubles(m) doubles.  Returns hipError_t as int, -1 when the sweeps did not converge.
 int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps);
 
 // ---- degree network (mlp.hip) -------------------------------------------------------------------

@@ -109,14 +109,15 @@ struct chfsi_handle_s {
     double batch_filter_ms = 0, batch_flops = 0;
     int batch_graph_launches = 0, batch_kernel_launches = 0;
     bool batch_use_graph = true;   // replay each loop's filter steps as one captured graph
-    int batch_lanes = 4;           // streams the problems of a batch are spread over
+    int batch_lanes = 1;           // streams the problems of a batch are spread over
     hipEvent_t bev[3] = {nullptr, nullptr, nullptr};   // filter start / end, lane join
 };
 
 // steps (solver.hip)
-chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, int* info_dev);
+chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, int* info_dev,
+                         const GemmWs& gw);
 chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                                 int* info_dev, int* info_host);
+                                 int* info_dev, int* info_host, const GemmWs& gw);
 chfsi_status step_lanczos_enqueue(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed,
                                   zd* LV, zd* w, zd* c, double* coef_dev, double* hal, double* hbe);
 chfsi_status lanczos_finish(int k, const double* hal, const double* hbe, std::vector<double>& theta,

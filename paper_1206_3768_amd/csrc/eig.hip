@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <numeric>
 #include <vector>
 
@@ -59,48 +61,43 @@ __device__ inline zd zaxpy(double c, zd x, zd s, zd y) { zd p = zmul(s, y); retu
 // global index of subproblem index u for the block pair (P, Q)
 __device__ inline int sub_index(int P, int Q, int u) { return u < EB ? P * EB + u : Q * EB + (u - EB); }
 
-__global__ __launch_bounds__(256) void k_eig_pad(int m, int M, const zd* __restrict__ G, int ldg, zd* __restrict__ Gp,
-                                                 zd* __restrict__ Wp)
+// per column j < m of the Hermitian G: stat[j] = max_{i != j} |G_ij|, stat[m + j] = Re G_jj
+__global__ __launch_bounds__(256) void k_eig_rowstat(int m, const zd* __restrict__ G, int ldg, double* __restrict__ stat)
+{
+    __shared__ double sm[256];
+    const int j = blockIdx.x;
+    double o = 0;
+    for (int i = threadIdx.x; i < m; i += 256) {
+        if (i == j) continue;
+        const zd g = G[(size_t)i + (size_t)j * ldg];
+        o = fmax(o, sqrt(g.x * g.x + g.y * g.y));
+    }
+    sm[threadIdx.x] = o;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stat[j] = sm[0];
+        stat[m + j] = G[(size_t)j + (size_t)j * ldg].x;
+    }
+}
+
+// Gp (M x M) = [G(act, act) 0; 0 PAD I] for the k active indices act[0 .. k); Wp = I
+__global__ __launch_bounds__(256) void k_eig_compress(int k, int M, const zd* __restrict__ G, int ldg,
+                                                      const int* __restrict__ act, zd* __restrict__ Gp,
+                                                      zd* __restrict__ Wp)
 {
     const size_t total = (size_t)M * M;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % M), j = (int)(e / M);
         zd g = make_double2(0.0, 0.0);
-        if (i < m && j < m) g = G[(size_t)i + (size_t)j * ldg];
+        if (i < k && j < k) g = G[(size_t)act[i] + (size_t)act[j] * ldg];
         else if (i == j) g.x = PAD;
         if (i == j) g.y = 0.0;
         Gp[e] = g;
         Wp[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    }
-}
-
-// one workgroup: out[0] = max_i |G_ii|, out[1] = max_{i != j} |G_ij| over the leading m x m part
-__global__ __launch_bounds__(256) void k_eig_scale(int m, const zd* __restrict__ G, int ldg, double* out)
-{
-    __shared__ double sd[256], so[256];
-    double d = 0, o = 0;
-    for (int e = threadIdx.x; e < m * m; e += 256) {
-        const int i = e % m, j = e / m;
-        const zd g = G[(size_t)i + (size_t)j * ldg];
-        const double a = sqrt(g.x * g.x + g.y * g.y);
-        if (i == j) d = fmax(d, fabs(g.x));
-        else o = fmax(o, a);
-    }
-    sd[threadIdx.x] = d;
-    so[threadIdx.x] = o;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
-            so[threadIdx.x] = fmax(so[threadIdx.x], so[threadIdx.x + s]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        out[0] = sd[0];
-        out[1] = so[0];
-        const double t = 1e-14 * fmax(sd[0], so[0]);   // rotation threshold on |g|
-        out[2] = t * t;                                  // compared with |g|^2
     }
 }
 
@@ -122,7 +119,7 @@ __global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, con
         V[u * EP + v] = make_double2(u == v ? 1.0 : 0.0, 0.0);
     }
     if (tid < ES) rot[tid] = 0;
-    const double tol2 = scale[2];
+    const double tol2 = scale[1];   // squared rotation threshold
     // this thread's 2 x 2 block (pair bi, pair bj) and its two rows of V (rows bi, bi + 16; pair bj)
     const int bi = tid / (ES / 2), bj = tid % (ES / 2);
     __syncthreads();
@@ -298,17 +295,22 @@ __global__ __launch_bounds__(256) void k_eig_maxreduce(int M, const double* __re
     if (threadIdx.x == 0) out[0] = sm[0];
 }
 
-// W(:, k) = Wp(0:m, perm[k]), theta[k] = diag[perm[k]] for k < m
-__global__ __launch_bounds__(256) void k_eig_gather(int m, int M, const zd* __restrict__ Wp, const int* __restrict__ perm,
-                                                    const double* __restrict__ diag, zd* __restrict__ W, int ldw,
-                                                    double* __restrict__ theta)
+// Eigenvectors of G in ascending order: column c of W is e_{-src[c]-1} when src[c] < 0 (a
+// deflated index) and otherwise column src[c] of Wp scattered to the rows act[0 .. k); theta[c] =
+// val[c].  pos[i] = position of row i in act, or -1.
+__global__ __launch_bounds__(256) void k_eig_expand(int m, int M, const zd* __restrict__ Wp, const int* __restrict__ src,
+                                                    const int* __restrict__ pos, const double* __restrict__ val,
+                                                    zd* __restrict__ W, int ldw, double* __restrict__ theta)
 {
     const size_t total = (size_t)m * m;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % m), k = (int)(e / m);
-        const int c = perm[k];
-        W[(size_t)i + (size_t)k * ldw] = Wp[(size_t)i + (size_t)c * M];
-        if (i == 0) theta[k] = diag[c];
+        const int i = (int)(e % m), c = (int)(e / m);
+        const int sc = src[c];
+        zd w = make_double2(0.0, 0.0);
+        if (sc < 0) w.x = (i == -sc - 1) ? 1.0 : 0.0;
+        else if (pos[i] >= 0) w = Wp[(size_t)pos[i] + (size_t)sc * M];
+        W[(size_t)i + (size_t)c * ldw] = w;
+        if (i == 0) theta[c] = val[c];
     }
 }
 
@@ -322,73 +324,117 @@ int grid_for(size_t n)
 
 int eig_padded_order(int m) { return ((m + ES - 1) / ES) * ES; }
 
+size_t eig_host_doubles(int m) { return 3 * (size_t)eig_padded_order(m) + 8; }
+
 size_t eig_work_bytes(int m)
 {
     const size_t M = (size_t)eig_padded_order(m);
-    return (2 * M * M + (M / ES) * ES * ES) * sizeof(zd) + (2 * M + 8) * sizeof(double) + M * sizeof(int) + 1024;
+    return (2 * M * M + (M / ES) * ES * ES) * sizeof(zd) + (4 * M + 16) * sizeof(double) + 4 * M * sizeof(int) + 1024;
 }
 
 // Eigen-decomposition G = W diag(theta) W^H of the Hermitian m x m matrix G (device, leading
 // dimension ldg): on return G holds W (columns ascending in theta), theta[m] (device) the
-// eigenvalues.  work: eig_work_bytes(m) bytes of device memory; host: M + 1 doubles of host memory
-// (pinned for speed) with M = eig_padded_order(m).  *sweeps receives the sweeps taken.  Returns a
-// hipError_t as int, or -1 when 40 sweeps did not reach the threshold.
+// eigenvalues.  Indices whose whole off-diagonal row is below the stopping threshold are already
+// eigenpairs of G to that accuracy (deflated): block Jacobi runs on the remaining k x k part only,
+// which in the late loops of a solve is a small fraction of m.  work: eig_work_bytes(m) bytes of
+// device memory; host: eig_host_doubles(m) doubles of host memory (pinned for speed).
+// *sweeps receives the sweeps taken.  Returns a hipError_t as int, or -1 when 40 sweeps did not
+// reach the threshold.
 int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps)
 {
+    if (sweeps) *sweeps = 0;
     if (m <= 0) return 0;
-    const int M = eig_padded_order(m), nb = M / EB, npair = nb / 2;
+    const int Mm = eig_padded_order(m);
     char* w = (char*)work;
     zd* Gp = (zd*)w;
-    zd* Wp = Gp + (size_t)M * M;
-    zd* J = Wp + (size_t)M * M;
-    double* dbuf = (double*)(J + (size_t)npair * ES * ES);   // [0, 8): scale, [8, 8 + M): column maxima
-    double* scale = dbuf;
-    double* colmax = dbuf + 8;
-    double* outd = colmax + M;                                // off max + diagonal [M + 1]
-    int* perm = (int*)(outd + M + 1);
-    hipLaunchKernelGGL(k_eig_scale, dim3(1), dim3(256), 0, s, m, (const zd*)G, ldg, scale);
-    hipLaunchKernelGGL(k_eig_pad, dim3(grid_for((size_t)M * M)), dim3(256), 0, s, m, M, (const zd*)G, ldg, Gp, Wp);
-    double sc[3] = {0, 0, 0};
-    int rc = (int)hipMemcpyAsync(sc, scale, sizeof(sc), hipMemcpyDeviceToHost, s);
+    zd* Wp = Gp + (size_t)Mm * Mm;
+    zd* J = Wp + (size_t)Mm * Mm;
+    double* dbuf = (double*)(J + (size_t)(Mm / ES) * ES * ES);
+    double* stat = dbuf;                  // [2 m]: row off-diagonal maxima, diagonal
+    double* colmax = dbuf + 2 * Mm;       // [Mm]
+    double* outd = colmax + Mm;           // [Mm + 1]: off max, diagonal of Gp
+    double* scl = outd + Mm + 1;          // [4]: scale, threshold^2
+    int* iw = (int*)(scl + 4);            // act [Mm], src [Mm], pos [Mm]
+    hipLaunchKernelGGL(k_eig_rowstat, dim3(m), dim3(256), 0, s, m, (const zd*)G, ldg, stat);
+    int rc = (int)hipMemcpyAsync(host, stat, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, s);
     if (rc == 0) rc = (int)hipStreamSynchronize(s);
     if (rc != 0) return rc;
-    const double stop = 5e-14 * std::max(sc[0], sc[1]);
+    double sc = 0;
+    for (int j = 0; j < m; ++j) sc = std::max(sc, std::max(host[j], std::fabs(host[m + j])));
+    const double stop = 5e-14 * sc;        // off-diagonal target
+    const double rot = 1e-14 * sc;         // rotations below this are skipped
+    std::vector<int> act, pos(m, -1);
+    std::vector<double> dval(m);
+    for (int j = 0; j < m; ++j) {
+        dval[j] = host[m + j];
+        if (host[j] > stop) { pos[j] = (int)act.size(); act.push_back(j); }
+    }
+    const int k = (int)act.size();
+    std::vector<double> aval;              // eigenvalues of the active part (compressed order)
     int sw = 0;
-    bool done = !(sc[1] > stop);   // already diagonal
-    if (done) {
-        hipLaunchKernelGGL(k_eig_colmax, dim3(M), dim3(256), 0, s, m, M, (const zd*)Gp, colmax, outd);
-        rc = (int)hipMemcpyAsync(host, outd, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, s);
-        if (rc == 0) rc = (int)hipStreamSynchronize(s);
+    if (k > 0) {
+        const int M = eig_padded_order(k), nb = M / EB, npair = nb / 2;
+        // staged through the (pinned) host buffer; the first sweep's synchronisation retires the
+        // copies before that part of the buffer is written again
+        int* hact = (int*)(host + Mm + 8);
+        double* hs = host + 2 * Mm + 8;
+        std::memcpy(hact, act.data(), sizeof(int) * k);
+        hs[0] = sc;
+        hs[1] = rot * rot;
+        rc = (int)hipMemcpyAsync(iw, hact, sizeof(int) * k, hipMemcpyHostToDevice, s);
+        if (rc == 0) rc = (int)hipMemcpyAsync(scl, hs, sizeof(double) * 2, hipMemcpyHostToDevice, s);
         if (rc != 0) return rc;
-    }
-    while (!done && sw < 40) {
-        for (int r = 0; r < nb - 1; ++r) {
-            hipLaunchKernelGGL(k_eig_inner, dim3(npair), dim3(256), 0, s, M, nb, r, (const zd*)Gp, J,
-                               (const double*)scale);
-            hipLaunchKernelGGL(k_eig_apply, dim3(npair * npair + (M / ES) * npair), dim3(256), 0, s, M, nb, r, Gp, Wp,
-                               (const zd*)J);
+        hipLaunchKernelGGL(k_eig_compress, dim3(grid_for((size_t)M * M)), dim3(256), 0, s, k, M, (const zd*)G, ldg,
+                           (const int*)iw, Gp, Wp);
+        bool done = false;
+        while (!done && sw < 40) {
+            for (int r = 0; r < nb - 1; ++r) {
+                hipLaunchKernelGGL(k_eig_inner, dim3(npair), dim3(256), 0, s, M, nb, r, (const zd*)Gp, J,
+                                   (const double*)scl);
+                hipLaunchKernelGGL(k_eig_apply, dim3(npair * npair + (M / ES) * npair), dim3(256), 0, s, M, nb, r,
+                                   Gp, Wp, (const zd*)J);
+            }
+            ++sw;
+            hipLaunchKernelGGL(k_eig_colmax, dim3(M), dim3(256), 0, s, k, M, (const zd*)Gp, colmax, outd);
+            hipLaunchKernelGGL(k_eig_maxreduce, dim3(1), dim3(256), 0, s, M, (const double*)colmax, outd);
+            rc = (int)hipMemcpyAsync(host, outd, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, s);
+            if (rc == 0) rc = (int)hipStreamSynchronize(s);
+            if (rc != 0) return rc;
+            done = host[0] <= stop;
         }
-        ++sw;
-        hipLaunchKernelGGL(k_eig_colmax, dim3(M), dim3(256), 0, s, m, M, (const zd*)Gp, colmax, outd);
-        hipLaunchKernelGGL(k_eig_maxreduce, dim3(1), dim3(256), 0, s, M, (const double*)colmax, outd);
-        rc = (int)hipMemcpyAsync(host, outd, sizeof(double) * (M + 1), hipMemcpyDeviceToHost, s);
-        if (rc == 0) rc = (int)hipStreamSynchronize(s);
-        if (rc != 0) return rc;
-        done = host[0] <= stop;
+        if (sweeps) *sweeps = sw;
+        if (!done) return -1;
+        aval.assign(host + 1, host + 1 + k);
     }
-    if (sweeps) *sweeps = sw;
-    if (!done) return -1;
-    // ascending order of the diagonal (padded indices last)
-    std::vector<int> ord(M);
+    // ascending order over deflated and active eigenvalues
+    std::vector<int> ord(m);
     std::iota(ord.begin(), ord.end(), 0);
-    const double* d = host + 1;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] < d[b]; });
-    // `ord` must outlive the copy: the stream is synchronised before returning
-    rc = (int)hipMemcpyAsync(perm, ord.data(), sizeof(int) * m, hipMemcpyHostToDevice, s);
+    std::vector<int> defl;                 // deflated indices in increasing order
+    for (int j = 0; j < m; ++j)
+        if (pos[j] < 0) defl.push_back(j);
+    // candidate c < k: active eigenpair c; c >= k: deflated index defl[c - k]
+    auto value = [&](int c) { return c < k ? aval[c] : dval[defl[c - k]]; };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return value(a) < value(b); });
+    // host staging: src [m], pos [m] as ints, values [m] as doubles
+    int* hsrc = (int*)(host + Mm + 8);
+    int* hpos = hsrc + m;
+    double* hval = host + 2 * Mm + 8;
+    for (int c = 0; c < m; ++c) {
+        const int o = ord[c];
+        hsrc[c] = o < k ? o : -(defl[o - k] + 1);
+        hval[c] = value(o);
+    }
+    std::memcpy(hpos, pos.data(), sizeof(int) * m);
+    int* dsrc = iw + Mm;                   // src [m] then pos [m], one copy
+    int* dpos = dsrc + m;
+    double* dval_d = colmax;               // reused: [m] values in output order
+    rc = (int)hipMemcpyAsync(dsrc, hsrc, sizeof(int) * 2 * m, hipMemcpyHostToDevice, s);
+    if (rc == 0) rc = (int)hipMemcpyAsync(dval_d, hval, sizeof(double) * m, hipMemcpyHostToDevice, s);
     if (rc != 0) return rc;
-    hipLaunchKernelGGL(k_eig_gather, dim3(grid_for((size_t)m * m)), dim3(256), 0, s, m, M, (const zd*)Wp,
-                       (const int*)perm, (const double*)(outd + 1), G, ldg, theta);
+    const int Mk = eig_padded_order(std::max(k, 1));
+    hipLaunchKernelGGL(k_eig_expand, dim3(grid_for((size_t)m * m)), dim3(256), 0, s, m, Mk, (const zd*)Wp,
+                       (const int*)dsrc, (const int*)dpos, (const double*)dval_d, G, ldg, theta);
     rc = (int)hipGetLastError();
-    if (rc == 0) rc = (int)hipStreamSynchronize(s);
+    if (rc == 0) rc = (int)hipStreamSynchronize(s);   // the host staging must outlive the copies
     return rc;
 }

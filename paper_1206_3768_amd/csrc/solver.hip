@@ -2,7 +2,7 @@
 //
 // The solver follows Algorithm 1 (Chebyshev filtered subspace iteration with locking) inside the
 // reduction of Section 3.2:
-//   reduction      S = L L^H, H = L^{-1} A L^{-H}          (rocSOLVER potrf + rocBLAS trsm)
+//   reduction      S = L L^H, H = L^{-1} A L^{-H}          (own blocked Cholesky + rocBLAS trsm)
 //   Lanczos        k steps, full reorthogonalisation      (own kernels; k x k eig on the host)
 //   loop           filter -> orthonormalise -> Rayleigh-Ritz -> residuals -> lock prefix
 //   back-transform X = L^{-H} Y and ||A x - lambda S x|| / ||A||_lo verification
@@ -10,7 +10,6 @@
 // the m_a Ritz values and residual norms it needs for the locking decision.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -319,12 +318,12 @@ static inline const rocblas_double_complex* rbz(const zd* p) { return reinterpre
 // whole reduction; the Cholesky info word is copied to *info_host (host memory, valid after the
 // stream has been synchronised; nonzero = S not positive definite, H then meaningless).
 chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                                 int* info_dev, int* info_host)
+                                 int* info_dev, int* info_host, const GemmWs& gw)
 {
     hipStream_t st = h->stream;
     TRY(launch_zlacpy(st, n, n, S, lds, L, n));
     TRY(hipMemsetAsync(info_dev, 0, sizeof(int), st));
-    TRYRB(rocsolver_zpotrf(h->rb, rocblas_fill_lower, n, rbz(L), n, info_dev));
+    TRY(chol_lower(st, n, L, n, info_dev, gw));
     TRY(hipMemcpyAsync(info_host, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     TRY(launch_zero_upper(st, n, L, n));
     TRY(launch_zlacpy(st, n, n, A, lda, H, n));
@@ -338,10 +337,10 @@ chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, co
 }
 
 chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                         int* info_dev)
+                         int* info_dev, const GemmWs& gw)
 {
     int info = 0;
-    chfsi_status s = step_reduce_enqueue(h, n, A, lda, S, lds, H, L, info_dev, &info);
+    chfsi_status s = step_reduce_enqueue(h, n, A, lda, S, lds, H, L, info_dev, &info, gw);
     if (s != CHFSI_SUCCESS) return s;
     TRY(hipStreamSynchronize(h->stream));
     return info != 0 ? CHFSI_ERR_NOT_HPD : CHFSI_SUCCESS;
@@ -424,8 +423,9 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
     for (int pass = 0; pass < 3; ++pass) {
         TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, Y, ldy, 0.0, G, ma, gw));
         if (pass == 0) TRY(launch_add_diag_const(st, ma, G, ma, shift));
-        TRYRB(rocsolver_zpotrf(h->rb, rocblas_fill_upper, ma, rbz(G), ma, info_dev + pass));
-        TRYRB(rocblas_ztrsm(h->rb, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+        // G = L L^H = R^H R with R = L^H; Y <- Y R^{-1} = Y L^{-H}
+        TRY(chol_lower(st, ma, G, ma, info_dev + pass, gw));
+        TRYRB(rocblas_ztrsm(h->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
                             rocblas_diagonal_non_unit, n, ma, &one, rbz(G), ma, rbz(Y), ldy));
     }
     return CHFSI_SUCCESS;
@@ -434,7 +434,7 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
 // Rayleigh-Ritz on orthonormal Y (n x ma): HY = H Y, G = Y^H HY, G = W diag(theta) W^H (ascending,
 // phase-normalised W, block-Jacobi eigensolver of eig.hip), Y <- Y W, HY <- HY W, then
 // r_j = ||HY_j - theta_j Y_j||.  eig_work: eig_work_bytes(ma) bytes of device memory; eig_host:
-// eig_padded_order(ma) + 1 doubles of host memory.
+// eig_host_doubles(ma) doubles of host memory.
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY,
                                 zd* T, zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
                                 const GemmWs& gw, PhaseTimer* tm)

@@ -74,11 +74,8 @@ struct SolveState {
     double* h_be() { return hd + 2 * m + 2 + k; }  // [k]
     double* h_lam() { return hd + 2 * m + 2 + 2 * k; }       // [m]
     double* h_res() { return hd + 3 * m + 2 + 2 * k; }       // [m]
-    double* h_eig() { return hd + 4 * m + 2 + 2 * k; }       // [eig_padded_order(m) + 1]
-    static size_t pinned_doubles(int m, int k)
-    {
-        return 4 * (size_t)m + 2 + 2 * (size_t)k + (size_t)eig_padded_order(m) + 1;
-    }
+    double* h_eig() { return hd + 4 * m + 2 + 2 * k; }       // [eig_host_doubles(m)]
+    static size_t pinned_doubles(int m, int k) { return 4 * (size_t)m + 2 + 2 * (size_t)k + eig_host_doubles(m); }
     int ma() const { return m - nlocked; }
     zd* Ya() { return b.V + (size_t)nlocked * n; }
 };

@@ -245,6 +245,32 @@ def test_rayleigh_ritz_parity(hd, orc):
     assert np.allclose(r, rr, rtol=1e-8, atol=1e-14)
 
 
+def test_rayleigh_ritz_with_converged_columns(hd, orc):
+    """Columns that are exact eigenvectors give rows of Y^H H Y without off-diagonal coupling; the
+    eigensolver deflates them and must still return every pair, in ascending order."""
+    spec = synth.config_single_standard()
+    p = synth.designed_pencil(spec)
+    rng = np.random.default_rng(12)
+    exact = [3, 10, 11, 40, 200, 500]                      # eigenvector indices taken exactly
+    R = cgauss(512, 18, rng)
+    E = p.X_exact[:, exact]
+    R -= E @ (E.conj().T @ R)
+    R, _, _ = orc.qr(R)
+    Y = np.concatenate([R, E], axis=1)
+    Y = np.asfortranarray(Y[:, rng.permutation(Y.shape[1])])   # interleave exact and random columns
+    G = Y.conj().T @ p.A @ Y
+    w, W, _ = orc.jacobi(G)
+    Yr = Y @ W
+    rr = orc.residuals(p.A @ Yr, Yr, w)
+    dY = dev(Y)
+    th, r = hd.rayleigh_ritz(dev(p.A), dY)
+    assert np.max(np.abs(th - w)) <= 1e-13
+    assert all(np.min(np.abs(th - p.lam_exact[e])) <= 1e-13 for e in exact)
+    Yg = host(dY)
+    assert np.abs(Yg.conj().T @ Yg - np.eye(Y.shape[1])).max() <= 1e-13
+    assert np.allclose(r, rr, rtol=1e-6, atol=1e-13)
+
+
 # ---- the whole solver --------------------------------------------------------------------------
 
 def _angles(X, Y, S=None):
