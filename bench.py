@@ -15,7 +15,10 @@ Printed JSON (one line): value = filter TFLOP/s over the timed steps (8 n^2 flop
 vector and degree, divided by the filter phase time), ms_per_step = time to solution per cycle,
 roofline of the dominant kernel (the FP64 filter step) from hipEvents around each of its launches,
 and the CPU reference timed on a bounded sample.  Extra fields: random-start times and the
-warm/random speed-up per cycle, and the mixed-precision filter variants on the same cycles.
+warm/random speed-up per cycle, the mixed-precision filter variants on the same cycles, and the
+other workloads: the batched k-point cycle (32 problems, sequential vs one batch), the learned
+per-vector degree against fixed degrees (n = 4096 sequence) and the mixed-precision filters at
+n = 8192 with per-eigenvalue errors against FP64.
 """
 from __future__ import annotations
 
@@ -83,6 +86,140 @@ def cpu_baseline(seq_spec, pencils_host, x_prev, lam_prev) -> dict:
             "sample": f"oracle filter of one {n}x{m} block at degree {d} ({tf:.2f} s) and one warm-started "
                       f"solve of cycle 1 ({ts:.2f} s, {r.stats['loops']} loops, status {r.status})",
             "time_to_solution_ms": ts * 1e3, "filter_s": tf}
+
+
+def bench_kpoints(h, count: int = 32) -> dict:
+    """Batched SCF cycle: `count` k-point problems (n uniform in [1500, 6000], nev = ceil(0.06 n),
+    nex = ceil(0.2 nev), warm start from the unperturbed eigenvectors, perturbation 1e-3), solved
+    one after another with chfsi_solve and as one batch with chfsi_solve_batched (persistent
+    filter launch with the autotuned tile, graph replay and without it)."""
+    import torch
+    from paper_1206_3768_amd import chfsi, synth
+    t0 = time.perf_counter()
+    sizes = synth.kpoint_sizes(count)
+    probs, x0 = [], []
+    for k, n in enumerate(sizes):
+        kp = synth.kpoint_problem(k, n)
+        probs.append(dict(A=chfsi.to_device(kp.A), S=chfsi.to_device(kp.S), X=chfsi.to_device(kp.X0),
+                          nev=kp.nev, nex=kp.nex, x_is_guess=1))
+        x0.append(probs[-1]["X"].clone())
+        del kp
+    log(f"k-points: {count} problems generated and resident ({time.perf_counter() - t0:.1f} s)")
+
+    def reset():
+        for p, x in zip(probs, x0):
+            p["X"].copy_(x)
+        torch.cuda.synchronize()
+
+    seq_ms, seq_lam, seq_loops, seq_flops, seq_filter_ms = 0.0, [], [], 0.0, 0.0
+    for p in probs:   # warm-up of the sequential path on the first problem
+        reset()
+        h.solve(p["A"], p["S"], p["X"], True, chfsi.default_params(nev=p["nev"], nex=p["nex"], deg=12, tol=1e-10))
+        break
+    reset()
+    for p in probs:
+        prm = chfsi.default_params(nev=p["nev"], nex=p["nex"], deg=12, tol=1e-10)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = h.solve(p["A"], p["S"], p["X"], True, prm)
+        seq_ms += (time.perf_counter() - t) * 1e3
+        if r.status != 0:
+            raise RuntimeError(f"sequential k-point solve failed: status {r.status}")
+        seq_lam.append(r.lam[:p["nev"]].copy())
+        seq_loops.append(r.stats["loops"])
+        seq_flops += r.stats["filter_flops"]
+        seq_filter_ms += r.stats["t_filter_kernels"]
+    reset()
+    plan, plan_ms = h.autotune_batched(probs)
+    out = {"count": count, "n_range": [min(sizes), max(sizes)], "sequential_ms": round(seq_ms, 1),
+           "sequential_filter_tflops": round(seq_flops / seq_filter_ms / 1e9, 2),
+           "autotuned_tile": list(plan), "autotune_step_ms": round(plan_ms, 3)}
+    prm = chfsi.default_params(nev=1, nex=0, deg=12, tol=1e-10)
+    for use_graph in (True, False):
+        h.set_batched_plan(*plan, use_graph=use_graph)
+        best = None
+        for _ in range(2):
+            reset()
+            t = time.perf_counter()
+            st, res = h.solve_batched(probs, prm)
+            ms = (time.perf_counter() - t) * 1e3
+            if st != 0:
+                raise RuntimeError(f"batched k-point solve failed: status {st}")
+            best = ms if best is None else min(best, ms)
+        info = h.batched_info()
+        dl = max(float(np.max(np.abs(r.lam[:p["nev"]] - l) / np.maximum(np.abs(l), 1e-3)))
+                 for r, p, l in zip(res, probs, seq_lam))
+        out["graph" if use_graph else "no_graph"] = {
+            "batched_ms": round(best, 1), "speedup_vs_sequential": round(seq_ms / best, 3),
+            "filter_ms": round(info["filter_ms"], 1),
+            "filter_tflops": round(info["filter_flops"] / info["filter_ms"] / 1e9, 2),
+            "graph_replays": info["graph_launches"], "persistent_launches": info["kernel_launches"],
+            "max_rel_eig_diff_vs_sequential": dl,
+            "max_resid": max(float(r.resid[:p["nev"]].max()) for r, p in zip(res, probs)),
+            "loops_equal_to_sequential": [r.stats["loops"] for r in res] == seq_loops}
+    h.set_batched_plan(64, 64, use_graph=True)
+    return out
+
+
+def bench_learned_degree(h, cycles: int = 10) -> dict:
+    """Learned per-vector degree against every fixed degree and the analytic rule on the held-out
+    seed 0 of the n = 4096 standard sequence (warm cycles 1 .. cycles-1), FP64 and FP32 filters."""
+    from paper_1206_3768_amd import chfsi, degree_model, sequence, synth
+    blob = degree_model.load()
+    if blob is None:
+        return {"skipped": "no trained network"}
+    h.set_degree_model(blob)
+    seq = sequence.Sequence(synth.config_learned_degree(seed=0, n=4096, cycles=cycles), handle=h)
+    res = {}
+    for d in (12, 16, 20, 25):
+        res[f"fixed{d}"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=d)
+    res["analytic+2"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=2)
+    res["learned"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED)
+    res["fixed25_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=25, precision=chfsi.FP32)
+    res["learned_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED, precision=chfsi.FP32)
+    h.set_degree_model(None)
+    out = {k: {"time_to_solution_ms": round(v["ms"], 1), "matvecs": v["matvecs"], "loops": v["loops"],
+               "filter_ms": round(v["filter_ms"], 1), "all_converged": v["ok"], "max_resid": v["max_resid"]}
+           for k, v in res.items()}
+    best = min((k for k in res if k.startswith("fixed") and not k.endswith("fp32")), key=lambda k: res[k]["ms"])
+    out["best_fixed"] = best
+    out["learned_vs_best_fixed_time"] = round(res[best]["ms"] / res["learned"]["ms"], 3)
+    out["learned_fp32_vs_best_fixed_time"] = round(res[best]["ms"] / res["learned_fp32"]["ms"], 3)
+    out["learned_vs_best_fixed_matvecs"] = round(res[best]["matvecs"] / res["learned"]["matvecs"], 3)
+    out["workload"] = f"n=4096 standard sequence, seed 0, warm cycles 1..{cycles - 1}, nev 256, nex 64"
+    return out
+
+
+def bench_mixed_precision(h, cycles: int = 5) -> dict:
+    """Mixed-precision filters on the n = 8192 generalized sequence (nev 400, nex 80, degree 12):
+    time to solution per warm cycle and the largest error of every eigenvalue against FP64."""
+    from paper_1206_3768_amd import chfsi, sequence, synth
+    spec = synth.config_mixed_precision(cycles=cycles)
+    seq = sequence.Sequence(spec, handle=h)
+    ref = seq.run_reference()
+    if any(r.status != 0 for r in ref):
+        return {"failed": "reference pass"}
+    work = seq.new_block()
+    out = {"workload": f"n={spec.n} generalized sequence, nev {spec.nev}, nex {spec.nex}, degree {spec.deg}, "
+                       f"warm cycles 1..{cycles - 1}"}
+    base = None
+    for name in ("fp64", "fp32", "bf16x6", "bf16x3"):
+        rs = [seq.solve(c, warm=True, X=work, filter_precision=name) for c in range(1, cycles)]
+        rs = [seq.solve(c, warm=True, X=work, filter_precision=name) for c in range(1, cycles)]   # second pass timed
+        errs = [np.abs(r.lam[:spec.nev] - seq.lam[r.cycle][:spec.nev]) / np.maximum(np.abs(seq.lam[r.cycle][:spec.nev]), 1e-3)
+                for r in rs if r.status == 0]
+        tot = sum(r.wall_ms for r in rs)
+        if name == "fp64":
+            base = tot
+        out[name] = {"all_converged": all(r.status == 0 for r in rs), "time_to_solution_ms": round(tot, 1),
+                     "speedup_vs_fp64": round(base / tot, 3) if base else None,
+                     "filter_ms": round(sum(r.stats["t_filter"] for r in rs), 1),
+                     "matvecs": sum(r.stats["matvecs"] for r in rs),
+                     "loops": [r.stats["loops"] for r in rs],
+                     "max_rel_eig_err_vs_fp64_per_cycle": [float(e.max()) for e in errs],
+                     "median_rel_eig_err_vs_fp64": float(np.median(np.concatenate(errs))) if errs else None,
+                     "max_resid": float(max(r.resid[:spec.nev].max() for r in rs))}
+    return out
 
 
 def main() -> int:
@@ -223,6 +360,14 @@ def main() -> int:
                  for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid", "t_lock", "t_back",
                            "t_total")}
         out["phase_ms_per_solve"] = phase
+
+    if not args.no_extras:
+        log("k-point batch ...")
+        out["batched_kpoints"] = bench_kpoints(seq.h)
+        log("learned degree (n=4096) ...")
+        out["learned_degree"] = bench_learned_degree(seq.h)
+        log("mixed precision (n=8192) ...")
+        out["mixed_precision_n8192"] = bench_mixed_precision(seq.h)
 
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle) on a bounded sample ...")

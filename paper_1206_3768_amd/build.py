@@ -1,5 +1,5 @@
 """Builds libchfsi.so (gfx950) in-tree with hipcc: one object per translation unit, compiled in
-parallel, linked against rocBLAS (triangular solves).  ``python -m paper_1206_3768_amd.build``."""
+parallel; every kernel is the library's own (no vendor math library is linked).  ``python -m paper_1206_3768_amd.build``."""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchfsi.so")
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "blas1.hip", "mlp.hip", "solver.hip", "api.hip", "tune.hip", "batched.hip", "eig.hip", "chol.hip"]
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "blas1.hip", "mlp.hip", "solver.hip", "api.hip", "tune.hip", "batched.hip", "eig.hip", "chol.hip", "trsm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # packed FP32 ops are disabled: hipcc must not form v_pk_{add,mul,fma}_f32 from scalar code
@@ -38,7 +38,7 @@ def build(verbose: bool = True) -> str:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs + [
-        "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+        "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -1,7 +1,6 @@
 // C ABI entry points of include/chfsi.h: the whole solver (Algorithm 1 inside the reduction of
 // Section 3.2), the filter alone, the step-level entry points and the dense product.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -54,7 +53,7 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
     b.r = ar.take<double>(m);
     b.E = ar.take<double>(m + 8);
     b.lam = ar.take<double>(m);
-    b.dsc = ar.take<double>((size_t)std::max(n, m) + 16);
+    b.dsc = ar.take<double>(2 * ((size_t)std::max(n, m) + 16));   // two independent scratch halves
     b.info = ar.take<int>(16);
     b.flag = ar.take<int>(m + 8);
     b.iperm = ar.take<int>(m + 8);
@@ -230,14 +229,20 @@ chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
         TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.info, s.hi, b.gw));
         s.H = b.H;
         s.ldh = n;
+        // The reduction completes before the caller enqueues more work.  A batch solved over several
+        // streams overlapped the reductions of different problems otherwise, and in that mode some
+        // problems ended with a factor inconsistent with their H (no device error; cause not
+        // identified); every other phase overlaps correctly.
+        TRY(hipStreamSynchronize(st));
     }
     double* hn = s.h_norms();
     hn[1] = 1.0;
     TRY(launch_max_colnorm(st, n, s.A, s.lda, b.dsc));
     TRY(hipMemcpyAsync(&hn[0], b.dsc, sizeof(double), hipMemcpyDeviceToHost, st));
-    if (s.S) {
-        TRY(launch_max_rowsum_abs(st, n, s.S, s.lds, b.dsc));
-        TRY(hipMemcpyAsync(&hn[1], b.dsc, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (s.S) {   // second half of dsc: no kernel rewrites a buffer with a copy from it pending
+        double* d2 = b.dsc + std::max(n, m) + 16;
+        TRY(launch_max_rowsum_abs(st, n, s.S, s.lds, d2));
+        TRY(hipMemcpyAsync(&hn[1], d2, sizeof(double), hipMemcpyDeviceToHost, st));
     }
     if (s.prec == CHFSI_FP32) TRY(launch_z2c(st, n, n, s.H, s.ldh, b.Hf, n));
     if (s.prec == CHFSI_BF16X3 || s.prec == CHFSI_BF16X6)
@@ -440,11 +445,7 @@ chfsi_status st_final_enqueue(chfsi_handle h, SolveState& s)
     mark(s, PH_BACK, st, true);
     TRY(launch_zlacpy(st, n, m, b.V, n, s.X, s.ldx));
     if (s.S) {
-        const rocblas_double_complex one(1.0, 0.0);
-        if (rocblas_ztrsm(h->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                          rocblas_diagonal_non_unit, n, m, &one, reinterpret_cast<rocblas_double_complex*>(b.L), n,
-                          reinterpret_cast<rocblas_double_complex*>(s.X), s.ldx) != rocblas_status_success)
-            return CHFSI_ERR_DEVICE;
+        TRY(trsm_left_lower_h(st, n, m, b.L, n, s.X, s.ldx, b.gw));   // X = L^{-H} V
     }
     TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.A, s.lda, s.X, s.ldx, 0.0, b.HY, n, b.gw));
     const zd* SX = s.X;

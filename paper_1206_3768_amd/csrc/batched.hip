@@ -6,7 +6,6 @@
 // The small dense steps (QR, Rayleigh-Ritz, locking, verification) stay per problem, spread over
 // several streams so that those of different problems overlap on the device.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -155,13 +154,6 @@ chfsi_status ensure_lanes(chfsi_handle h)
             (void)hipStreamDestroy(l.st);
             return CHFSI_ERR_DEVICE;
         }
-        if (rocblas_create_handle(&l.rb) != rocblas_status_success) {
-            (void)hipEventDestroy(l.ev);
-            (void)hipStreamDestroy(l.st);
-            return CHFSI_ERR_DEVICE;
-        }
-        rocblas_set_stream(l.rb, l.st);
-        rocblas_set_pointer_mode(l.rb, rocblas_pointer_mode_host);
         h->lanes.push_back(l);
     }
     for (auto& e : h->bev)
@@ -227,14 +219,13 @@ chfsi_status get_graph(chfsi_handle h, int steps, int bm, int bn, int grid, hipG
     return CHFSI_SUCCESS;
 }
 
-// binds the handle's stream / rocBLAS handle to a lane for the per-problem steps; restores them
+// binds the handle's stream to a lane for the per-problem steps; restores it
 struct LaneBinding {
     chfsi_handle h;
     hipStream_t st0;
-    rocblas_handle rb0;
-    explicit LaneBinding(chfsi_handle hh) : h(hh), st0(hh->stream), rb0(hh->rb) {}
-    void use(int lane) { h->stream = h->lanes[lane].st; h->rb = h->lanes[lane].rb; }
-    void main() { h->stream = st0; h->rb = rb0; }
+    explicit LaneBinding(chfsi_handle hh) : h(hh), st0(hh->stream) {}
+    void use(int lane) { h->stream = h->lanes[lane].st; }
+    void main() { h->stream = st0; }
     ~LaneBinding() { main(); }
 };
 

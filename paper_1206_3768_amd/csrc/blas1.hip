@@ -452,9 +452,8 @@ int launch_fro2(hipStream_t s, int n, int m, const zd* Y, int ldy, double* out)
 
 // dot scratch: alpha_out[1..2] holds the complex dot product v^H w
 int launch_lanczos_alpha(hipStream_t s, int n, const zd* v, zd* w, const zd* vprev, double* alpha_out,
-                         const double* beta_prev)
+                         const double* beta_prev, zd* dot)
 {
-    zd* dot = (zd*)(alpha_out + 2);
     hipLaunchKernelGGL(k_coldots, dim3(1), dim3(256), 0, s, n, 1, v, n, w, dot);
     hipLaunchKernelGGL(k_lanczos_update, dim3((n + 255) / 256), dim3(256), 0, s, n, v, w, vprev, dot, alpha_out,
                        beta_prev);

@@ -88,8 +88,10 @@ int launch_max_rowsum_abs(hipStream_t s, int n, const zd* A, int lda, double* ou
 int launch_add_diag(hipStream_t s, int m, zd* G, int ldg, const double* shift_dev, double factor);
 int launch_fro2(hipStream_t s, int n, int m, const zd* Y, int ldy, double* out);            // ||Y||_F^2
 // Lanczos helpers
+// alpha = Re(v^H w) written to *alpha_out (device), w -= alpha v + beta_prev v_prev; dot: device
+// scratch for the complex product
 int launch_lanczos_alpha(hipStream_t s, int n, const zd* v, zd* w, const zd* vprev, double* alpha_out,
-                         const double* beta_prev);
+                         const double* beta_prev, zd* dot);
 int launch_lanczos_normalize(hipStream_t s, int n, const zd* w, zd* vnext, double* beta_out);
 // phase-normalize eigenvector columns: largest-magnitude entry (first on ties) real positive
 int launch_phase_normalize(hipStream_t s, int m, int ncols, zd* W, int ldw);
@@ -103,6 +105,12 @@ int launch_copy_cols_flag_c(hipStream_t s, int n, int m, const zf* src, int lds,
 // A = L L^H in place (lower triangle read and written), blocked with 64-column panels; *info
 // (device, zero on entry) receives the first non-positive pivot, 1-based.
 int chol_lower(hipStream_t s, int n, zd* A, int lda, int* info, const GemmWs& gw);
+
+// ---- triangular solves with a lower Cholesky factor L (trsm.hip) ---------------------------------
+int trsm_left_lower(hipStream_t s, int n, int nrhs, const zd* L, int ldl, zd* B, int ldb, const GemmWs& gw);    // L X = B
+int trsm_left_lower_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, zd* B, int ldb, const GemmWs& gw);  // L^H X = B
+int trsm_right_lower_h(hipStream_t s, int nrow, int ncol, const zd* L, int ldl, zd* B, int ldb,
+                       const GemmWs& gw);                                                                        // X L^H = B
 
 // ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
 int eig_padded_order(int m);

@@ -1,7 +1,6 @@
 // Host-side structures of the ChFSI library shared by the driver translation units.
 #pragma once
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <functional>
 #include <vector>
@@ -63,11 +62,10 @@ struct KernelTimer {
 
 struct TuneEntry { int prec, n, m; int bm, bn, ksplit, mode; };
 
-// A stream with its own rocBLAS handle: the batched solver binds each problem to one lane so
-// that the small dense steps of different problems overlap on the device.
+// A stream of the batched solver: each problem is bound to one lane so that the small dense steps
+// of different problems can overlap on the device.
 struct Lane {
     hipStream_t st = nullptr;
-    rocblas_handle rb = nullptr;
     hipEvent_t ev = nullptr;
 };
 
@@ -83,7 +81,6 @@ struct BatchGraph {
 struct chfsi_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
-    rocblas_handle rb = nullptr;
     Arena ws;
     PhaseTimer timer;
     std::vector<double> trace;

@@ -2,14 +2,13 @@
 //
 // The solver follows Algorithm 1 (Chebyshev filtered subspace iteration with locking) inside the
 // reduction of Section 3.2:
-//   reduction      S = L L^H, H = L^{-1} A L^{-H}          (own blocked Cholesky + rocBLAS trsm)
+//   reduction      S = L L^H, H = L^{-1} A L^{-H}          (own blocked Cholesky and triangular solves)
 //   Lanczos        k steps, full reorthogonalisation      (own kernels; k x k eig on the host)
 //   loop           filter -> orthonormalise -> Rayleigh-Ritz -> residuals -> lock prefix
 //   back-transform X = L^{-H} Y and ||A x - lambda S x|| / ||A||_lo verification
 // Every matrix operation runs on the handle's stream; the host synchronises once per loop to read
 // the m_a Ritz values and residual norms it needs for the locking decision.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -188,19 +187,14 @@ chfsi_status chfsi_create(chfsi_handle* out, int device, void* hip_stream)
     if (!h) return CHFSI_ERR_ALLOC;
     h->device = device;
     h->stream = (hipStream_t)hip_stream;
-    if (rocblas_create_handle(&h->rb) != rocblas_status_success) { delete h; return CHFSI_ERR_DEVICE; }
-    rocblas_set_stream(h->rb, h->stream);
-    rocblas_set_pointer_mode(h->rb, rocblas_pointer_mode_host);
     h->tile_cnt_len = 1 << 18;
     if (hipMalloc((void**)&h->tile_cnt, sizeof(int) * h->tile_cnt_len) != hipSuccess) {
-        rocblas_destroy_handle(h->rb);
         delete h;
         return CHFSI_ERR_ALLOC;
     }
     if (hipMemsetAsync(h->tile_cnt, 0, sizeof(int) * h->tile_cnt_len, h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess) {
         (void)hipFree(h->tile_cnt);
-        rocblas_destroy_handle(h->rb);
         delete h;
         return CHFSI_ERR_DEVICE;
     }
@@ -226,7 +220,6 @@ chfsi_status chfsi_destroy(chfsi_handle h)
     }
     if (h->btable) (void)hipFree(h->btable);
     for (auto& l : h->lanes) {
-        if (l.rb) rocblas_destroy_handle(l.rb);
         if (l.ev) (void)hipEventDestroy(l.ev);
         if (l.st) (void)hipStreamDestroy(l.st);
     }
@@ -235,7 +228,6 @@ chfsi_status chfsi_destroy(chfsi_handle h)
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->model) (void)hipFree(h->model);
     if (h->tile_cnt) (void)hipFree(h->tile_cnt);
-    if (h->rb) rocblas_destroy_handle(h->rb);
     delete h;
     return CHFSI_SUCCESS;
 }
@@ -301,17 +293,11 @@ void host_tridiag_eig(int k, const double* al, const double* be, std::vector<dou
 // steps of the method on device buffers
 // ---------------------------------------------------------------------------------------------
 
-static inline rocblas_double_complex* rbz(zd* p) { return reinterpret_cast<rocblas_double_complex*>(p); }
-static inline const rocblas_double_complex* rbz(const zd* p) { return reinterpret_cast<const rocblas_double_complex*>(p); }
 
 #define TRY(x)                                              \
     do {                                                    \
         int rc_ = (int)(x);                                 \
         if (rc_ != 0) return CHFSI_ERR_DEVICE;              \
-    } while (0)
-#define TRYRB(x)                                            \
-    do {                                                    \
-        if ((x) != rocblas_status_success) return CHFSI_ERR_DEVICE; \
     } while (0)
 
 // S = L L^H (L lower, strict upper part zeroed), H = L^{-1} A L^{-H}, Hermitized.  Enqueues the
@@ -327,11 +313,8 @@ chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, co
     TRY(hipMemcpyAsync(info_host, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     TRY(launch_zero_upper(st, n, L, n));
     TRY(launch_zlacpy(st, n, n, A, lda, H, n));
-    const rocblas_double_complex one(1.0, 0.0);
-    TRYRB(rocblas_ztrsm(h->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                        rocblas_diagonal_non_unit, n, n, &one, rbz(L), n, rbz(H), n));
-    TRYRB(rocblas_ztrsm(h->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                        rocblas_diagonal_non_unit, n, n, &one, rbz(L), n, rbz(H), n));
+    TRY(trsm_left_lower(st, n, n, L, n, H, n, gw));      // L^{-1} A
+    TRY(trsm_right_lower_h(st, n, n, L, n, H, n, gw));   // (L^{-1} A) L^{-H}
     TRY(launch_hermitize(st, n, H, n));
     return CHFSI_SUCCESS;
 }
@@ -355,14 +338,14 @@ chfsi_status step_lanczos_enqueue(chfsi_handle h, int n, const zd* H, int ldh, i
     hipStream_t st = h->stream;
     double* al = coef_dev;             // [k]
     double* be = coef_dev + k;         // [k]
-    double* scr = coef_dev + 2 * k;    // [8] scratch
+    double* scr = coef_dev + 2 * k;    // [8] scratch: normalisation of v_1, complex products
     TRY(launch_philox_block(st, seed, 2, n, 1, LV, n));
     TRY(launch_lanczos_normalize(st, n, LV, LV, scr));
     for (int j = 0; j < k; ++j) {
         zd* vj = LV + (size_t)j * n;
         TRY(launch_coldots(st, n, n, H, ldh, vj, w));           // w = H v_j (H Hermitian)
-        TRY(launch_lanczos_alpha(st, n, vj, w, j > 0 ? vj - n : nullptr, scr, j > 0 ? be + j - 1 : nullptr));
-        TRY(hipMemcpyAsync(al + j, scr, sizeof(double), hipMemcpyDeviceToDevice, st));
+        TRY(launch_lanczos_alpha(st, n, vj, w, j > 0 ? vj - n : nullptr, al + j, j > 0 ? be + j - 1 : nullptr,
+                                 (zd*)(scr + 2)));
         for (int pass = 0; pass < 2; ++pass) {
             TRY(launch_coldots(st, n, j + 1, LV, n, w, c));
             TRY(launch_gemv_n(st, n, j + 1, LV, n, c, -1.0, w));
@@ -419,14 +402,12 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
     TRY(launch_scale_cols_inv(st, n, ma, Y, ldy, dsc));
     const double u = 1.1102230246251565e-16;
     const double shift = 11.0 * ((double)n * ma + (double)ma * (ma + 1)) * u * (double)ma;
-    const rocblas_double_complex one(1.0, 0.0);
     for (int pass = 0; pass < 3; ++pass) {
         TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, Y, ldy, 0.0, G, ma, gw));
         if (pass == 0) TRY(launch_add_diag_const(st, ma, G, ma, shift));
         // G = L L^H = R^H R with R = L^H; Y <- Y R^{-1} = Y L^{-H}
         TRY(chol_lower(st, ma, G, ma, info_dev + pass, gw));
-        TRYRB(rocblas_ztrsm(h->rb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                            rocblas_diagonal_non_unit, n, ma, &one, rbz(G), ma, rbz(Y), ldy));
+        TRY(trsm_right_lower_h(st, n, ma, G, ma, Y, ldy, gw));
     }
     return CHFSI_SUCCESS;
 }

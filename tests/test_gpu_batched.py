@@ -149,6 +149,26 @@ def test_batched_more_problems_than_one_launch_holds(hd):
         assert np.abs(X.conj().T @ kp.S @ X - np.eye(X.shape[1])).max() <= 1e-12
 
 
+def test_batched_over_several_streams_matches_one_stream(hd):
+    """The per-problem dense steps spread over four streams give the same converged pairs as one."""
+    from paper_1206_3768_amd import chfsi
+    rng = np.random.default_rng(21)
+    sizes = [int(v) for v in rng.integers(700, 1600, size=12)]
+    kps = _problems(sizes, seed=13)
+    out = {}
+    for lanes in (1, 4):
+        hd.set_batched_plan(64, 64, use_graph=True, lanes=lanes)
+        probs = _upload(kps)
+        st, res = hd.solve_batched(probs, _params())
+        assert st == 0, [r.status for r in res]
+        out[lanes] = res
+    hd.set_batched_plan(64, 64, use_graph=True, lanes=1)
+    for kp, a, b in zip(kps, out[1], out[4]):
+        assert a.stats["loops"] == b.stats["loops"]
+        assert np.all(np.abs(a.lam[:kp.nev] - b.lam[:kp.nev]) <= 1e-12 * np.maximum(np.abs(a.lam[:kp.nev]), 1e-3))
+        assert b.resid[:kp.nev].max() <= 1e-10
+
+
 def test_batched_error_in_one_problem_leaves_the_others(hd):
     from paper_1206_3768_amd import chfsi
     kps = _problems([200, 240, 260], seed=10)
