@@ -2,8 +2,8 @@
 // right-looking with 64-column panels:
 //   k_chol_panel  one workgroup per 64-row block of the panel: every workgroup factors the 64 x 64
 //                 diagonal block in LDS (redundantly, which costs less than a second launch);
-//                 workgroup 0 writes L11, workgroup b > 0 solves L21_b L11^H = A21_b by forward
-//                 substitution in LDS.
+//                 workgroup 0 writes L11, workgroup b > 0 inverts L11 in LDS (tri64.h) and forms
+//                 L21_b = A21_b L11^{-H} as a product.
 //   trailing      A22 <- A22 - L21 L21^H with the MFMA complex GEMM of gemm.hip.
 // A non-positive (or non-finite) pivot sets *info to its 1-based column, as LAPACK's potrf does;
 // the factorisation then continues on meaningless numbers and the caller discards the result.
@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "tri64.h"
 
 namespace {
 
@@ -30,44 +31,57 @@ __device__ inline zd zsub_mul_conj(zd acc, zd a, zd b)   // acc - a conj(b)
 __global__ __launch_bounds__(256) void k_chol_panel(int n, int k0, zd* __restrict__ A, int lda, int* __restrict__ info)
 {
     __shared__ zd L[CB * CP];    // diagonal block, factored in place (lower)
-    __shared__ zd X[CB * CP];    // the row block being solved
-    __shared__ double piv;
+    __shared__ zd X[CB * CP];    // L11^{-1}
     const int tid = threadIdx.x;
     const int nb = min(CB, n - k0);
-    // diagonal block (lower triangle mirrored; identity padding beyond nb)
+    // diagonal block: lower triangle (the upper is never read), identity padding beyond nb
+    #pragma unroll
     for (int e = tid; e < CB * CB; e += 256) {
         const int i = e % CB, j = e / CB;
         zd v = make_double2(i == j ? 1.0 : 0.0, 0.0);
-        if (i < nb && j < nb) {
-            if (i >= j) v = A[(size_t)(k0 + i) + (size_t)(k0 + j) * lda];
-            else {
-                const zd u = A[(size_t)(k0 + j) + (size_t)(k0 + i) * lda];
-                v = make_double2(u.x, -u.y);
-            }
+        if (i < nb && j < nb && i >= j) {
+            v = A[(size_t)(k0 + i) + (size_t)(k0 + j) * lda];
             if (i == j) v.y = 0.0;
         }
         L[i * CP + j] = v;
     }
     __syncthreads();
-    // unblocked right-looking Cholesky of the 64 x 64 block
-    for (int k = 0; k < CB; ++k) {
-        if (tid == 0) {
-            const double d = L[k * CP + k].x;
-            piv = d;
-            if (!(d > 0.0) && blockIdx.x == 0 && k < nb && info) atomicCAS(info, 0, k0 + k + 1);
-            L[k * CP + k] = make_double2(sqrt(d > 0.0 ? d : 1.0), 0.0);
+    // right-looking Cholesky of the 64 x 64 block, four columns at a time: wave 0 factors the
+    // 64 x 4 column panel in registers (lane = row, diagonal entries shared by shuffles), then all
+    // threads apply the rank-4 update to the trailing lower triangle
+    const int lane = tid & 63;
+    for (int k = 0; k < CB; k += 4) {
+        if (tid < 64) {
+            zd v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = L[lane * CP + k + c];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int kc = k + c;
+                const double d = __shfl(v[c].x, kc);
+                if (lane == 0 && !(d > 0.0) && blockIdx.x == 0 && kc < nb && info) atomicCAS(info, 0, k0 + kc + 1);
+                const double sd = sqrt(d > 0.0 ? d : 1.0), inv = 1.0 / sd;
+                if (lane > kc) v[c] = make_double2(v[c].x * inv, v[c].y * inv);
+                else if (lane == kc) v[c] = make_double2(sd, 0.0);
+#pragma unroll
+                for (int j = c + 1; j < 4; ++j) {   // columns k + j of the panel, rows >= k + j
+                    const double lr = __shfl(v[c].x, k + j), li = __shfl(v[c].y, k + j);
+                    if (lane >= k + j) v[j] = zsub_mul_conj(v[j], v[c], make_double2(lr, li));
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (lane >= k + c) L[lane * CP + k + c] = v[c];
         }
         __syncthreads();
-        const double inv = 1.0 / sqrt(piv > 0.0 ? piv : 1.0);
-        for (int i = k + 1 + tid; i < CB; i += 256) {
-            zd v = L[i * CP + k];
-            L[i * CP + k] = make_double2(v.x * inv, v.y * inv);
-        }
-        __syncthreads();
-        const int rem = CB - k - 1;
+        const int r0t = k + 4, rem = CB - r0t;
         for (int e = tid; e < rem * rem; e += 256) {
-            const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-            if (i >= j) L[i * CP + j] = zsub_mul_conj(L[i * CP + j], L[i * CP + k], L[j * CP + k]);
+            const int i = r0t + e % rem, j = r0t + e / rem;
+            if (i < j) continue;
+            zd acc = L[i * CP + j];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc = zsub_mul_conj(acc, L[i * CP + k + c], L[j * CP + k + c]);
+            L[i * CP + j] = acc;
         }
         __syncthreads();
     }
@@ -80,33 +94,49 @@ __global__ __launch_bounds__(256) void k_chol_panel(int n, int k0, zd* __restric
     }
     const int r0 = k0 + blockIdx.x * CB;            // first row of this row block
     const int nr = min(CB, n - r0);
-    // L21 rows by forward substitution, x L11^H = a for each row: x_j = (a_j - sum_{l < j} x_l
-    // conj(L_jl)) / L_jj.  Four lanes per row (one wave holds 16 rows) split each sum and combine
-    // it with shuffles; one barrier per column makes x_j visible to the next column.
+    // L21 = A21 L11^{-H}: row r, column v: sum_l A21(r, l) conj(X(v, l)), X = L11^{-1}; the
+    // coefficient table conj(X(v, l)) goes to L (transposed, contiguous in v), the rows of A21 to X
+    tri64::lower_inverse(L, X);
+    #pragma unroll
+    for (int e = tid; e < CB * CB; e += 256) {   // L[l][v] = conj(X[v][l]), contiguous in v
+        const int v = e % CB, l = e / CB;
+        const zd x = X[v * CP + l];
+        L[l * CP + v] = make_double2(x.x, -x.y);
+    }
+    __syncthreads();
+    #pragma unroll
     for (int e = tid; e < CB * CB; e += 256) {
         const int r = e % CB, l = e / CB;
         X[r * CP + l] = (r < nr && l < nb) ? A[(size_t)(r0 + r) + (size_t)(k0 + l) * lda] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const int r = tid >> 2, t = tid & 3;
-    for (int j = 0; j < nb; ++j) {
-        zd acc = make_double2(0.0, 0.0);
-        for (int l = t; l < j; l += 4) acc = zsub_mul_conj(acc, X[r * CP + l], L[j * CP + l]);
-        acc.x += __shfl_xor(acc.x, 1);
-        acc.y += __shfl_xor(acc.y, 1);
-        acc.x += __shfl_xor(acc.x, 2);
-        acc.y += __shfl_xor(acc.y, 2);
-        if (t == 0) {
-            const double d = 1.0 / L[j * CP + j].x;
-            const zd a = X[r * CP + j];
-            X[r * CP + j] = make_double2((a.x + acc.x) * d, (a.y + acc.y) * d);
+    const int rg = (tid >> 4) * 4, vg = (tid & 15) * 4;
+    zd acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = make_double2(0.0, 0.0);
+    for (int l = 0; l < CB; ++l) {
+        zd av[4], xv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = X[(rg + a) * CP + l];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xv[c] = L[l * CP + vg + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {   // acc += a xv  (xv holds conj(X[v][l]))
+                acc[a][c].x += av[a].x * xv[c].x - av[a].y * xv[c].y;
+                acc[a][c].y += av[a].y * xv[c].x + av[a].x * xv[c].y;
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int r = rg + a, v = vg + c;
+            if (r < nr && v < nb) A[(size_t)(r0 + r) + (size_t)(k0 + v) * lda] = acc[a][c];
         }
-        __syncthreads();
-    }
-    for (int e = tid; e < nr * nb; e += 256) {
-        const int rr = e % nr, l = e / nr;
-        A[(size_t)(r0 + rr) + (size_t)(k0 + l) * lda] = X[rr * CP + l];
-    }
 }
 
 }  // namespace

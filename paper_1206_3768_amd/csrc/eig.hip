@@ -113,6 +113,7 @@ __global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, con
     const int tid = threadIdx.x;
     int P, Q;
     rr_pair(nb, round, blockIdx.x, P, Q);
+    #pragma unroll
     for (int e = tid; e < ES * ES; e += 256) {
         const int u = e % ES, v = e / ES;
         A[u * EP + v] = Gp[(size_t)sub_index(P, Q, u) + (size_t)sub_index(P, Q, v) * M];
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, con
         __syncthreads();
     }
     zd* Jw = J + (size_t)blockIdx.x * ES * ES;
+    #pragma unroll
     for (int e = tid; e < ES * ES; e += 256) {
         const int u = e % ES, v = e / ES;
         Jw[e] = V[u * EP + v];
@@ -208,6 +210,7 @@ __global__ __launch_bounds__(256) void k_eig_apply(int M, int nb, int round, zd*
     int Pp, Qp, Pq, Qq;
     rr_pair(nb, round, p, Pp, Qp);
     rr_pair(nb, round, q, Pq, Qq);
+    #pragma unroll
     for (int e = tid; e < ES * ES; e += 256) {
         const int u = e % ES, v = e / ES;
         const size_t col = (size_t)sub_index(Pq, Qq, v) * M;

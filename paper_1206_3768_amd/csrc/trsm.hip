@@ -1,6 +1,6 @@
 // Triangular solves with the Cholesky factor L (lower, n x n) of the reduction to standard form
-// and of Cholesky QR: blocked substitution with 64 x 64 diagonal blocks solved in LDS and the
-// off-diagonal updates on the MFMA complex GEMM of gemm.hip.
+// and of Cholesky QR: blocked substitution with 64 x 64 diagonal blocks (inverted in LDS, then
+// applied as a product) and the off-diagonal updates on the MFMA complex GEMM of gemm.hip.
 //   trsm_left_lower   L X = B          (H = L^{-1} A, first half of the reduction)
 //   trsm_left_lower_h L^H X = B        (X = L^{-H} V, back-transform of the eigenvectors)
 //   trsm_right_lower_h X L^H = B       (H = W L^{-H}, second half; Q = Y R^{-1} of Cholesky QR)
@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "tri64.h"
 
 namespace {
 
@@ -29,60 +30,74 @@ __device__ inline zd zfma(zd acc, zd a, zd b, double sgn)   // acc + sgn a b
 __device__ inline zd zc(zd a) { return make_double2(a.x, -a.y); }
 
 // Solves the diagonal block k0 .. k0 + nb of L against 64 vectors of B per workgroup.
-//   RL_C: vectors are rows r of B(:, k0:k0+nb):   x L_kk^H = b  (forward)
-//   LL_N: vectors are columns c of B(k0:k0+nb, :): L_kk x = b    (forward)
-//   LL_C: vectors are columns c of B(k0:k0+nb, :): L_kk^H x = b  (backward)
-// nvec: number of vectors (rows of B for RL_C, columns for LL_*).  Four lanes per vector split
-// each dot product and combine it with shuffles; one barrier per position.
+//   RL_C: vectors are rows r of B(:, k0:k0+nb):   x L_kk^H = b,  x_v = sum_l b_l conj(X_vl)
+//   LL_N: vectors are columns c of B(k0:k0+nb, :): L_kk x = b,    x_v = sum_l X_vl b_l
+//   LL_C: vectors are columns c of B(k0:k0+nb, :): L_kk^H x = b,  x_v = sum_l conj(X_lv) b_l
+// with X = L_kk^{-1} (tri64.h).  nvec: number of vectors (rows of B for RL_C, columns for LL_*).
+// Each thread computes a 4 x 4 block of (vector, position) outputs.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_trsm_diag(int k0, int nb, int nvec, const zd* __restrict__ L, int ldl,
                                                    zd* __restrict__ B, int ldb)
 {
-    __shared__ zd T[TB * TP];   // L_kk (lower), identity padding
-    __shared__ zd X[TB * TP];   // X[u][v]: vector u, position v
+    __shared__ zd T[TB * TP];   // L_kk (lower, identity padding), then the coefficient table
+    __shared__ zd X[TB * TP];   // L_kk^{-1}, then the vectors: X[u][v]
     const int tid = threadIdx.x;
     const int v0 = blockIdx.x * TB;
     const int nv = min(TB, nvec - v0);
+    #pragma unroll
     for (int e = tid; e < TB * TB; e += 256) {
         const int i = e % TB, j = e / TB;
         zd t = make_double2(i == j ? 1.0 : 0.0, 0.0);
         if (i < nb && j < nb && i >= j) t = L[(size_t)(k0 + i) + (size_t)(k0 + j) * ldl];
-        T[i * TP + j] = (i >= j || i >= nb || j >= nb) ? t : make_double2(0.0, 0.0);
-        // vector u = i, position v = j
+        T[i * TP + j] = t;
+    }
+    __syncthreads();
+    tri64::lower_inverse(T, X);
+    // coefficient table C[l][v] (contiguous in v for the product below):
+    //   LL_N: X[v][l],  LL_C: conj(X[l][v]),  RL_C: conj(X[v][l])
+    #pragma unroll
+    for (int e = tid; e < TB * TB; e += 256) {
+        const int v = e % TB, l = e / TB;
+        T[l * TP + v] = (MODE == LL_N) ? X[v * TP + l] : (MODE == LL_C) ? zc(X[l * TP + v]) : zc(X[v * TP + l]);
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int e = tid; e < TB * TB; e += 256) {   // vector u = i, position v = j into X; consecutive
+        // threads walk the contiguous dimension of B (vectors for RL_C, positions for LL_*)
+        const int i = (MODE == RL_C) ? e % TB : e / TB, j = (MODE == RL_C) ? e / TB : e % TB;
         zd b = make_double2(0.0, 0.0);
         if (i < nv && j < nb)
             b = (MODE == RL_C) ? B[(size_t)(v0 + i) + (size_t)(k0 + j) * ldb] : B[(size_t)(k0 + j) + (size_t)(v0 + i) * ldb];
         X[i * TP + j] = b;
     }
     __syncthreads();
-    const int u = tid >> 2, t = tid & 3;
-    for (int s = 0; s < nb; ++s) {
-        const int v = (MODE == LL_C) ? nb - 1 - s : s;
-        zd acc = make_double2(0.0, 0.0);
-        if (MODE == LL_C) {
-            for (int l = v + 1 + t; l < nb; l += 4) acc = zfma(acc, zc(T[l * TP + v]), X[u * TP + l], -1.0);
-        } else {
-            for (int l = t; l < v; l += 4) {
-                const zd c = (MODE == RL_C) ? zc(T[v * TP + l]) : T[v * TP + l];
-                acc = zfma(acc, c, X[u * TP + l], -1.0);
+    const int ug = (tid >> 4) * 4, vg = (tid & 15) * 4;
+    zd acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = make_double2(0.0, 0.0);
+    for (int l = 0; l < TB; ++l) {
+        zd bv[4], cf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) bv[a] = X[(ug + a) * TP + l];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cf[c] = T[l * TP + vg + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[a][c] = zfma(acc[a][c], cf[c], bv[a], 1.0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = ug + a, j = vg + c;
+            if (i < nv && j < nb) {
+                if (MODE == RL_C) B[(size_t)(v0 + i) + (size_t)(k0 + j) * ldb] = acc[a][c];
+                else B[(size_t)(k0 + j) + (size_t)(v0 + i) * ldb] = acc[a][c];
             }
         }
-        acc.x += __shfl_xor(acc.x, 1);
-        acc.y += __shfl_xor(acc.y, 1);
-        acc.x += __shfl_xor(acc.x, 2);
-        acc.y += __shfl_xor(acc.y, 2);
-        if (t == 0) {
-            const double d = 1.0 / T[v * TP + v].x;
-            const zd b = X[u * TP + v];
-            X[u * TP + v] = make_double2((b.x + acc.x) * d, (b.y + acc.y) * d);
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < nv * nb; e += 256) {
-        const int i = e % nv, j = e / nv;
-        if (MODE == RL_C) B[(size_t)(v0 + i) + (size_t)(k0 + j) * ldb] = X[i * TP + j];
-        else B[(size_t)(k0 + j) + (size_t)(v0 + i) * ldb] = X[i * TP + j];
-    }
 }
 
 template <int MODE>
