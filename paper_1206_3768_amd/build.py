@@ -18,6 +18,9 @@ ARCH = "gfx950"
 # packed FP32 ops are disabled: hipcc must not form v_pk_{add,mul,fma}_f32 from scalar code
 CFLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # MFMA accumulators in ordinary VGPRs: with the default AGPR form the compiler copies the
+          # loop-carried accumulators between AGPRs and VGPRs on every k-stage of the GEMM tiles
+          "-mllvm", "-amdgpu-mfma-vgpr-form=1",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

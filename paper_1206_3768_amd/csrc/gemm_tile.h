@@ -68,7 +68,6 @@ __device__ __forceinline__ void tile_mainloop(const typename CT<T>::c* __restric
             for (int r = 0; r < 4; ++r) { accr[bi][bj][r] = 0; acci[bi][bj][r] = 0; }
 
     C2 ra[NPA], rb[NPB];
-    const C2 zero = {0, 0};
 
     // element p of a stage tile handled by this thread: op(A) row ai(p), column ak(p); op(B) row
     // bk(p), column bj(p).  Consecutive threads walk the contiguous dimension of the stored matrix.
@@ -79,32 +78,44 @@ __device__ __forceinline__ void tile_mainloop(const typename CT<T>::c* __restric
 #define GEMM_GLOAD(k0)                                                                                    \
     {                                                                                                     \
         _Pragma("unroll") for (int p = 0; p < NPA; ++p) {                                                 \
-            const int gi = i0 + AI(p), gk = (k0) + AK(p);                                                 \
-            const int ci = min(gi, M - 1), ck = min(gk, ke - 1);   /* clamped: always in bounds */      \
-            const size_t off = (OPA == OP_N) ? (size_t)ci + (size_t)ck * lda : (size_t)ck + (size_t)ci * lda; \
-            const C2 v = A[off];                                                                          \
-            ra[p] = (gi < M && gk < ke) ? ((OPA == OP_N) ? v : cconj(v)) : zero;                           \
+            const int ci = min(i0 + AI(p), M - 1), ck = min((k0) + AK(p), ke - 1);   /* clamped */       \
+            ra[p] = A[(OPA == OP_N) ? (size_t)ci + (size_t)ck * lda : (size_t)ck + (size_t)ci * lda];      \
         }                                                                                                 \
         _Pragma("unroll") for (int p = 0; p < NPB; ++p) {                                                 \
-            const int gj = j0 + BJ(p), gk = (k0) + BKK(p);                                                \
-            const int cj = min(gj, N - 1), ck = min(gk, ke - 1);                                          \
-            const size_t off = (OPB == OP_N) ? (size_t)ck + (size_t)cj * ldb : (size_t)cj + (size_t)ck * ldb; \
-            const C2 v = B[off];                                                                          \
-            rb[p] = (gj < N && gk < ke) ? ((OPB == OP_N) ? v : cconj(v)) : zero;                           \
+            const int cj = min(j0 + BJ(p), N - 1), ck = min((k0) + BKK(p), ke - 1);                      \
+            rb[p] = B[(OPB == OP_N) ? (size_t)ck + (size_t)cj * ldb : (size_t)cj + (size_t)ck * ldb];      \
         }                                                                                                 \
     }
-#define GEMM_SSTORE(buf)                                                                                  \
+    // the loaded values are masked (outside the matrix or beyond ke: zero) and conjugated only when
+    // they are stored to LDS, one stage later, so that no instruction waits on the global loads
+    // before the MFMAs of the current stage have been issued
+#define GEMM_SSTORE(buf, k0)                                                                              \
     {                                                                                                     \
-        _Pragma("unroll") for (int p = 0; p < NPA; ++p) As[(buf) * S::AS_ELEMS + AK(p) * LDA_S + AI(p)] = ra[p]; \
-        _Pragma("unroll") for (int p = 0; p < NPB; ++p) Bs[(buf) * S::BS_ELEMS + BKK(p) * LDB_S + BJ(p)] = rb[p]; \
+        _Pragma("unroll") for (int p = 0; p < NPA; ++p) {                                                 \
+            const bool ok = i0 + AI(p) < M && (k0) + AK(p) < ke;                                          \
+            C2 v;                                                                                         \
+            v.x = ok ? ra[p].x : T(0);                                                                    \
+            v.y = ok ? ((OPA == OP_N) ? ra[p].y : -ra[p].y) : T(0);                                       \
+            As[(buf) * S::AS_ELEMS + AK(p) * LDA_S + AI(p)] = v;                                          \
+        }                                                                                                 \
+        _Pragma("unroll") for (int p = 0; p < NPB; ++p) {                                                 \
+            const bool ok = j0 + BJ(p) < N && (k0) + BKK(p) < ke;                                        \
+            C2 v;                                                                                         \
+            v.x = ok ? rb[p].x : T(0);                                                                    \
+            v.y = ok ? ((OPB == OP_N) ? rb[p].y : -rb[p].y) : T(0);                                       \
+            Bs[(buf) * S::BS_ELEMS + BKK(p) * LDB_S + BJ(p)] = v;                                         \
+        }                                                                                                 \
     }
 
     if (nstages > 0) GEMM_GLOAD(kb);
     for (int s = 0; s < nstages; ++s) {
         const int buf = s & 1;
-        GEMM_SSTORE(buf);
+        GEMM_SSTORE(buf, kb + s * BK);
         __syncthreads();
-        if (s + 1 < nstages) GEMM_GLOAD(kb + (s + 1) * BK);
+        // the next stage's loads (the last stage reloads itself: in bounds, never stored) are issued
+        // unconditionally so that they overlap the MFMAs below
+        GEMM_GLOAD(kb + min(s + 1, nstages - 1) * BK);
+        asm volatile("" ::: "memory");   // keeps the compiler from sinking the loads below the MFMAs
         const C2* as = As + buf * S::AS_ELEMS;
         const C2* bs = Bs + buf * S::BS_ELEMS;
 #pragma unroll
