@@ -23,7 +23,6 @@ n = 8192 with per-eigenvalue errors against FP64.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import statistics
@@ -43,14 +42,6 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("gemm.hip",):
-        with open(os.path.join(ROOT, "paper_1206_3768_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload: str, kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it was
     taken on the current kernel source (else None)."""
@@ -59,6 +50,7 @@ def load_traffic(workload: str, kernel: str):
         return None
     with open(path) as fh:
         t = json.load(fh)
+    from paper_1206_3768_amd.traffic import kernel_source_hash
     if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")

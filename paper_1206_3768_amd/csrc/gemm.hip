@@ -84,10 +84,13 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nt = g.tiles_m * g.tiles_n * g.ksplit;
     const int tile = xcd_remap(blockIdx.x, nt);
+    // tile order (ks, it, jt), jt fastest: the contiguous range of tiles that one XCD receives covers
+    // one K slice, so that the XCD's L2 holds only that slice of op(B) (and the column tiles of one
+    // row block share its op(A) panel)
     const int jt = tile % g.tiles_n;
     const int r1 = tile / g.tiles_n;
-    const int ks = r1 % g.ksplit;
-    const int it = r1 / g.ksplit;
+    const int it = r1 % g.tiles_m;
+    const int ks = r1 / g.tiles_m;
     const int i0 = it * BM, j0 = jt * BN;
     const int kb = ks * g.kchunk;
     const int ke = min(g.K, kb + g.kchunk);
