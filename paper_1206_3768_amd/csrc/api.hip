@@ -34,6 +34,7 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
         b.H = ar.take<zd>(nn);
         b.L = ar.take<zd>(nn);
     }
+    b.dinvL = ar.take<zd>(tri_dinv_elems(n));
     if (prec == CHFSI_FP32) b.Hf = ar.take<zf>(nn);
     if (prec == CHFSI_BF16X3 || prec == CHFSI_BF16X6) {
         const int nterms = prec == CHFSI_BF16X3 ? 2 : 3;
@@ -49,6 +50,7 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
     }
     b.G = ar.take<zd>(mm);
     b.Cm = ar.take<zd>(mm);
+    b.dinvG = ar.take<zd>(tri_dinv_elems(m));
     b.theta = ar.take<double>(m);
     b.r = ar.take<double>(m);
     b.E = ar.take<double>(m + 8);
@@ -226,7 +228,7 @@ chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
     s.ldh = s.lda;
     s.hi[0] = 0;
     if (s.S) {
-        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.info, s.hi, b.gw));
+        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.info, s.hi, b.gw));
         s.H = b.H;
         s.ldh = n;
         // The reduction completes before the caller enqueues more work.  A batch solved over several
@@ -348,7 +350,7 @@ chfsi_status st_loop_enqueue(chfsi_handle h, SolveState& s)
     s.filtered += ma;
     mark(s, PH_QR, st, true);
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, st));
-    TRYS(step_orthonormalize(h, n, ma, Ya, n, s.nlocked, b.V, n, b.G, b.Cm, b.dsc, b.info, b.gw));
+    TRYS(step_orthonormalize(h, n, ma, Ya, n, s.nlocked, b.V, n, b.G, b.Cm, b.dinvG, b.dsc, b.info, b.gw));
     mark(s, PH_QR, st, false);
     mark(s, PH_RR, st, true);
     TRYS(step_rayleigh_ritz(h, n, s.H, s.ldh, ma, Ya, n, b.HY, b.T, b.G, b.theta, b.r, b.eigw, s.h_eig(), b.gw,
@@ -445,7 +447,7 @@ chfsi_status st_final_enqueue(chfsi_handle h, SolveState& s)
     mark(s, PH_BACK, st, true);
     TRY(launch_zlacpy(st, n, m, b.V, n, s.X, s.ldx));
     if (s.S) {
-        TRY(trsm_left_lower_h(st, n, m, b.L, n, s.X, s.ldx, b.gw));   // X = L^{-H} V
+        TRY(trsm_left_lower_h(st, n, m, b.L, n, b.dinvL, s.X, s.ldx, b.gw));   // X = L^{-H} V
     }
     TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.A, s.lda, s.X, s.ldx, 0.0, b.HY, n, b.gw));
     const zd* SX = s.X;
@@ -644,8 +646,8 @@ chfsi_status chfsi_reduce(chfsi_handle h, int n, const void* A, int lda, const v
     if (!h || !A || !S || !H || !L || n <= 0 || lda < n || lds < n) return CHFSI_ERR_ARG;
     if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
     SolveBufs b;
-    TRYS(prepare(h, b, 1, 1, 1, false, CHFSI_FP64));
-    TRYS(step_reduce(h, n, (const zd*)A, lda, (const zd*)S, lds, (zd*)H, (zd*)L, b.info, b.gw));
+    TRYS(prepare(h, b, n, 1, 1, false, CHFSI_FP64));
+    TRYS(step_reduce(h, n, (const zd*)A, lda, (const zd*)S, lds, (zd*)H, (zd*)L, b.dinvL, b.info, b.gw));
     TRY(hipStreamSynchronize(h->stream));
     return CHFSI_SUCCESS;
 }
@@ -676,7 +678,7 @@ chfsi_status chfsi_orthonormalize(chfsi_handle h, int n, int m, void* Y, int ldy
     const int mm = std::max(m, nl);
     TRYS(prepare(h, b, n, mm, 1, false, CHFSI_FP64));
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, h->stream));
-    TRYS(step_orthonormalize(h, n, m, (zd*)Y, ldy, nl, (const zd*)YL, ldyl, b.G, b.Cm, b.dsc, b.info, b.gw));
+    TRYS(step_orthonormalize(h, n, m, (zd*)Y, ldy, nl, (const zd*)YL, ldyl, b.G, b.Cm, b.dinvG, b.dsc, b.info, b.gw));
     int hinfo[3];
     TRY(hipMemcpyAsync(hinfo, b.info, sizeof(hinfo), hipMemcpyDeviceToHost, h->stream));
     TRY(hipStreamSynchronize(h->stream));

@@ -103,14 +103,23 @@ int launch_copy_cols_flag_c(hipStream_t s, int n, int m, const zf* src, int lds,
 
 // ---- Cholesky factorisation (chol.hip) -----------------------------------------------------------
 // A = L L^H in place (lower triangle read and written), blocked with 64-column panels; *info
-// (device, zero on entry) receives the first non-positive pivot, 1-based.
-int chol_lower(hipStream_t s, int n, zd* A, int lda, int* info, const GemmWs& gw);
+// (device, zero on entry) receives the first non-positive pivot, 1-based; dinv (device,
+// tri_dinv_elems(n) elements) receives the inverses of L's 64 x 64 diagonal blocks (block kb at
+// dinv + 4096 kb, column-major, ld 64), which the triangular solves below take with L.
+int chol_lower(hipStream_t s, int n, zd* A, int lda, int* info, zd* dinv, const GemmWs& gw);
 
 // ---- triangular solves with a lower Cholesky factor L (trsm.hip) ---------------------------------
-int trsm_left_lower(hipStream_t s, int n, int nrhs, const zd* L, int ldl, zd* B, int ldb, const GemmWs& gw);    // L X = B
-int trsm_left_lower_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, zd* B, int ldb, const GemmWs& gw);  // L^H X = B
-int trsm_right_lower_h(hipStream_t s, int nrow, int ncol, const zd* L, int ldl, zd* B, int ldb,
-                       const GemmWs& gw);                                                                        // X L^H = B
+size_t tri_dinv_elems(int n);
+enum { TA_LEFT_N = 0, TA_LEFT_C = 1, TA_RIGHT_C = 2 };
+// in place: TA_LEFT_N B <- D B (B nb x nvec), TA_LEFT_C B <- D^H B, TA_RIGHT_C B <- B D^H (B nvec x nb);
+// D: 64 x 64 column-major, nb <= 64
+int tri_apply(hipStream_t s, int mode, int nb, int nvec, const zd* D, zd* B, int ldb);
+int trsm_left_lower(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                    const GemmWs& gw);   // L X = B
+int trsm_left_lower_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                      const GemmWs& gw);   // L^H X = B
+int trsm_right_lower_h(hipStream_t s, int nrow, int ncol, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                       const GemmWs& gw);   // X L^H = B
 
 // ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
 int eig_padded_order(int m);

@@ -111,10 +111,10 @@ struct chfsi_handle_s {
 };
 
 // steps (solver.hip)
-chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, int* info_dev,
-                         const GemmWs& gw);
+chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, zd* dinv,
+                         int* info_dev, const GemmWs& gw);
 chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                                 int* info_dev, int* info_host, const GemmWs& gw);
+                                 zd* dinv, int* info_dev, int* info_host, const GemmWs& gw);
 chfsi_status step_lanczos_enqueue(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed,
                                   zd* LV, zd* w, zd* c, double* coef_dev, double* hal, double* hbe);
 chfsi_status lanczos_finish(int k, const double* hal, const double* hbe, std::vector<double>& theta,
@@ -123,7 +123,7 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
                           zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
                           double& beta_k, int& k_used);
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
-                                 zd* G, zd* Cm, double* dsc, int* info_dev, const GemmWs& gw);
+                                 zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw);
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY, zd* T,
                                 zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
                                 const GemmWs& gw, PhaseTimer* tm);

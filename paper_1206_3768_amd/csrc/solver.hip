@@ -304,26 +304,26 @@ void host_tridiag_eig(int k, const double* al, const double* be, std::vector<dou
 // whole reduction; the Cholesky info word is copied to *info_host (host memory, valid after the
 // stream has been synchronised; nonzero = S not positive definite, H then meaningless).
 chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                                 int* info_dev, int* info_host, const GemmWs& gw)
+                                 zd* dinv, int* info_dev, int* info_host, const GemmWs& gw)
 {
     hipStream_t st = h->stream;
     TRY(launch_zlacpy(st, n, n, S, lds, L, n));
     TRY(hipMemsetAsync(info_dev, 0, sizeof(int), st));
-    TRY(chol_lower(st, n, L, n, info_dev, gw));
+    TRY(chol_lower(st, n, L, n, info_dev, dinv, gw));
     TRY(hipMemcpyAsync(info_host, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     TRY(launch_zero_upper(st, n, L, n));
     TRY(launch_zlacpy(st, n, n, A, lda, H, n));
-    TRY(trsm_left_lower(st, n, n, L, n, H, n, gw));      // L^{-1} A
-    TRY(trsm_right_lower_h(st, n, n, L, n, H, n, gw));   // (L^{-1} A) L^{-H}
+    TRY(trsm_left_lower(st, n, n, L, n, dinv, H, n, gw));      // L^{-1} A
+    TRY(trsm_right_lower_h(st, n, n, L, n, dinv, H, n, gw));   // (L^{-1} A) L^{-H}
     TRY(launch_hermitize(st, n, H, n));
     return CHFSI_SUCCESS;
 }
 
-chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
+chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, zd* dinv,
                          int* info_dev, const GemmWs& gw)
 {
     int info = 0;
-    chfsi_status s = step_reduce_enqueue(h, n, A, lda, S, lds, H, L, info_dev, &info, gw);
+    chfsi_status s = step_reduce_enqueue(h, n, A, lda, S, lds, H, L, dinv, info_dev, &info, gw);
     if (s != CHFSI_SUCCESS) return s;
     TRY(hipStreamSynchronize(h->stream));
     return info != 0 ? CHFSI_ERR_NOT_HPD : CHFSI_SUCCESS;
@@ -389,7 +389,7 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
 // column normalisation; Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SISC 2020).  R's
 // diagonal is real positive in every pass, so Q is the Q factor of Y.
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
-                                 zd* G, zd* Cm, double* dsc, int* info_dev, const GemmWs& gw)
+                                 zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw)
 {
     hipStream_t st = h->stream;
     if (ma <= 0) return CHFSI_SUCCESS;
@@ -406,8 +406,8 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
         TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, Y, ldy, 0.0, G, ma, gw));
         if (pass == 0) TRY(launch_add_diag_const(st, ma, G, ma, shift));
         // G = L L^H = R^H R with R = L^H; Y <- Y R^{-1} = Y L^{-H}
-        TRY(chol_lower(st, ma, G, ma, info_dev + pass, gw));
-        TRY(trsm_right_lower_h(st, n, ma, G, ma, Y, ldy, gw));
+        TRY(chol_lower(st, ma, G, ma, info_dev + pass, dinv, gw));
+        TRY(trsm_right_lower_h(st, n, ma, G, ma, dinv, Y, ldy, gw));
     }
     return CHFSI_SUCCESS;
 }

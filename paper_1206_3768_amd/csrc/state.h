@@ -18,6 +18,7 @@ struct SolveBufs {
     zf *Vf = nullptr, *Tf = nullptr;   // n x m complex64
     uint16_t* ysplit = nullptr;        // BF16 split of Y_k
     zd *G = nullptr, *Cm = nullptr;    // m x m
+    zd *dinvL = nullptr, *dinvG = nullptr;   // inverted 64 x 64 diagonal blocks of L (n) and of the Gram factor (m)
     double *theta = nullptr, *r = nullptr, *E = nullptr, *lam = nullptr, *dsc = nullptr;
     int* info = nullptr;
     int* flag = nullptr;
