@@ -20,6 +20,14 @@ namespace {
 constexpr int CB = 64;          // panel width
 constexpr int CP = CB + 1;      // LDS pitch
 
+// value of v in lane `lane` (wave-uniform) of the wave
+__device__ inline double readlane_d(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ inline zd zsub_mul_conj(zd acc, zd a, zd b)   // acc - a conj(b)
 {
     acc.x -= a.x * b.x + a.y * b.y;
@@ -27,31 +35,32 @@ __device__ inline zd zsub_mul_conj(zd acc, zd a, zd b)   // acc - a conj(b)
     return acc;
 }
 
-// Factors the diagonal block at k0 in LDS (one workgroup), writes L11 to A and L11^{-1} (64 x 64,
-// column-major, zero above the diagonal, identity beyond nb) to D.
-__global__ __launch_bounds__(256) void k_chol_diag(int n, int k0, zd* __restrict__ A, int lda, int* __restrict__ info,
-                                                   zd* __restrict__ D)
+// Factors the nb x nb (nb <= 64) diagonal block at A in LDS (one workgroup), writes L11 to A and
+// L11^{-1} (64 x 64, column-major, zero above the diagonal, identity beyond nb) to D.  col0: global
+// index of the block's first column (for the pivot reported in *info).
+__global__ __launch_bounds__(256) void k_chol_diag(int nb, int col0, zd* __restrict__ A, int lda,
+                                                   int* __restrict__ info, zd* __restrict__ D)
 {
     __shared__ zd L[CB * CP];    // diagonal block, factored in place (lower)
     __shared__ zd X[CB * CP];    // L11^{-1}
     const int tid = threadIdx.x;
-    const int nb = min(CB, n - k0);
     // lower triangle (the upper is never read), identity padding beyond nb
     #pragma unroll
     for (int e = tid; e < CB * CB; e += 256) {
         const int i = e % CB, j = e / CB;
         zd v = make_double2(i == j ? 1.0 : 0.0, 0.0);
         if (i < nb && j < nb && i >= j) {
-            v = A[(size_t)(k0 + i) + (size_t)(k0 + j) * lda];
+            v = A[(size_t)i + (size_t)j * lda];
             if (i == j) v.y = 0.0;
         }
         L[i * CP + j] = v;
     }
     __syncthreads();
     // right-looking Cholesky, four columns at a time: wave 0 factors the 64 x 4 column panel in
-    // registers (lane = row, diagonal entries shared by shuffles), then all threads apply the rank-4
-    // update to the trailing lower triangle
-    const int lane = tid & 63;
+    // registers (lane = row; the diagonal and the panel rows are broadcast with v_readlane), then
+    // all threads apply the rank-4 update to the trailing lower triangle (lane = row i, the waves
+    // take every fourth column j; the entries of row j are broadcast reads)
+    const int lane = tid & 63, wave = tid >> 6;
     for (int k = 0; k < CB; k += 4) {
         if (tid < 64) {
             zd v[4];
@@ -60,15 +69,15 @@ __global__ __launch_bounds__(256) void k_chol_diag(int n, int k0, zd* __restrict
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int kc = k + c;
-                const double d = __shfl(v[c].x, kc);
-                if (lane == 0 && !(d > 0.0) && kc < nb && info) atomicCAS(info, 0, k0 + kc + 1);
+                const double d = readlane_d(v[c].x, kc);
+                if (lane == 0 && !(d > 0.0) && kc < nb && info) atomicCAS(info, 0, col0 + kc + 1);
                 const double sd = sqrt(d > 0.0 ? d : 1.0), inv = 1.0 / sd;
                 if (lane > kc) v[c] = make_double2(v[c].x * inv, v[c].y * inv);
                 else if (lane == kc) v[c] = make_double2(sd, 0.0);
 #pragma unroll
                 for (int j = c + 1; j < 4; ++j) {   // columns k + j of the panel, rows >= k + j
-                    const double lr = __shfl(v[c].x, k + j), li = __shfl(v[c].y, k + j);
-                    if (lane >= k + j) v[j] = zsub_mul_conj(v[j], v[c], make_double2(lr, li));
+                    const zd l = make_double2(readlane_d(v[c].x, k + j), readlane_d(v[c].y, k + j));
+                    if (lane >= k + j) v[j] = zsub_mul_conj(v[j], v[c], l);
                 }
             }
 #pragma unroll
@@ -76,20 +85,24 @@ __global__ __launch_bounds__(256) void k_chol_diag(int n, int k0, zd* __restrict
                 if (lane >= k + c) L[lane * CP + k + c] = v[c];
         }
         __syncthreads();
-        const int r0t = k + 4, rem = CB - r0t;
-        for (int e = tid; e < rem * rem; e += 256) {
-            const int i = r0t + e % rem, j = r0t + e / rem;
-            if (i < j) continue;
-            zd acc = L[i * CP + j];
+        const int r0t = k + 4;
+        if (lane >= r0t) {
+            zd a[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc = zsub_mul_conj(acc, L[i * CP + k + c], L[j * CP + k + c]);
-            L[i * CP + j] = acc;
+            for (int c = 0; c < 4; ++c) a[c] = L[lane * CP + k + c];
+            for (int j = r0t + wave; j < CB; j += 4) {
+                if (j > lane) break;
+                zd acc = L[lane * CP + j];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc = zsub_mul_conj(acc, a[c], L[j * CP + k + c]);
+                L[lane * CP + j] = acc;
+            }
         }
         __syncthreads();
     }
     for (int e = tid; e < nb * nb; e += 256) {
         const int i = e % nb, j = e / nb;
-        if (i >= j) A[(size_t)(k0 + i) + (size_t)(k0 + j) * lda] = L[i * CP + j];
+        if (i >= j) A[(size_t)i + (size_t)j * lda] = L[i * CP + j];
     }
     tri64::lower_inverse(L, X);
     #pragma unroll
@@ -101,27 +114,52 @@ __global__ __launch_bounds__(256) void k_chol_diag(int n, int k0, zd* __restrict
 
 }  // namespace
 
+namespace {
+
+// recursive on halves (split at a multiple of 64) above 1024: L11 = chol(A11), L21 = A21 L11^{-H}
+// (a triangular solve with the inverses just stored), A22 -= L21 L21^H (one GEMM with K = n / 2),
+// L22 = chol(A22); up to 1024, right-looking over 64-column panels (fewer launches)
+int chol_rec(hipStream_t s, int k0, int n, zd* A, int lda, int* info, zd* dinv, const GemmWs& gw)
+{
+    if (n <= 1024) {
+        for (int j0 = 0; j0 < n; j0 += CB) {
+            const int nb = std::min(CB, n - j0);
+            zd* Ajj = A + j0 + (size_t)j0 * lda;
+            zd* D = dinv + (size_t)(j0 / CB) * CB * CB;
+            hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, nb, k0 + j0, Ajj, lda, info, D);
+            int rc = (int)hipGetLastError();
+            if (rc != 0) return rc;
+            const int m2 = n - j0 - nb;
+            if (m2 > 0) {
+                zd* L21 = Ajj + nb;
+                rc = tri_apply(s, TA_RIGHT_C, nb, m2, D, L21, lda);   // L21 = A21 L11^{-H}
+                if (rc != 0) return rc;
+                rc = launch_zgemm(s, OP_N, OP_C, m2, m2, nb, -1.0, L21, lda, L21, lda, 1.0, Ajj + nb + (size_t)nb * lda,
+                                  lda, gw);
+                if (rc != 0) return rc;
+            }
+        }
+        return 0;
+    }
+    const int h = CB * (((n + CB - 1) / CB + 1) / 2);
+    int rc = chol_rec(s, k0, h, A, lda, info, dinv, gw);
+    if (rc != 0) return rc;
+    zd* L21 = A + h;
+    rc = trsm_right_lower_h(s, n - h, h, A, lda, dinv, L21, lda, gw);
+    if (rc != 0) return rc;
+    rc = launch_zgemm(s, OP_N, OP_C, n - h, n - h, h, -1.0, L21, lda, L21, lda, 1.0, A + h + (size_t)h * lda, lda, gw);
+    if (rc != 0) return rc;
+    return chol_rec(s, k0 + h, n - h, A + h + (size_t)h * lda, lda, info, dinv + (size_t)(h / CB) * CB * CB, gw);
+}
+
+}  // namespace
+
 // L L^H = A (n x n, lower triangle of A read, L written in place).  *info (device, zeroed by the
 // caller) receives the first non-positive pivot (1-based) or stays 0.  dinv (device,
 // tri_dinv_elems(n) elements) receives the inverses of the 64 x 64 diagonal blocks of L, which the
-// triangular solves with this L take.  gw: workspace of the trailing GEMMs.  Returns hipError_t as int.
+// triangular solves with this L take.  gw: workspace of the GEMMs.  Returns hipError_t as int.
 int chol_lower(hipStream_t s, int n, zd* A, int lda, int* info, zd* dinv, const GemmWs& gw)
 {
-    for (int k0 = 0; k0 < n; k0 += CB) {
-        const int nb = std::min(CB, n - k0);
-        zd* D = dinv + (size_t)(k0 / CB) * CB * CB;
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, n, k0, A, lda, info, D);
-        int rc = (int)hipGetLastError();
-        if (rc != 0) return rc;
-        const int m2 = n - k0 - nb;
-        if (m2 > 0) {
-            zd* L21 = A + (size_t)(k0 + nb) + (size_t)k0 * lda;
-            zd* A22 = A + (size_t)(k0 + nb) + (size_t)(k0 + nb) * lda;
-            rc = tri_apply(s, TA_RIGHT_C, nb, m2, D, L21, lda);   // L21 = A21 L11^{-H}
-            if (rc != 0) return rc;
-            rc = launch_zgemm(s, OP_N, OP_C, m2, m2, nb, -1.0, L21, lda, L21, lda, 1.0, A22, lda, gw);
-            if (rc != 0) return rc;
-        }
-    }
-    return 0;
+    if (n <= 0) return 0;
+    return chol_rec(s, 0, n, A, lda, info, dinv, gw);
 }

@@ -14,6 +14,14 @@ constexpr int N = 64, P = 65, B = 16;
 __device__ inline zd cmul(zd a, zd b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline zd cadd(zd a, zd b) { return make_double2(a.x + b.x, a.y + b.y); }
 
+// v from lane ^ 1 and lane ^ 2 of the same quad (DPP quad permutations [1,0,3,2], [2,3,0,1])
+template <int CTRL> __device__ inline double quad_perm(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // L: lower triangle read (pitch P); X: receives L^{-1}, lower, zeros above the diagonal.  L's
 // diagonal must be real and nonzero.  256 threads; ends with a barrier.
 __device__ inline void lower_inverse(const zd* L, zd* X)
@@ -39,10 +47,10 @@ __device__ inline void lower_inverse(const zd* L, zd* X)
                 const int l = 4 * q + t;
                 if (l < i && l >= c) acc = cadd(acc, cmul(L[(o + i) * P + o + l], x[q]));
             }
-            acc.x += __shfl_xor(acc.x, 1);
-            acc.y += __shfl_xor(acc.y, 1);
-            acc.x += __shfl_xor(acc.x, 2);
-            acc.y += __shfl_xor(acc.y, 2);
+            acc.x += quad_perm<0xB1>(acc.x);
+            acc.y += quad_perm<0xB1>(acc.y);
+            acc.x += quad_perm<0x4E>(acc.x);
+            acc.y += quad_perm<0x4E>(acc.y);
             const double d = 1.0 / L[(o + i) * P + o + i].x;
             const zd v = (i < c) ? make_double2(0.0, 0.0)
                                  : make_double2(((i == c ? 1.0 : 0.0) - acc.x) * d, -acc.y * d);

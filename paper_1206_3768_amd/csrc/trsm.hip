@@ -5,9 +5,10 @@
 //   trsm_left_lower    L X = B          (H = L^{-1} A, first half of the reduction)
 //   trsm_left_lower_h  L^H X = B        (X = L^{-H} V, back-transform of the eigenvectors)
 //   trsm_right_lower_h X L^H = B        (H = W L^{-H}, second half; Q = Y R^{-1} of Cholesky QR)
-// Each solve runs over the 64-blocks of the triangular dimension in dependency order: one
-// launch multiplies a block row (or column) of B by the stored inverse in place, then one GEMM
-// subtracts its contribution from the rest.  Only the lower triangle of L is read.
+// A large solve recurses on halves of the triangular dimension (solve one half, subtract its
+// contribution from the other with one GEMM, solve the other half); up to 1024 it runs over the
+// 64-blocks, each one in-place product with its stored inverse followed by one GEMM for the rest.
+// Only the lower triangle of L is read.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,17 +80,26 @@ int tri_apply(hipStream_t s, int mode, int nb, int nvec, const zd* D, zd* B, int
     return (int)hipGetLastError();
 }
 
-// L X = B, L n x n lower, B n x nrhs (overwritten by X).
-int trsm_left_lower(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
-                    const GemmWs& gw)
+namespace {
+
+// first index of the second half of [0, n): a multiple of TB, so that every sub-block starts on a
+// stored diagonal block
+inline int split_point(int n) { return TB * (((n + TB - 1) / TB + 1) / 2); }
+
+// The solves recurse on halves of the triangular dimension down to REC_MIN, so that most of the
+// work of a large solve is in a few GEMMs with a long inner dimension; below REC_MIN they run over
+// the 64-blocks (one in-place product with the stored inverse, then one GEMM with K = 64 for the
+// rest), which takes fewer launches.  L, dinv and B point at the sub-problem's origin.
+constexpr int REC_MIN = 1024;
+
+int loop_left(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb, const GemmWs& gw)
 {
     for (int k0 = 0; k0 < n; k0 += TB) {
         const int nb = std::min(TB, n - k0);
         int rc = tri_apply(s, TA_LEFT_N, nb, nrhs, dinv + (size_t)(k0 / TB) * TB * TB, B + k0, ldb);
         if (rc != 0) return rc;
-        const int rest = n - k0 - nb;
-        if (rest > 0) {   // B(k0+nb:, :) -= L(k0+nb:, k0:k0+nb) X(k0:k0+nb, :)
-            rc = launch_zgemm(s, OP_N, OP_N, rest, nrhs, nb, -1.0, L + (size_t)(k0 + nb) + (size_t)k0 * ldl, ldl,
+        if (n - k0 - nb > 0) {   // B(k0+nb:, :) -= L(k0+nb:, k0:k0+nb) X(k0:k0+nb, :)
+            rc = launch_zgemm(s, OP_N, OP_N, n - k0 - nb, nrhs, nb, -1.0, L + (size_t)(k0 + nb) + (size_t)k0 * ldl, ldl,
                               B + k0, ldb, 1.0, B + k0 + nb, ldb, gw);
             if (rc != 0) return rc;
         }
@@ -97,12 +107,10 @@ int trsm_left_lower(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const 
     return 0;
 }
 
-// L^H X = B, L n x n lower, B n x nrhs (overwritten by X).
-int trsm_left_lower_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
-                      const GemmWs& gw)
+int loop_left_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                const GemmWs& gw)
 {
-    const int nblk = (n + TB - 1) / TB;
-    for (int kb = nblk - 1; kb >= 0; --kb) {
+    for (int kb = (n + TB - 1) / TB - 1; kb >= 0; --kb) {
         const int k0 = kb * TB, nb = std::min(TB, n - k0);
         int rc = tri_apply(s, TA_LEFT_C, nb, nrhs, dinv + (size_t)kb * TB * TB, B + k0, ldb);
         if (rc != 0) return rc;
@@ -114,20 +122,81 @@ int trsm_left_lower_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, cons
     return 0;
 }
 
-// X L^H = B, L ncol x ncol lower, B nrow x ncol (overwritten by X).
-int trsm_right_lower_h(hipStream_t s, int nrow, int ncol, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
-                       const GemmWs& gw)
+int loop_right_h(hipStream_t s, int nrow, int n, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                 const GemmWs& gw)
 {
-    for (int k0 = 0; k0 < ncol; k0 += TB) {
-        const int nb = std::min(TB, ncol - k0);
+    for (int k0 = 0; k0 < n; k0 += TB) {
+        const int nb = std::min(TB, n - k0);
         int rc = tri_apply(s, TA_RIGHT_C, nb, nrow, dinv + (size_t)(k0 / TB) * TB * TB, B + (size_t)k0 * ldb, ldb);
         if (rc != 0) return rc;
-        const int rest = ncol - k0 - nb;
-        if (rest > 0) {   // B(:, k0+nb:) -= X(:, k0:k0+nb) L(k0+nb:, k0:k0+nb)^H
-            rc = launch_zgemm(s, OP_N, OP_C, nrow, rest, nb, -1.0, B + (size_t)k0 * ldb, ldb,
+        if (n - k0 - nb > 0) {   // B(:, k0+nb:) -= X(:, k0:k0+nb) L(k0+nb:, k0:k0+nb)^H
+            rc = launch_zgemm(s, OP_N, OP_C, nrow, n - k0 - nb, nb, -1.0, B + (size_t)k0 * ldb, ldb,
                               L + (size_t)(k0 + nb) + (size_t)k0 * ldl, ldl, 1.0, B + (size_t)(k0 + nb) * ldb, ldb, gw);
             if (rc != 0) return rc;
         }
     }
     return 0;
+}
+
+int rec_left(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb, const GemmWs& gw)
+{
+    if (n <= REC_MIN) return loop_left(s, n, nrhs, L, ldl, dinv, B, ldb, gw);
+    const int h = split_point(n);
+    int rc = rec_left(s, h, nrhs, L, ldl, dinv, B, ldb, gw);
+    if (rc != 0) return rc;
+    // B2 -= L21 X1
+    rc = launch_zgemm(s, OP_N, OP_N, n - h, nrhs, h, -1.0, L + h, ldl, B, ldb, 1.0, B + h, ldb, gw);
+    if (rc != 0) return rc;
+    return rec_left(s, n - h, nrhs, L + h + (size_t)h * ldl, ldl, dinv + (size_t)(h / TB) * TB * TB, B + h, ldb, gw);
+}
+
+int rec_left_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb, const GemmWs& gw)
+{
+    if (n <= REC_MIN) return loop_left_h(s, n, nrhs, L, ldl, dinv, B, ldb, gw);
+    const int h = split_point(n);
+    int rc = rec_left_h(s, n - h, nrhs, L + h + (size_t)h * ldl, ldl, dinv + (size_t)(h / TB) * TB * TB, B + h, ldb, gw);
+    if (rc != 0) return rc;
+    // B1 -= L21^H X2
+    rc = launch_zgemm(s, OP_C, OP_N, h, nrhs, n - h, -1.0, L + h, ldl, B + h, ldb, 1.0, B, ldb, gw);
+    if (rc != 0) return rc;
+    return rec_left_h(s, h, nrhs, L, ldl, dinv, B, ldb, gw);
+}
+
+int rec_right_h(hipStream_t s, int nrow, int n, const zd* L, int ldl, const zd* dinv, zd* B, int ldb, const GemmWs& gw)
+{
+    if (n <= REC_MIN) return loop_right_h(s, nrow, n, L, ldl, dinv, B, ldb, gw);
+    const int h = split_point(n);
+    int rc = rec_right_h(s, nrow, h, L, ldl, dinv, B, ldb, gw);
+    if (rc != 0) return rc;
+    // B2 -= X1 L21^H
+    rc = launch_zgemm(s, OP_N, OP_C, nrow, n - h, h, -1.0, B, ldb, L + h, ldl, 1.0, B + (size_t)h * ldb, ldb, gw);
+    if (rc != 0) return rc;
+    return rec_right_h(s, nrow, n - h, L + h + (size_t)h * ldl, ldl, dinv + (size_t)(h / TB) * TB * TB,
+                       B + (size_t)h * ldb, ldb, gw);
+}
+
+}  // namespace
+
+// L X = B, L n x n lower, B n x nrhs (overwritten by X).
+int trsm_left_lower(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                    const GemmWs& gw)
+{
+    if (n <= 0 || nrhs <= 0) return 0;
+    return rec_left(s, n, nrhs, L, ldl, dinv, B, ldb, gw);
+}
+
+// L^H X = B, L n x n lower, B n x nrhs (overwritten by X).
+int trsm_left_lower_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                      const GemmWs& gw)
+{
+    if (n <= 0 || nrhs <= 0) return 0;
+    return rec_left_h(s, n, nrhs, L, ldl, dinv, B, ldb, gw);
+}
+
+// X L^H = B, L ncol x ncol lower, B nrow x ncol (overwritten by X).
+int trsm_right_lower_h(hipStream_t s, int nrow, int ncol, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                       const GemmWs& gw)
+{
+    if (nrow <= 0 || ncol <= 0) return 0;
+    return rec_right_h(s, nrow, ncol, L, ldl, dinv, B, ldb, gw);
 }
