@@ -167,7 +167,8 @@ def bench_learned_degree(h, cycles: int = 10) -> dict:
         res[f"fixed{d}"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=d)
     res["analytic+2"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=2)
     res["learned"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED)
-    res["fixed25_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=25, precision=chfsi.FP32)
+    for d in (16, 20, 25):
+        res[f"fixed{d}_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=d, precision=chfsi.FP32)
     res["learned_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED, precision=chfsi.FP32)
     h.set_degree_model(None)
     out = {k: {"time_to_solution_ms": round(v["ms"], 1), "matvecs": v["matvecs"], "loops": v["loops"],
@@ -178,6 +179,9 @@ def bench_learned_degree(h, cycles: int = 10) -> dict:
     out["learned_vs_best_fixed_time"] = round(res[best]["ms"] / res["learned"]["ms"], 3)
     out["learned_fp32_vs_best_fixed_time"] = round(res[best]["ms"] / res["learned_fp32"]["ms"], 3)
     out["learned_vs_best_fixed_matvecs"] = round(res[best]["matvecs"] / res["learned"]["matvecs"], 3)
+    best32 = min((k for k in res if k.startswith("fixed") and k.endswith("fp32")), key=lambda k: res[k]["ms"])
+    out["best_fixed_fp32"] = best32
+    out["learned_fp32_vs_best_fixed_fp32_time"] = round(res[best32]["ms"] / res["learned_fp32"]["ms"], 3)
     out["workload"] = f"n=4096 standard sequence, seed 0, warm cycles 1..{cycles - 1}, nev 256, nex 64"
     return out
 

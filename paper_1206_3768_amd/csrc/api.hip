@@ -417,6 +417,26 @@ chfsi_status st_loop_complete(chfsi_handle h, SolveState& s)
     if (p.deg_margin != 0 && (p.degree_policy == CHFSI_DEG_ANALYTIC || p.degree_policy == CHFSI_DEG_LEARNED))
         for (int j = cnt; j < ma; ++j)
             s.deg[nlocked + j] = std::max(p.deg_min, std::min(p.deg_max, s.deg[nlocked + j] + p.deg_margin));
+    // With a per-vector degree (analytic or learned, chosen to bring each residual to the locking
+    // threshold in one loop) a column keeps the low-precision filter for the next loop only while
+    // that loop is not expected to take its residual below the switch level: predicted r / rho^d,
+    // rho = |t| + sqrt(t^2 - 1) the growth per step of T_d at its Ritz value (the model of the
+    // analytic rule).  A vector filtered in low precision stops near that level, so filtering it
+    // there in low precision would cost one more loop.  (With a fixed degree the prediction is
+    // looser and the switch waits for the residual itself.)
+    if (s.prec != CHFSI_FP64 && (p.degree_policy == CHFSI_DEG_ANALYTIC || p.degree_policy == CHFSI_DEG_LEARNED)) {
+        const double c2 = 0.5 * (a + bb), e2 = 0.5 * (bb - a), lthr = std::log10(s.sw_thr);
+        for (int j = cnt; j < ma; ++j) {
+            const int pos = nlocked + j;
+            const double t = (hth[j] - c2) / e2;
+            if (!s.lowp[pos] || !(std::fabs(t) > 1.0)) continue;
+            const double rho = std::fabs(t) + std::sqrt(t * t - 1.0);
+            if (std::log10(std::max(hr[j], 1e-300)) - s.deg[pos] * std::log10(rho) <= lthr) {
+                s.lowp[pos] = 0;
+                ++s.switches;
+            }
+        }
+    }
     if (p.trace) {
         const double c2 = 0.5 * (a + bb), e2 = 0.5 * (bb - a);
         for (int j = cnt; j < ma; ++j) {
