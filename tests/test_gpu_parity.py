@@ -163,8 +163,9 @@ def test_filter_closed_form_diagonal(hd, orc):
 
 # ---- reduction, Lanczos, QR, Rayleigh-Ritz ------------------------------------------------------
 
-def test_reduce_parity(hd, orc, torch_dev):
-    spec = synth.SequenceSpec(n=257, n_low=20, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=8)
+@pytest.mark.parametrize("n", [257, 1100])   # 1100: the recursive split above 1024 with a ragged tail
+def test_reduce_parity(hd, orc, torch_dev, n):
+    spec = synth.SequenceSpec(n=n, n_low=20, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=8)
     p = synth.designed_pencil(spec, keep_vectors=False)
     Lr, st = orc.cholesky(p.S)
     Hr = orc.reduce(p.A, Lr)
@@ -176,13 +177,14 @@ def test_reduce_parity(hd, orc, torch_dev):
     assert relerr(host(dH), Hr) <= 1e-12
 
 
-def test_reduce_rejects_non_hpd(hd, torch_dev):
+@pytest.mark.parametrize("n,bad", [(40, 5), (1100, 1050)])
+def test_reduce_rejects_non_hpd(hd, torch_dev, n, bad):
     from paper_1206_3768_amd import chfsi
-    S = np.eye(40, dtype=complex)
-    S[5, 5] = -1
-    dH = torch_dev.empty((40, 40), dtype=torch_dev.complex128, device="cuda")
+    S = np.eye(n, dtype=complex)
+    S[bad, bad] = -1
+    dH = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
     with pytest.raises(chfsi.ChfsiError) as ei:
-        hd.reduce(dev(herm(40)), dev(S), dH, dH.clone())
+        hd.reduce(dev(herm(n)), dev(S), dH, dH.clone())
     assert ei.value.status == 2
 
 
@@ -345,6 +347,18 @@ def test_solve_generalized_sequence_matches_oracle(hd, orc):
         assert abs(res.stats["loops"] - ref.stats["loops"]) <= 1
         X_ref, b_ref = ref.X, (ref.lam[0], ref.lam[-1])
         X_gpu, b_gpu = X, (res.lam[0], res.lam[-1])
+
+
+def test_solve_generalized_above_recursion_size_matches_designed_spectrum(hd):
+    """n = 1100: the Cholesky factorisation and the triangular solves of the reduction and of the
+    back-transform take their recursive branch; the pencil's spectrum is known exactly."""
+    from paper_1206_3768_amd import chfsi
+    spec = synth.SequenceSpec(n=1100, n_low=55, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=4)
+    p = synth.designed_pencil(spec)
+    nev, nex = 40, 16
+    dX = dev(np.zeros((spec.n, nev + nex), dtype=complex))
+    res = hd.solve(dev(p.A), dev(p.S), dX, False, chfsi.default_params(nev=nev, nex=nex, deg=12, tol=1e-10, seed=2))
+    _check_solution(res, p.lam_exact, nev, np.linalg.norm(p.A, 2), host(dX), p.S)
 
 
 def test_solve_analytic_degree_policy(hd):
