@@ -350,11 +350,15 @@ chfsi_status st_loop_enqueue(chfsi_handle h, SolveState& s)
     s.filtered += ma;
     mark(s, PH_QR, st, true);
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, st));
-    TRYS(step_orthonormalize(h, n, ma, Ya, n, s.nlocked, b.V, n, b.G, b.Cm, b.dinvG, b.dsc, b.info, b.gw));
+    // (the eigensolver's pinned host buffer is free until Rayleigh-Ritz)
+    TRYS(step_orthonormalize(h, n, ma, Ya, n, s.nlocked, b.V, n, b.G, b.Cm, b.dinvG, b.dsc, b.info, b.gw,
+                             s.h_eig()));
     mark(s, PH_QR, st, false);
     mark(s, PH_RR, st, true);
+    // the Rayleigh quotient is diagonalised to a tenth of the locking threshold: a Ritz vector
+    // then differs from the exact one of the subspace by far less than the residual that locks it
     TRYS(step_rayleigh_ritz(h, n, s.H, s.ldh, ma, Ya, n, b.HY, b.T, b.G, b.theta, b.r, b.eigw, s.h_eig(), b.gw,
-                            s.tm));
+                            s.tm, 0.1 * s.thr));
     mark(s, PH_RR, st, false);
     TRY(hipMemcpyAsync(s.h_theta(), b.theta, sizeof(double) * ma, hipMemcpyDeviceToHost, st));
     TRY(hipMemcpyAsync(s.h_r(), b.r, sizeof(double) * ma, hipMemcpyDeviceToHost, st));

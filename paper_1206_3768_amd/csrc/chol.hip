@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(int nb, int col0, zd* __restr
                 const int kc = k + c;
                 const double d = readlane_d(v[c].x, kc);
                 if (lane == 0 && !(d > 0.0) && kc < nb && info) atomicCAS(info, 0, col0 + kc + 1);
-                const double sd = sqrt(d > 0.0 ? d : 1.0), inv = 1.0 / sd;
+                const double inv = rsqrt_nr(d > 0.0 ? d : 1.0), sd = (d > 0.0 ? d : 1.0) * inv;
                 if (lane > kc) v[c] = make_double2(v[c].x * inv, v[c].y * inv);
                 else if (lane == kc) v[c] = make_double2(sd, 0.0);
 #pragma unroll

@@ -21,6 +21,17 @@ __host__ __device__ inline zd zmul(zd a, zd b) { return make_double2(a.x * b.x -
 __host__ __device__ inline zd zcmul(zd a, zd b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }  // conj(a) b
 __host__ __device__ inline double zabs2(zd a) { return a.x * a.x + a.y * a.y; }
 
+// 1 / sqrt(x), x > 0 normal: the hardware estimate (v_rsq_f64) refined by two Newton steps, each of
+// which roughly squares the relative error, so any estimate good to 2^-14 ends at double precision
+__device__ inline double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * (1.5 - hx * y * y);
+    y = y * (1.5 - hx * y * y);
+    return y;
+}
+
 // ---- GEMM (gemm.hip) --------------------------------------------------------------------------
 // C = alpha op(A) op(B) + beta C, complex, op = N or C, all device pointers, real scalars.
 // `ws`/`ws_bytes` is scratch for split-K partials (may be null: no split).
@@ -127,7 +138,10 @@ size_t eig_work_bytes(int m);
 size_t eig_host_doubles(int m);
 // G (m x m, device) <- W with G = W diag(theta) W^H, theta ascending (device).  host: at least
 // eig_host_doubles(m) doubles.  Returns hipError_t as int, -1 when the sweeps did not converge.
-int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps);
+// stop_abs: off-diagonal level (absolute) that is accurate enough for the caller; the sweeps stop at
+// max(5e-14 scale, stop_abs) (0: at 5e-14 of the matrix scale)
+int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps,
+               double stop_abs = 0.0);
 
 // ---- degree network (mlp.hip) -------------------------------------------------------------------
 #define MLP_NF 5

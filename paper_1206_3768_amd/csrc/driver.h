@@ -123,10 +123,11 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
                           zd* c, double* coef_dev, std::vector<double>& theta, std::vector<double>& z1sq,
                           double& beta_k, int& k_used);
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
-                                 zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw);
+                                 zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw,
+                                 double* host_tmp = nullptr);
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY, zd* T,
                                 zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
-                                const GemmWs& gw, PhaseTimer* tm);
+                                const GemmWs& gw, PhaseTimer* tm, double eig_stop = 0.0);
 void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps);
 chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
                         const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);

@@ -13,8 +13,8 @@
 //   k_eig_apply  G <- J^H G J and W <- W J, one workgroup per 32 x 32 tile; J is block
 //                diagonal in block-pair order, so every tile is touched by exactly one workgroup.
 // After each sweep the largest off-diagonal modulus and the diagonal are copied to the host, which
-// stops once the off-diagonal is below 5e-14 of the matrix scale (rotations are skipped below
-// 1e-14 of it: the Ritz vectors are then exact to residuals far below the locking threshold).  A
+// stops once the off-diagonal is below 5e-14 of the matrix scale or below the caller's level
+// (rotations are skipped below a fifth of that level).  A
 // Rayleigh quotient of nearly converged Ritz vectors is nearly diagonal (its off-diagonal entries
 // are bounded by the residual norms), so the later loops of a solve need two or three sweeps.
 //
@@ -23,9 +23,9 @@
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = t c; Golub and Van
 // Loan, Matrix Computations, section 8.5) conjugated by diag(1, e^{-i phi}):
 //   R = [[c, s e^{i phi}], [-s e^{-i phi}, c]],   R^H G R diagonal.
-// With d = (b - a) / 2 and rho = sqrt(d^2 + |g|^2): t = sign(d) |g| / (|d| + rho) and
-// s e^{i phi} = sign(d) c g / (|d| + rho), so one sqrt, one reciprocal and one rsqrt suffice and
-// |g| itself is never needed (the threshold test compares |g|^2).
+// With d = (b - a) / 2 and rho = sqrt(d^2 + |g|^2): c^2 = (1 + |d| / rho) / 2 and
+// s e^{i phi} = sign(d) g / (2 rho c), so two reciprocal square roots suffice and |g| itself is never
+// needed (the threshold test compares |g|^2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -133,11 +133,14 @@ __global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, con
             double c = 1.0;
             zd se = make_double2(0.0, 0.0);
             if (g2 > tol2) {
+                // cos^2 = (1 + |d| / rho) / 2, s e^{i phi} = sign(d) g / (2 rho cos), rho = sqrt(d^2 + |g|^2):
+                // two reciprocal square roots, no cancellation (|d| / rho >= 0)
                 const double d = 0.5 * (A[q * EP + q].x - A[p * EP + p].x);
-                const double inv = 1.0 / (fabs(d) + sqrt(d * d + g2));
-                const double t2 = g2 * inv * inv;
-                c = rsqrt(1.0 + t2);
-                const double f = (d >= 0 ? c : -c) * inv;
+                const double irho = rsqrt_nr(d * d + g2);
+                const double w = 0.5 + 0.5 * fabs(d) * irho;
+                const double ic = rsqrt_nr(w);
+                c = w * ic;
+                const double f = (d >= 0 ? 0.5 : -0.5) * irho * ic;
                 se = make_double2(f * g.x, f * g.y);
                 rot[r] = 1;
             }
@@ -343,7 +346,8 @@ size_t eig_work_bytes(int m)
 // device memory; host: eig_host_doubles(m) doubles of host memory (pinned for speed).
 // *sweeps receives the sweeps taken.  Returns a hipError_t as int, or -1 when 40 sweeps did not
 // reach the threshold.
-int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps)
+int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, double* host, int* sweeps,
+               double stop_abs)
 {
     if (sweeps) *sweeps = 0;
     if (m <= 0) return 0;
@@ -364,8 +368,8 @@ int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, 
     if (rc != 0) return rc;
     double sc = 0;
     for (int j = 0; j < m; ++j) sc = std::max(sc, std::max(host[j], std::fabs(host[m + j])));
-    const double stop = 5e-14 * sc;        // off-diagonal target
-    const double rot = 1e-14 * sc;         // rotations below this are skipped
+    const double stop = std::max(5e-14 * sc, stop_abs);   // off-diagonal target
+    const double rot = 0.2 * stop;                         // rotations below this are skipped
     std::vector<int> act, pos(m, -1);
     std::vector<double> dval(m);
     for (int j = 0; j < m; ++j) {

@@ -388,8 +388,13 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
 // Cholesky QR followed by two Cholesky QR passes (shift s = 11 (n m + m (m+1)) u ||Y||_F^2 after
 // column normalisation; Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, SISC 2020).  R's
 // diagonal is real positive in every pass, so Q is the Q factor of Y.
+// With host_tmp (host memory, one double) the first Gram matrix decides: when its largest
+// off-diagonal row sum is below 1/2, Gershgorin bounds kappa(Y) by sqrt(3) and plain Cholesky QR
+// twice (no shift) is already accurate to rounding, so the shifted pass is left out (one host
+// synchronisation instead of one Cholesky QR pass).
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
-                                 zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw)
+                                 zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw,
+                                 double* host_tmp)
 {
     hipStream_t st = h->stream;
     if (ma <= 0) return CHFSI_SUCCESS;
@@ -402,9 +407,16 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
     TRY(launch_scale_cols_inv(st, n, ma, Y, ldy, dsc));
     const double u = 1.1102230246251565e-16;
     const double shift = 11.0 * ((double)n * ma + (double)ma * (ma + 1)) * u * (double)ma;
-    for (int pass = 0; pass < 3; ++pass) {
+    bool shifted = true;
+    for (int pass = 0; pass < (shifted ? 3 : 2); ++pass) {
         TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, Y, ldy, 0.0, G, ma, gw));
-        if (pass == 0) TRY(launch_add_diag_const(st, ma, G, ma, shift));
+        if (pass == 0 && host_tmp) {
+            TRY(launch_max_rowsum_abs(st, ma, G, ma, dsc));
+            TRY(hipMemcpyAsync(host_tmp, dsc, sizeof(double), hipMemcpyDeviceToHost, st));
+            TRY(hipStreamSynchronize(st));
+            shifted = !(host_tmp[0] - 1.0 < 0.5);
+        }
+        if (pass == 0 && shifted) TRY(launch_add_diag_const(st, ma, G, ma, shift));
         // G = L L^H = R^H R with R = L^H; Y <- Y R^{-1} = Y L^{-H}
         TRY(chol_lower(st, ma, G, ma, info_dev + pass, dinv, gw));
         TRY(trsm_right_lower_h(st, n, ma, G, ma, dinv, Y, ldy, gw));
@@ -415,16 +427,16 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
 // Rayleigh-Ritz on orthonormal Y (n x ma): HY = H Y, G = Y^H HY, G = W diag(theta) W^H (ascending,
 // phase-normalised W, block-Jacobi eigensolver of eig.hip), Y <- Y W, HY <- HY W, then
 // r_j = ||HY_j - theta_j Y_j||.  eig_work: eig_work_bytes(ma) bytes of device memory; eig_host:
-// eig_host_doubles(ma) doubles of host memory.
+// eig_host_doubles(ma) doubles of host memory; eig_stop: see eig_jacobi.
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY,
                                 zd* T, zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
-                                const GemmWs& gw, PhaseTimer* tm)
+                                const GemmWs& gw, PhaseTimer* tm, double eig_stop)
 {
     hipStream_t st = h->stream;
     TRY(launch_zgemm(st, OP_N, OP_N, n, ma, n, 1.0, H, ldh, Y, ldy, 0.0, HY, n, gw));
     TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, HY, n, 0.0, G, ma, gw));
     int sweeps = 0;
-    const int rc = eig_jacobi(st, ma, G, ma, theta_dev, eig_work, eig_host, &sweeps);
+    const int rc = eig_jacobi(st, ma, G, ma, theta_dev, eig_work, eig_host, &sweeps, eig_stop);
     if (rc == -1) return CHFSI_ERR_NUMERIC;
     TRY(rc);
     TRY(launch_phase_normalize(st, ma, ma, G, ma));
