@@ -44,16 +44,25 @@ __global__ __launch_bounds__(256) void k_chol_diag(int nb, int col0, zd* __restr
     __shared__ zd L[CB * CP];    // diagonal block, factored in place (lower)
     __shared__ zd X[CB * CP];    // L11^{-1}
     const int tid = threadIdx.x;
-    // lower triangle (the upper is never read), identity padding beyond nb
-    #pragma unroll
-    for (int e = tid; e < CB * CB; e += 256) {
-        const int i = e % CB, j = e / CB;
-        zd v = make_double2(i == j ? 1.0 : 0.0, 0.0);
-        if (i < nb && j < nb && i >= j) {
-            v = A[(size_t)i + (size_t)j * lda];
-            if (i == j) v.y = 0.0;
+    // lower triangle (the upper is never read), identity padding beyond nb: all 16 loads of a
+    // thread are issued (clamped into the block) before any is used
+    {
+        zd v[CB * CB / 256];
+#pragma unroll
+        for (int p = 0; p < CB * CB / 256; ++p) {
+            const int e = tid + 256 * p, i = e % CB, j = e / CB;
+            v[p] = A[(size_t)min(i, nb - 1) + (size_t)min(j, nb - 1) * lda];
         }
-        L[i * CP + j] = v;
+#pragma unroll
+        for (int p = 0; p < CB * CB / 256; ++p) {
+            const int e = tid + 256 * p, i = e % CB, j = e / CB;
+            zd w = make_double2(i == j ? 1.0 : 0.0, 0.0);
+            if (i < nb && j < nb && i >= j) {
+                w.x = v[p].x;
+                w.y = i == j ? 0.0 : v[p].y;
+            }
+            L[i * CP + j] = w;
+        }
     }
     __syncthreads();
     // right-looking Cholesky, four columns at a time: wave 0 factors the 64 x 4 column panel in
@@ -90,19 +99,26 @@ __global__ __launch_bounds__(256) void k_chol_diag(int nb, int col0, zd* __restr
             zd a[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) a[c] = L[lane * CP + k + c];
-            for (int j = r0t + wave; j < CB; j += 4) {
-                if (j > lane) break;
-                zd acc = L[lane * CP + j];
+            // columns j = r0t + wave + 4 t, j <= lane, four at a time so that their LDS reads overlap
+            for (int j0 = r0t + wave; j0 <= lane; j0 += 16) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc = zsub_mul_conj(acc, a[c], L[j * CP + k + c]);
-                L[lane * CP + j] = acc;
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + 4 * u;
+                    if (j <= lane) {
+                        zd acc = L[lane * CP + j];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc = zsub_mul_conj(acc, a[c], L[j * CP + k + c]);
+                        L[lane * CP + j] = acc;
+                    }
+                }
             }
         }
         __syncthreads();
     }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e % nb, j = e / nb;
-        if (i >= j) A[(size_t)i + (size_t)j * lda] = L[i * CP + j];
+    #pragma unroll
+    for (int e = tid; e < CB * CB; e += 256) {
+        const int i = e % CB, j = e / CB;
+        if (i < nb && j < nb && i >= j) A[(size_t)i + (size_t)j * lda] = L[i * CP + j];
     }
     tri64::lower_inverse(L, X);
     #pragma unroll

@@ -28,6 +28,7 @@ __device__ inline void lower_inverse(const zd* L, zd* X)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // zero the strict upper triangle and the off-diagonal blocks' upper parts
+#pragma unroll
     for (int e = tid; e < N * N; e += 256) {
         const int i = e % N, j = e / N;
         if (i < j) X[i * P + j] = make_double2(0.0, 0.0);
@@ -62,26 +63,43 @@ __device__ inline void lower_inverse(const zd* L, zd* X)
     __syncthreads();
     // off-diagonal blocks by distance: T = sum_k L_ik X_kj, then X_ij = -X_ii T
     __shared__ zd Tb[3 * B * B];
+    // (each thread takes elements tid, tid + 256, tid + 512 of the nblk blocks at once, and each sum
+    // runs in two halves, so that several independent chains of LDS reads and FMAs are in flight)
     for (int dist = 1; dist < 4; ++dist) {
         const int nblk = 4 - dist;                    // blocks (i, j) = (j + dist, j), j < nblk
-        for (int e = tid; e < nblk * B * B; e += 256) {
-            const int jb = e / (B * B), r = (e / B) % B, c = e % B;
-            const int ib = jb + dist;
-            zd acc = make_double2(0.0, 0.0);
-            for (int kb = jb; kb < ib; ++kb)
-#pragma unroll 4
-                for (int k = 0; k < B; ++k)
-                    acc = cadd(acc, cmul(L[(ib * B + r) * P + kb * B + k], X[(kb * B + k) * P + jb * B + c]));
-            Tb[e] = acc;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int e = tid + 256 * s;
+            if (e < nblk * B * B) {
+                const int jb = e / (B * B), r = (e / B) % B, c = e % B;
+                const int ib = jb + dist;
+                zd acc0 = make_double2(0.0, 0.0), acc1 = acc0;
+                for (int kb = jb; kb < ib; ++kb)
+#pragma unroll
+                    for (int k = 0; k < B; k += 2) {
+                        acc0 = cadd(acc0, cmul(L[(ib * B + r) * P + kb * B + k], X[(kb * B + k) * P + jb * B + c]));
+                        acc1 = cadd(acc1, cmul(L[(ib * B + r) * P + kb * B + k + 1],
+                                               X[(kb * B + k + 1) * P + jb * B + c]));
+                    }
+                Tb[e] = cadd(acc0, acc1);
+            }
         }
         __syncthreads();
-        for (int e = tid; e < nblk * B * B; e += 256) {
-            const int jb = e / (B * B), r = (e / B) % B, c = e % B;
-            const int ib = jb + dist;
-            zd acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-            for (int k = 0; k < B; ++k) acc = cadd(acc, cmul(X[(ib * B + r) * P + ib * B + k], Tb[jb * B * B + k * B + c]));
-            X[(ib * B + r) * P + jb * B + c] = make_double2(-acc.x, -acc.y);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int e = tid + 256 * s;
+            if (e < nblk * B * B) {
+                const int jb = e / (B * B), r = (e / B) % B, c = e % B;
+                const int ib = jb + dist;
+                zd acc0 = make_double2(0.0, 0.0), acc1 = acc0;
+#pragma unroll
+                for (int k = 0; k < B; k += 2) {
+                    acc0 = cadd(acc0, cmul(X[(ib * B + r) * P + ib * B + k], Tb[jb * B * B + k * B + c]));
+                    acc1 = cadd(acc1, cmul(X[(ib * B + r) * P + ib * B + k + 1], Tb[jb * B * B + (k + 1) * B + c]));
+                }
+                const zd acc = cadd(acc0, acc1);
+                X[(ib * B + r) * P + jb * B + c] = make_double2(-acc.x, -acc.y);
+            }
         }
         __syncthreads();
     }
