@@ -10,8 +10,9 @@
 //                no pair exceeds the threshold is skipped) and writes the accumulated rotation J.
 //                A single inner sweep per round costs at most one extra outer sweep and halves or
 //                better the inner work.
-//   k_eig_apply  G <- J^H G J and W <- W J, one workgroup per 32 x 32 tile; J is block
-//                diagonal in block-pair order, so every tile is touched by exactly one workgroup.
+//   k_eig_apply  G <- J^H G J and W <- W J, one workgroup per 32 x 32 tile (products on the FP64
+//                MFMA); J is block diagonal in block-pair order, so every tile is touched by
+//                exactly one workgroup.
 // After each sweep the largest off-diagonal modulus and the diagonal are copied to the host, which
 // stops once the off-diagonal is below 5e-14 of the matrix scale or below the caller's level
 // (rotations are skipped below a fifth of that level).  A
@@ -35,6 +36,7 @@
 #include <vector>
 
 #include "common.h"
+#include "gemm_tile.h"
 
 namespace {
 
@@ -191,6 +193,29 @@ __global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, con
     }
 }
 
+// 32 x 32 complex product op(A) B on the FP64 MFMA (v_mfma_f64_16x16x4f64, four real products per
+// complex one), A and B in LDS with pitch EP, op(A) = A or (CONJ_A) A^H.  Each of the 4 waves forms
+// one 16 x 16 output tile: register r of lane l holds row 16 (wave & 1) + (l & 15) and column
+// 16 (wave >> 1) + 4 r + (l >> 4).
+template <bool CONJ_A>
+__device__ inline void cgemm32(const zd* A, const zd* B, d4& cr, d4& ci)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = 16 * (wave & 1) + (lane & 15), col = 16 * (wave >> 1) + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { cr[r] = 0.0; ci[r] = 0.0; }
+#pragma unroll
+    for (int kk = 0; kk < ES / 4; ++kk) {
+        const int k = 4 * kk + (lane >> 4);
+        const zd a = CONJ_A ? zconjd(A[k * EP + row]) : A[row * EP + k];
+        const zd b = B[k * EP + col];
+        cr = chfsi_tile::mfma16(b.x, a.x, cr);
+        ci = chfsi_tile::mfma16(b.y, a.x, ci);
+        cr = chfsi_tile::mfma16(-b.y, a.y, cr);
+        ci = chfsi_tile::mfma16(b.x, a.y, ci);
+    }
+}
+
 // Kernel B: G <- J^H G J on the (pair p, pair q) tiles, W <- W J on (32-row slab, pair q) tiles.
 __global__ __launch_bounds__(256) void k_eig_apply(int M, int nb, int round, zd* __restrict__ Gp, zd* __restrict__ Wp,
                                                    const zd* __restrict__ J)
@@ -198,7 +223,7 @@ __global__ __launch_bounds__(256) void k_eig_apply(int M, int nb, int round, zd*
     __shared__ zd X[ES * EP];
     __shared__ zd Jq[ES * EP];
     __shared__ zd Jp[ES * EP];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int npair = nb / 2;
     const int b = blockIdx.x;
     const bool gpart = b < npair * npair;
@@ -222,43 +247,27 @@ __global__ __launch_bounds__(256) void k_eig_apply(int M, int nb, int round, zd*
         if (gpart) Jp[u * EP + v] = J[(size_t)p * ES * ES + e];
     }
     __syncthreads();
-    zd t[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {   // T = X Jq
-        const int e = tid + 256 * k, u = e % ES, v = e / ES;
-        zd s = make_double2(0.0, 0.0);
-        for (int w = 0; w < ES; ++w) {
-            const zd x = X[u * EP + w], y = Jq[w * EP + v];
-            s.x += x.x * y.x - x.y * y.y;
-            s.y += x.x * y.y + x.y * y.x;
-        }
-        t[k] = s;
-    }
+    d4 tr, ti;
+    cgemm32<false>(X, Jq, tr, ti);   // T = X Jq
+    const int row = 16 * (wave & 1) + (lane & 15);
     if (!gpart) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = tid + 256 * k, u = e % ES, v = e / ES;
-            Wp[(size_t)slab * ES + u + (size_t)sub_index(Pq, Qq, v) * M] = t[k];
+        for (int r = 0; r < 4; ++r) {
+            const int col = 16 * (wave >> 1) + 4 * r + (lane >> 4);
+            Wp[(size_t)slab * ES + row + (size_t)sub_index(Pq, Qq, col) * M] = make_double2(tr[r], ti[r]);
         }
         return;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int e = tid + 256 * k, u = e % ES, v = e / ES;
-        X[u * EP + v] = t[k];
-    }
+    for (int r = 0; r < 4; ++r) X[row * EP + 16 * (wave >> 1) + 4 * r + (lane >> 4)] = make_double2(tr[r], ti[r]);
     __syncthreads();
+    d4 gr, gi;
+    cgemm32<true>(Jp, X, gr, gi);    // G' = Jp^H T
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {   // G' = Jp^H T
-        const int e = tid + 256 * k, u = e % ES, v = e / ES;
-        zd s = make_double2(0.0, 0.0);
-        for (int w = 0; w < ES; ++w) {
-            const zd x = Jp[w * EP + u], y = X[w * EP + v];   // conj(Jp[w][u]) * T[w][v]
-            s.x += x.x * y.x + x.y * y.y;
-            s.y += x.x * y.y - x.y * y.x;
-        }
-        Gp[(size_t)sub_index(Pp, Qp, u) + (size_t)sub_index(Pq, Qq, v) * M] = s;
+    for (int r = 0; r < 4; ++r) {
+        const int col = 16 * (wave >> 1) + 4 * r + (lane >> 4);
+        Gp[(size_t)sub_index(Pp, Qp, row) + (size_t)sub_index(Pq, Qq, col) * M] = make_double2(gr[r], gi[r]);
     }
 }
 
