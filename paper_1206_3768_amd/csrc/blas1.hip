@@ -57,23 +57,27 @@ __global__ void k_c2z(int M, int N, const zf* A, int lda, zd* B, int ldb)
 }
 
 // H <- (H + H^H)/2, one thread per lower-triangle entry (diagonal: imaginary part dropped)
-__global__ void k_hermitize(int n, zd* H, int ldh)
+// 32 x 32 tiles: tile (bi, bj), bi >= bj, is read (coalesced) into LDS and written conjugate
+// transposed to tile (bj, bi)
+__global__ __launch_bounds__(256) void k_mirror_lower(int n, zd* H, int ldh)
 {
-    const size_t total = (size_t)n * n;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % n), j = (int)(e / n);
-        if (i < j) continue;
-        zd a = H[(size_t)i + (size_t)j * ldh];
-        if (i == j) {
-            H[(size_t)i + (size_t)j * ldh] = make_double2(a.x, 0.0);
-        } else {
-            zd b = H[(size_t)j + (size_t)i * ldh];
-            zd v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-            H[(size_t)i + (size_t)j * ldh] = v;
-            H[(size_t)j + (size_t)i * ldh] = make_double2(v.x, -v.y);
-        }
+    __shared__ zd T[32][33];
+    const int bi = blockIdx.x, bj = blockIdx.y;
+    if (bi < bj) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {   // T[c][rr] = H(bi*32 + rr, bj*32 + c)
+        const int i = bi * 32 + tx, j = bj * 32 + r;
+        if (i < n && j < n) T[r][tx] = H[(size_t)i + (size_t)j * ldh];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {   // H(i, j) = conj(H(j, i)) for i = bj*32 + tx < j = bi*32 + r
+        const int i = bj * 32 + tx, j = bi * 32 + r;
+        if (i >= n || j >= n || i > j) continue;
+        const zd v = T[tx][r];
+        H[(size_t)i + (size_t)j * ldh] = make_double2(v.x, i == j ? 0.0 : -v.y);
     }
 }
+
 
 // Philox4x64-10 (Salmon et al., SC'11): ten rounds with the published multipliers and Weyl
 // constants.  Element e of stream `stream` uses counter (e/2, stream, 0, 0) and key (seed, 0);
@@ -371,10 +375,12 @@ int launch_c2z(hipStream_t s, int M, int N, const zf* A, int lda, zd* B, int ldb
     return (int)hipGetLastError();
 }
 
-int launch_hermitize(hipStream_t s, int n, zd* H, int ldh)
+
+int launch_mirror_lower(hipStream_t s, int n, zd* H, int ldh)
 {
     if (n <= 0) return 0;
-    hipLaunchKernelGGL(k_hermitize, dim3(grid_for((size_t)n * n)), dim3(256), 0, s, n, H, ldh);
+    const int t = (n + 31) / 32;
+    hipLaunchKernelGGL(k_mirror_lower, dim3(t, t), dim3(256), 0, s, n, H, ldh);
     return (int)hipGetLastError();
 }
 

@@ -163,7 +163,7 @@ int chol_rec(hipStream_t s, int k0, int n, zd* A, int lda, int* info, zd* dinv, 
     zd* L21 = A + h;
     rc = trsm_right_lower_h(s, n - h, h, A, lda, dinv, L21, lda, gw);
     if (rc != 0) return rc;
-    rc = launch_zgemm(s, OP_N, OP_C, n - h, n - h, h, -1.0, L21, lda, L21, lda, 1.0, A + h + (size_t)h * lda, lda, gw);
+    rc = gemm_lower_nc(s, n - h, h, L21, lda, L21, lda, A + h + (size_t)h * lda, lda, gw);   // lower triangle only
     if (rc != 0) return rc;
     return chol_rec(s, k0 + h, n - h, A + h + (size_t)h * lda, lda, info, dinv + (size_t)(h / CB) * CB * CB, gw);
 }

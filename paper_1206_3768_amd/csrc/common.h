@@ -82,7 +82,8 @@ size_t bf16_hplanes_elems(int n, int nterms);
 int launch_zlacpy(hipStream_t s, int M, int N, const zd* A, int lda, zd* B, int ldb);
 int launch_z2c(hipStream_t s, int M, int N, const zd* A, int lda, zf* B, int ldb);   // complex128 -> complex64
 int launch_c2z(hipStream_t s, int M, int N, const zf* A, int lda, zd* B, int ldb);   // complex64 -> complex128
-int launch_hermitize(hipStream_t s, int n, zd* H, int ldh);
+// upper triangle <- conjugate transpose of the lower triangle, diagonal made real
+int launch_mirror_lower(hipStream_t s, int n, zd* H, int ldh);
 int launch_philox_block(hipStream_t s, unsigned long long seed, unsigned long long stream, int n, int m, zd* Y,
                         int ldy);
 // y[j] = conj(V[:, j]) . x  for j < ncols (column dot products; for Hermitian V this is V x)
@@ -131,6 +132,12 @@ int trsm_left_lower_h(hipStream_t s, int n, int nrhs, const zd* L, int ldl, cons
                       const GemmWs& gw);   // L^H X = B
 int trsm_right_lower_h(hipStream_t s, int nrow, int ncol, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
                        const GemmWs& gw);   // X L^H = B
+// lower triangle of X with X L^H = B (B n x n; what H = W L^{-H} needs when H is Hermitian)
+int trsm_right_lower_h_lowertri(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                                const GemmWs& gw);
+// lower triangle of C (n x n) -= A B^H, A and B n x K
+int gemm_lower_nc(hipStream_t s, int n, int K, const zd* A, int lda, const zd* B, int ldb, zd* C, int ldc,
+                  const GemmWs& gw);
 
 // ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
 int eig_padded_order(int m);

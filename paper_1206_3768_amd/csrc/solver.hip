@@ -314,8 +314,12 @@ chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, co
     TRY(launch_zero_upper(st, n, L, n));
     TRY(launch_zlacpy(st, n, n, A, lda, H, n));
     TRY(trsm_left_lower(st, n, n, L, n, dinv, H, n, gw));      // L^{-1} A
-    TRY(trsm_right_lower_h(st, n, n, L, n, dinv, H, n, gw));   // (L^{-1} A) L^{-H}
-    TRY(launch_hermitize(st, n, H, n));
+    // (L^{-1} A) L^{-H} is Hermitian: above n = 4096 only its lower triangle is solved for (a quarter
+    // of the reduction's work saved; below, the extra launches of the split cost more than that),
+    // then the lower triangle is mirrored
+    if (n > 4096) TRY(trsm_right_lower_h_lowertri(st, n, L, n, dinv, H, n, gw));
+    else TRY(trsm_right_lower_h(st, n, n, L, n, dinv, H, n, gw));
+    TRY(launch_mirror_lower(st, n, H, n));
     return CHFSI_SUCCESS;
 }
 

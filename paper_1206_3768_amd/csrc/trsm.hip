@@ -175,7 +175,65 @@ int rec_right_h(hipStream_t s, int nrow, int n, const zd* L, int ldl, const zd* 
                        B + (size_t)h * ldb, ldb, gw);
 }
 
+// lower triangle of X with X L^H = B (B n x n), over the 64-blocks: column block k0 needs rows >= k0
+// only, and the update of the later columns only the square below-right of it
+int loop_right_h_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* B, int ldb, const GemmWs& gw)
+{
+    for (int k0 = 0; k0 < n; k0 += TB) {
+        const int nb = std::min(TB, n - k0);
+        int rc = tri_apply(s, TA_RIGHT_C, nb, n - k0, dinv + (size_t)(k0 / TB) * TB * TB, B + k0 + (size_t)k0 * ldb,
+                           ldb);
+        if (rc != 0) return rc;
+        const int rest = n - k0 - nb;
+        if (rest > 0) {   // B(k0+nb:, k0+nb:) -= X(k0+nb:, k0:k0+nb) L(k0+nb:, k0:k0+nb)^H
+            rc = launch_zgemm(s, OP_N, OP_C, rest, rest, nb, -1.0, B + (k0 + nb) + (size_t)k0 * ldb, ldb,
+                              L + (k0 + nb) + (size_t)k0 * ldl, ldl, 1.0, B + (k0 + nb) + (size_t)(k0 + nb) * ldb, ldb,
+                              gw);
+            if (rc != 0) return rc;
+        }
+    }
+    return 0;
+}
+
+// [X11; X21] L11^H = [B11; B21] gives the lower part of X11 (recursively) and X21 in full; then
+// B22 -= X21 L21^H on its lower triangle, and the lower part of X22 recursively
+int rec_right_h_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* B, int ldb, const GemmWs& gw)
+{
+    if (n <= REC_MIN) return loop_right_h_lower(s, n, L, ldl, dinv, B, ldb, gw);
+    const int h = split_point(n);
+    int rc = rec_right_h_lower(s, h, L, ldl, dinv, B, ldb, gw);
+    if (rc != 0) return rc;
+    rc = rec_right_h(s, n - h, h, L, ldl, dinv, B + h, ldb, gw);
+    if (rc != 0) return rc;
+    rc = gemm_lower_nc(s, n - h, h, B + h, ldb, L + h, ldl, B + h + (size_t)h * ldb, ldb, gw);
+    if (rc != 0) return rc;
+    return rec_right_h_lower(s, n - h, L + h + (size_t)h * ldl, ldl, dinv + (size_t)(h / TB) * TB * TB,
+                             B + h + (size_t)h * ldb, ldb, gw);
+}
+
 }  // namespace
+
+// lower triangle of C (n x n) -= A B^H (A, B n x K): the diagonal blocks up to 512 as full GEMMs,
+// larger ones split in halves (the strictly upper quarter is never computed)
+int gemm_lower_nc(hipStream_t s, int n, int K, const zd* A, int lda, const zd* B, int ldb, zd* C, int ldc,
+                  const GemmWs& gw)
+{
+    if (n <= 512) return launch_zgemm(s, OP_N, OP_C, n, n, K, -1.0, A, lda, B, ldb, 1.0, C, ldc, gw);
+    const int h = split_point(n);
+    int rc = gemm_lower_nc(s, h, K, A, lda, B, ldb, C, ldc, gw);
+    if (rc != 0) return rc;
+    rc = launch_zgemm(s, OP_N, OP_C, n - h, h, K, -1.0, A + h, lda, B, ldb, 1.0, C + h, ldc, gw);
+    if (rc != 0) return rc;
+    return gemm_lower_nc(s, n - h, K, A + h, lda, B + h, ldb, C + h + (size_t)h * ldc, ldc, gw);
+}
+
+// lower triangle of X with X L^H = B, B n x n (the strictly upper part of B is left meaningless)
+int trsm_right_lower_h_lowertri(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,
+                                const GemmWs& gw)
+{
+    if (n <= 0) return 0;
+    return rec_right_h_lower(s, n, L, ldl, dinv, B, ldb, gw);
+}
 
 // L X = B, L n x n lower, B n x nrhs (overwritten by X).
 int trsm_left_lower(hipStream_t s, int n, int nrhs, const zd* L, int ldl, const zd* dinv, zd* B, int ldb,

@@ -177,6 +177,27 @@ def test_reduce_parity(hd, orc, torch_dev, n):
     assert relerr(host(dH), Hr) <= 1e-12
 
 
+def test_reduce_above_4096_by_sampled_identities(hd, torch_dev):
+    """n = 4160: the second triangular solve of the reduction computes only the lower triangle of
+    H (then mirrored).  Checked without the oracle (too slow at this size) on sampled entries:
+    (L L^H)_ij = S_ij and (L H L^H)_ij = A_ij, H exactly Hermitian, L lower."""
+    spec = synth.SequenceSpec(n=4160, n_low=200, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=5)
+    p = synth.designed_pencil(spec, keep_vectors=False)
+    n = spec.n
+    dH = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
+    dL = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
+    hd.reduce(dev(p.A), dev(p.S), dH, dL)
+    H, L = host(dH), host(dL)
+    assert np.array_equal(H, H.conj().T)
+    assert np.all(np.triu(L, 1) == 0)
+    rng = np.random.default_rng(3)
+    idx = [(int(i), int(j)) for i, j in rng.integers(0, n, size=(24, 2))] + [(0, 0), (n - 1, n - 1), (n - 1, 0), (4096, 63)]
+    scale_a = np.abs(p.A).max()
+    for i, j in idx:
+        assert abs(L[i] @ L[j].conj() - p.S[i, j]) <= 1e-12 * np.abs(p.S).max()
+        assert abs(L[i] @ H @ L[j].conj() - p.A[i, j]) <= 1e-11 * scale_a
+
+
 @pytest.mark.parametrize("n,bad", [(40, 5), (1100, 1050)])
 def test_reduce_rejects_non_hpd(hd, torch_dev, n, bad):
     from paper_1206_3768_amd import chfsi
