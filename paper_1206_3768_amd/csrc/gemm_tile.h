@@ -1,7 +1,7 @@
 // The complex MFMA tile shared by the single-problem GEMM / filter kernels (gemm.hip) and the
 // persistent multi-problem filter kernel (batched.hip).
 //
-// Complex products run as four real products on v_mfma_f64_16x16x4f64 (FP64) or
+// Complex products run as three real products (GAUSS3 below) on v_mfma_f64_16x16x4f64 (FP64) or
 // v_mfma_f32_16x16x4f32 (FP32).  The MFMA is used "transposed": its A operand carries op(B)
 // (row index = output column j) and its B operand carries op(A) (column index = output row i),
 // so that each lane ends up owning output elements of one output row i, and 16 lanes store 16
@@ -24,6 +24,17 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) { return __builti
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
 template <typename C2> __device__ __forceinline__ C2 cconj(C2 v) { v.y = -v.y; return v; }
+
+// Complex products as three real products (Gauss): re = ArBr - AiBi, im = (Ar + Ai)(Br + Bi) - ArBr -
+// AiBi, three MFMAs per complex multiply-add instead of four.  The error bound of the imaginary part
+// grows from (|Ar||Bi| + |Ai||Br|) to about (|Ar| + |Ai|)(|Br| + |Bi|) times the same multiple of the
+// unit roundoff (Higham, Accuracy and Stability of Numerical Algorithms, section 23.2.4): at most a
+// factor 2 on the rounding error of a product, FP64 or FP32.
+#ifdef CHFSI_TILE_FOUR_PRODUCTS
+constexpr bool GAUSS3 = false;
+#else
+constexpr bool GAUSS3 = true;
+#endif
 
 // Row of the 16x16 MFMA result held in register r of lane l.  Measured on gfx950:
 // v_mfma_f32_16x16x4f32 holds row 4 (l/16) + r, v_mfma_f64_16x16x4f64 holds row 4 r + l/16;
@@ -60,12 +71,13 @@ __device__ __forceinline__ void tile_mainloop(const typename CT<T>::c* __restric
     const int wr = (wave & 1) * (BM / 2), wc = (wave >> 1) * (BN / 2);
     const int nstages = ke > kb ? (ke - kb + BK - 1) / BK : 0;
 
+    typename CT<T>::acc acc2[MI][NJ];   // T2 of the three-product form (unused with four products)
 #pragma unroll
     for (int bi = 0; bi < MI; ++bi)
 #pragma unroll
         for (int bj = 0; bj < NJ; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { accr[bi][bj][r] = 0; acci[bi][bj][r] = 0; }
+            for (int r = 0; r < 4; ++r) { accr[bi][bj][r] = 0; acci[bi][bj][r] = 0; acc2[bi][bj][r] = 0; }
 
     C2 ra[NPA], rb[NPB];
 
@@ -126,22 +138,51 @@ __device__ __forceinline__ void tile_mainloop(const typename CT<T>::c* __restric
             for (int bi = 0; bi < MI; ++bi) a[bi] = as[kr * LDA_S + wr + bi * 16 + (lane & 15)];
 #pragma unroll
             for (int bj = 0; bj < NJ; ++bj) b[bj] = bs[kr * LDB_S + wc + bj * 16 + (lane & 15)];
-            // re += Bre Are ; im += Bim Are   (all blocks), then re -= Bim Aim ; im += Bre Aim
+            if constexpr (GAUSS3) {
+                // T1 += Bre Are (accr), T2 += Bim Aim (acc2), T3 += (Bre + Bim)(Are + Aim) (acci)
+                T as_[MI], bs_[NJ];
 #pragma unroll
-            for (int bi = 0; bi < MI; ++bi)
+                for (int bi = 0; bi < MI; ++bi) as_[bi] = a[bi].x + a[bi].y;
 #pragma unroll
-                for (int bj = 0; bj < NJ; ++bj) {
-                    accr[bi][bj] = mfma16(b[bj].x, a[bi].x, accr[bi][bj]);
-                    acci[bi][bj] = mfma16(b[bj].y, a[bi].x, acci[bi][bj]);
-                }
+                for (int bj = 0; bj < NJ; ++bj) bs_[bj] = b[bj].x + b[bj].y;
 #pragma unroll
-            for (int bi = 0; bi < MI; ++bi)
+                for (int bi = 0; bi < MI; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < NJ; ++bj) {
-                    accr[bi][bj] = mfma16(-b[bj].y, a[bi].y, accr[bi][bj]);
-                    acci[bi][bj] = mfma16(b[bj].x, a[bi].y, acci[bi][bj]);
-                }
+                    for (int bj = 0; bj < NJ; ++bj) {
+                        accr[bi][bj] = mfma16(b[bj].x, a[bi].x, accr[bi][bj]);
+                        acc2[bi][bj] = mfma16(b[bj].y, a[bi].y, acc2[bi][bj]);
+                        acci[bi][bj] = mfma16(bs_[bj], as_[bi], acci[bi][bj]);
+                    }
+            } else {
+                // re += Bre Are ; im += Bim Are   (all blocks), then re -= Bim Aim ; im += Bre Aim
+#pragma unroll
+                for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < NJ; ++bj) {
+                        accr[bi][bj] = mfma16(b[bj].x, a[bi].x, accr[bi][bj]);
+                        acci[bi][bj] = mfma16(b[bj].y, a[bi].x, acci[bi][bj]);
+                    }
+#pragma unroll
+                for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < NJ; ++bj) {
+                        accr[bi][bj] = mfma16(-b[bj].y, a[bi].y, accr[bi][bj]);
+                        acci[bi][bj] = mfma16(b[bj].x, a[bi].y, acci[bi][bj]);
+                    }
+            }
         }
+    }
+    if constexpr (GAUSS3) {   // re = T1 - T2, im = T3 - T1 - T2
+#pragma unroll
+        for (int bi = 0; bi < MI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NJ; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T t1 = accr[bi][bj][r], t2 = acc2[bi][bj][r];
+                    accr[bi][bj][r] = t1 - t2;
+                    acci[bi][bj][r] = acci[bi][bj][r] - t1 - t2;
+                }
     }
 #undef GEMM_GLOAD
 #undef GEMM_SSTORE
