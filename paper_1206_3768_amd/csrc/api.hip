@@ -58,7 +58,7 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
     b.dsc = ar.take<double>(2 * ((size_t)std::max(n, m) + 16));   // two independent scratch halves
     b.info = ar.take<int>(16);
     b.flag = ar.take<int>(m + 8);
-    b.iperm = ar.take<int>(m + 8);
+    b.iperm = ar.take<int>(2 * (size_t)m + 16);   // a column order and its inverse
     b.LV = ar.take<zd>((size_t)n * (k + 1));
     b.lw = ar.take<zd>(n);
     b.lc = ar.take<zd>(k + 1);
@@ -107,9 +107,21 @@ int analytic_degree(double theta, double r, double a, double b, double thr, int 
     return (int)std::min<double>(dmax, std::max<double>(dmin, d));
 }
 
+// Puts the columns of Y back into the order they had before the filter sorted them (the inverse
+// permutation is at b.iperm + ma): the order of ascending Ritz values.  Cholesky QR keeps the span
+// of every leading set of columns, so the nearly converged columns must lead; in the degree order
+// they would be mixed with the unconverged ones, which costs the Rayleigh-Ritz eigensolver sweeps.
+chfsi_status restore_column_order(chfsi_handle h, SolveBufs& b, int n, int ma, zd* Y, int ldy)
+{
+    hipStream_t st = h->stream;
+    TRY(launch_permute_cols(st, n, ma, Y, ldy, b.T, n, b.iperm + ma));
+    TRY(launch_zlacpy(st, n, ma, b.T, n, Y, ldy));
+    return CHFSI_SUCCESS;
+}
+
 // Filters the active block Y (n x ma) with per-column degrees deg and precision flags lowp
-// (1 = low precision).  Columns are reordered: low-precision group first, each group sorted by
-// non-increasing degree; the reordering is harmless because QR and Rayleigh-Ritz follow.
+// (1 = low precision).  Columns are reordered for the filter (low-precision group first, each group
+// sorted by non-increasing degree) and put back into their order afterwards.
 chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ldh, int prec, int ma, zd* Y, int ldy,
                         std::vector<int>& deg, std::vector<int>& lowp, double a, double bb, double mu1,
                         double& flops, long long& matvecs)
@@ -123,15 +135,17 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
     });
     bool ident = true;
     for (int j = 0; j < ma; ++j) ident &= ord[j] == j;
+    std::vector<int> perm(2 * (size_t)ma);   // [order | inverse]
     if (!ident) {
-        TRY(hipMemcpyAsync(b.iperm, ord.data(), sizeof(int) * ma, hipMemcpyHostToDevice, st));
+        for (int j = 0; j < ma; ++j) { perm[j] = ord[j]; perm[ma + ord[j]] = j; }
+        TRY(hipMemcpyAsync(b.iperm, perm.data(), sizeof(int) * 2 * ma, hipMemcpyHostToDevice, st));
         TRY(launch_permute_cols(st, n, ma, Y, ldy, b.T, n, b.iperm));
         TRY(launch_zlacpy(st, n, ma, b.T, n, Y, ldy));
         std::vector<int> d2(ma), l2(ma);
         for (int j = 0; j < ma; ++j) { d2[j] = deg[ord[j]]; l2[j] = lowp[ord[j]]; }
         deg.swap(d2);
         lowp.swap(l2);
-        TRY(hipStreamSynchronize(st));   // ord must outlive the async copy
+        TRY(hipStreamSynchronize(st));   // perm must outlive the async copy
     }
     int nlow = 0;
     while (nlow < ma && lowp[nlow]) ++nlow;
@@ -154,6 +168,7 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
         std::vector<int> dh(deg.begin() + off, deg.end());
         TRYS(filter_f64(h, n, H, ldh, n64, Y + (size_t)off * ldy, ldy, b.T, dh, a, bb, mu1, b.flag, b.gw, flops, matvecs));
     }
+    if (!ident) TRYS(restore_column_order(h, b, n, ma, Y, ldy));
     return CHFSI_SUCCESS;
 }
 
@@ -330,10 +345,11 @@ chfsi_status st_order_columns(chfsi_handle h, SolveState& s, std::vector<int>& d
     dsorted.resize(ma);
     bool ident = true;
     for (int j = 0; j < ma; ++j) { dsorted[j] = d[ord[j]]; ident &= ord[j] == j; }
+    s.permuted = !ident;
     if (!ident) {
-        int* perm = s.hi + 32;   // pinned staging [m]
-        std::memcpy(perm, ord.data(), sizeof(int) * ma);
-        TRY(hipMemcpyAsync(s.b.iperm, perm, sizeof(int) * ma, hipMemcpyHostToDevice, st));
+        int* perm = s.hi + 32;   // pinned staging [2 m]: order, inverse
+        for (int j = 0; j < ma; ++j) { perm[j] = ord[j]; perm[ma + ord[j]] = j; }
+        TRY(hipMemcpyAsync(s.b.iperm, perm, sizeof(int) * 2 * ma, hipMemcpyHostToDevice, st));
         TRY(launch_permute_cols(st, n, ma, s.Ya(), n, s.b.T, n, s.b.iperm));
         TRY(launch_zlacpy(st, n, ma, s.b.T, n, s.Ya(), n));
     }
@@ -348,6 +364,10 @@ chfsi_status st_loop_enqueue(chfsi_handle h, SolveState& s)
     zd* Ya = s.Ya();
     s.loops += 1;
     s.filtered += ma;
+    if (s.permuted) {   // the batched filter ran on degree-sorted columns (st_order_columns)
+        TRYS(restore_column_order(h, b, n, ma, Ya, n));
+        s.permuted = false;
+    }
     mark(s, PH_QR, st, true);
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, st));
     // (the eigensolver's pinned host buffer is free until Rayleigh-Ritz)
@@ -629,20 +649,11 @@ chfsi_status chfsi_filter(chfsi_handle h, int n, const void* Hv, int ldh, void* 
     if (prec == CHFSI_BF16X3 || prec == CHFSI_BF16X6)
         TRY(launch_split_h_bf16(st, n, H, ldh, bf.Hb, n, prec == CHFSI_BF16X3 ? 2 : 3));
     (void)h->ktimer.collect(nullptr);
-    // the filter permutes columns by degree; undo that here so the caller sees its own order
-    std::vector<int> ord(m);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] > d[y]; });
+    // (run_filter sorts the columns by degree for the filter and puts them back afterwards)
     std::vector<int> lowp(m, prec != CHFSI_FP64 ? 1 : 0), dd = d;
     double flops = 0;
     long long mv = 0;
-    TRY(launch_zlacpy(st, n, m, Y, ldy, bf.V, n));
-    TRYS(run_filter(h, bf, n, H, ldh, prec, m, bf.V, n, dd, lowp, a, b, mu1, flops, mv));
-    // bf.V column j now holds input column ord[j]
-    std::vector<int> inv(m);
-    for (int j = 0; j < m; ++j) inv[ord[j]] = j;
-    TRY(hipMemcpyAsync(bf.iperm, inv.data(), sizeof(int) * m, hipMemcpyHostToDevice, st));
-    TRY(launch_permute_cols(st, n, m, bf.V, n, Y, ldy, bf.iperm));
+    TRYS(run_filter(h, bf, n, H, ldh, prec, m, Y, ldy, dd, lowp, a, b, mu1, flops, mv));
     TRY(hipStreamSynchronize(st));
     h->last_kernel_ms = h->ktimer.collect(&h->last_kernel_launches);
     return CHFSI_SUCCESS;

@@ -54,6 +54,7 @@ struct SolveState {
     PhaseTimer* tm = nullptr;          // phase events (single solves)
     double* hd = nullptr;              // pinned host doubles, see the accessors below
     int* hi = nullptr;                 // pinned host ints: info words [0, 16), staging [32, 32 + 2 m)
+    bool permuted = false;             // the active columns are in the filter's degree order
     // algorithm state
     const zd* H = nullptr;
     int ldh = 0;
