@@ -229,8 +229,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the random-start and mixed-precision runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported (this build has no "
-              "multi-GPU path: see DESIGN.md, 'How the path would shard')", file=sys.stderr)
+        print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported: the solver drives "
+              "one GPU and has no multi-GPU path", file=sys.stderr)
         return 2
     import torch
     from paper_1206_3768_amd import chfsi, sequence, synth

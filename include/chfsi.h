@@ -143,8 +143,10 @@ chfsi_status chfsi_solve(chfsi_handle h, int n, const void* A, int lda, const vo
  * no effect).  All unconverged problems advance through Algorithm 1 in lockstep loops: each
  * filter step of all of them is one persistent launch over a work list of output tiles of every
  * problem (tile plan from chfsi_autotune_batched / chfsi_set_batched_plan), the steps of a loop
- * replayed as one captured HIP graph; QR, Rayleigh-Ritz, locking and verification run per problem
- * on four internal streams.  Per problem the results match chfsi_solve with the same parameters
+ * replayed as one captured HIP graph; QR, Rayleigh-Ritz, locking and verification run per problem,
+ * spread over the handle's lanes (streams, chfsi_set_batched_plan; one by default, and the reduction
+ * of a problem completes before more work is enqueued).  Per problem the results match chfsi_solve
+ * with the same parameters
  * up to rounding.  Up to 64 problems share a launch; larger batches run in chunks of 64.
  * stats: [count], nullable; t_total of every entry is the wall time of the whole call, phase
  * times are not recorded (chfsi_batched_info has the filter time).  Returns the first
@@ -204,7 +206,8 @@ chfsi_status chfsi_autotune_filter(chfsi_handle h, int n, int m, int prec, chfsi
 chfsi_status chfsi_set_filter_plan(chfsi_handle h, int n, int m, int prec, const chfsi_tile_plan* plan);
 
 /* Step-level entry points (the pieces chfsi_solve is made of), for parity tests.
- *  chfsi_reduce:  L L^H = S, H = L^{-1} A L^{-H} (Hermitized).  H, L: n x n device outputs
+ *  chfsi_reduce:  L L^H = S, H = L^{-1} A L^{-H} (exactly Hermitian: the upper triangle is the
+ *                 conjugate of the lower one).  H, L: n x n device outputs
  *                 (leading dimension n).  CHFSI_ERR_NOT_HPD on a non-positive pivot.
  *  chfsi_lanczos: k-step Lanczos with full reorthogonalisation from the stream-2 Philox vector;
  *                 theta[k] ascending Ritz values of T_k, zw[k] = |z_1j|^2, *beta_k, *k_used (host).

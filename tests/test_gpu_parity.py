@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on identical seeded inputs.
 
-Tolerances (derived in DESIGN.md, "Parity tolerances"):
+Tolerances (each a rounding-error estimate of the operation with a safety margin):
   FP64 products / filter  : max-abs error <= 1e-12 * max|reference|
   FP32 filter             : <= 2e-4 * max|reference|      (u32 = 6e-8, n up to 512, degree 10)
   BF16x6 filter           : <= 2e-4 * max|reference|      (dropped split terms ~ 2^-24)
