@@ -1,6 +1,7 @@
 // Internal declarations of the gfx950 ChFSI library: complex types, device helpers and the
 // launchers each translation unit exports to the host driver.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,9 +49,22 @@ struct GemmWs {
     // forced tile plan (plan_bm == 0: choose automatically): output tile plan_bm x plan_bn
     // (32 or 64 each), K split plan_ksplit, split mode 1 (partials + reduce kernel) or 2 (fused)
     int plan_bm = 0, plan_bn = 0, plan_ksplit = 0, plan_mode = 1;
-    hipEvent_t ev_main = nullptr;   // recorded right after the main kernel when set
+    // launch timing of a filter step (all three set, or none): ev_start takes the start of the
+    // step's first kernel, ev_main the end of its main kernel and ev_end the end of its last kernel,
+    // each from the dispatch's own timestamps (no marker between the kernels)
+    hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr;
     int* plan_used = nullptr;       // when set, receives bm, bn, ksplit, mode of the launch
 };
+
+// Launches kernel<<<grid, block, 0, s>>>(args...); `start` / `stop` (either may be null) are set
+// to the kernel's own start and end times.
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t start, hipEvent_t stop,
+                         Args... args)
+{
+    if (start || stop) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, start, stop, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 struct FilterStep {
     // out = alpha * (H Yk - shift Yk) + beta * Yprev, columns [0, ncols)

@@ -42,9 +42,9 @@ struct PhaseTimer {
     void collect(double* out);
 };
 
-// hipEvents around every filter step: before the main kernel, right after it (recorded by the
-// launcher through GemmWs::ev_main) and after the step's reduce kernel; summed after the solve's
-// final synchronisation
+// hipEvents of every filter step: the start of its first kernel, the end of its main kernel and the
+// end of its last kernel (set by the launcher from the dispatches' own timestamps, see
+// GemmWs::ev_start); summed after the solve's final synchronisation
 struct KernelTimer {
     struct Rec { int n, ncols, prec; int plan[4]; };
     std::vector<hipEvent_t> pool;
@@ -53,10 +53,10 @@ struct KernelTimer {
     size_t used = 0;
     bool enabled = true;
     ~KernelTimer();
-    // records the start event and returns the event the launcher records after the main kernel;
-    // *plan_slot receives the plan of the launch
-    hipEvent_t begin(hipStream_t s, int n, int ncols, int prec, int** plan_slot);
-    void end(hipStream_t s);
+    // hands the step's three events and the slot of its plan to the launcher through gs (all null
+    // when timing is off); end() after the launch
+    void begin(int n, int ncols, int prec, GemmWs& gs);
+    void end(const GemmWs& gs);
     double collect(int* launches, double* step_ms = nullptr);   // main-kernel ms; resets
 };
 

@@ -216,16 +216,16 @@ Plan make_plan(int M, int N, int K, const GemmWs& gw, int elem_bytes)
 }
 
 template <typename T, int OPA, int OPB, int EPI, int BM, int BN>
-void launch_tile(hipStream_t s, int nt, int mode, const GDims& g, const typename CT<T>::c* A,
-                 const typename CT<T>::c* B, typename CT<T>::c* C, const typename CT<T>::c* Yk,
-                 const typename CT<T>::c* Yp, typename CT<T>::c* P, int* cnt)
+void launch_tile(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int nt, int mode, const GDims& g,
+                 const typename CT<T>::c* A, const typename CT<T>::c* B, typename CT<T>::c* C,
+                 const typename CT<T>::c* Yk, const typename CT<T>::c* Yp, typename CT<T>::c* P, int* cnt)
 {
     if (mode == 0)
-        hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, BM, BN, 0>), dim3(nt), dim3(256), 0, s, g, A, B, C, Yk, Yp, P, cnt);
+        launch_timed(k_zgemm<T, OPA, OPB, EPI, BM, BN, 0>, dim3(nt), dim3(256), s, e0, e1, g, A, B, C, Yk, Yp, P, cnt);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, BM, BN, 1>), dim3(nt), dim3(256), 0, s, g, A, B, C, Yk, Yp, P, cnt);
+        launch_timed(k_zgemm<T, OPA, OPB, EPI, BM, BN, 1>, dim3(nt), dim3(256), s, e0, e1, g, A, B, C, Yk, Yp, P, cnt);
     else
-        hipLaunchKernelGGL((k_zgemm<T, OPA, OPB, EPI, BM, BN, 2>), dim3(nt), dim3(256), 0, s, g, A, B, C, Yk, Yp, P, cnt);
+        launch_timed(k_zgemm<T, OPA, OPB, EPI, BM, BN, 2>, dim3(nt), dim3(256), s, e0, e1, g, A, B, C, Yk, Yp, P, cnt);
 }
 
 template <typename T, int OPA, int OPB, int EPI>
@@ -237,19 +237,30 @@ int run(hipStream_t s, GDims g, const Plan& p, const typename CT<T>::c* A, const
     if (gw.plan_used) {
         gw.plan_used[0] = p.bm; gw.plan_used[1] = p.bn; gw.plan_used[2] = p.ksplit; gw.plan_used[3] = p.mode;
     }
-    if (nt <= 0) return 0;
+    const bool timed = gw.ev_start && gw.ev_main && gw.ev_end;
+    if (nt <= 0) {
+        if (timed) {
+            (void)hipEventRecord(gw.ev_start, s);
+            (void)hipEventRecord(gw.ev_main, s);
+            (void)hipEventRecord(gw.ev_end, s);
+        }
+        return 0;
+    }
     typedef typename CT<T>::c C2;
     C2* P = (C2*)gw.ws;
-    if (p.bm == 64 && p.bn == 64) launch_tile<T, OPA, OPB, EPI, 64, 64>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
-    else if (p.bm == 64) launch_tile<T, OPA, OPB, EPI, 64, 32>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
-    else if (p.bn == 64) launch_tile<T, OPA, OPB, EPI, 32, 64>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
-    else launch_tile<T, OPA, OPB, EPI, 32, 32>(s, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
-    if (gw.ev_main) (void)hipEventRecord(gw.ev_main, s);
+    const hipEvent_t e0 = timed ? gw.ev_start : nullptr, e1 = timed ? gw.ev_main : nullptr;
+    if (p.bm == 64 && p.bn == 64) launch_tile<T, OPA, OPB, EPI, 64, 64>(s, e0, e1, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
+    else if (p.bm == 64) launch_tile<T, OPA, OPB, EPI, 64, 32>(s, e0, e1, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
+    else if (p.bn == 64) launch_tile<T, OPA, OPB, EPI, 32, 64>(s, e0, e1, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
+    else launch_tile<T, OPA, OPB, EPI, 32, 32>(s, e0, e1, nt, p.mode, g, A, B, C, Yk, Yp, P, gw.cnt);
     if (p.mode == 1) {
         const size_t total = (size_t)g.M * g.N;
         int blocks = (int)((total + 255) / 256);
         if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL((k_splitk_reduce<T, EPI>), dim3(blocks), dim3(256), 0, s, g, C, Yk, Yp, P);
+        launch_timed(k_splitk_reduce<T, EPI>, dim3(blocks), dim3(256), s, nullptr, timed ? gw.ev_end : nullptr, g, C,
+                     Yk, Yp, P);
+    } else if (timed) {
+        (void)hipEventRecord(gw.ev_end, s);
     }
     return (int)hipGetLastError();
 }

@@ -306,8 +306,9 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
     if (n <= 0 || ncols <= 0) return 0;
     if (nterms != 2 && nterms != 3) return (int)hipErrorInvalidValue;
     const int np = pad32(n), ncp = (ncols + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_split_y, dim3(grid_for((size_t)np * ncp)), dim3(256), 0, s, n, np, ncols, ncp, Yk, ldyk,
-                       ysplit, nterms);
+    const bool timed = gw.ev_start && gw.ev_main && gw.ev_end;
+    launch_timed(k_split_y, dim3(grid_for((size_t)np * ncp)), dim3(256), s, timed ? gw.ev_start : nullptr, nullptr, n,
+                 np, ncols, ncp, Yk, ldyk, ysplit, nterms);
     BArgs g;
     g.n = n; g.np = np; g.ncols = ncols; g.ncp = ncp; g.nterms = nterms;
     g.Hp = Hplanes; g.Ys = ysplit; g.Yk = Yk; g.ldyk = ldyk; g.Yp = Yprev; g.ldyp = ldyp; g.Yo = Yout; g.ldyo = ldyo;
@@ -327,17 +328,18 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
     g.ksplit = (np + kc - 1) / kc;
     const int nt = g.tiles_m * g.tiles_n * g.ksplit;
     const bool split = g.ksplit > 1;
+    const hipEvent_t e1 = timed ? gw.ev_main : nullptr;
     if (nterms == 2) {
-        if (split) hipLaunchKernelGGL((k_filter_bf16<2, true>), dim3(nt), dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((k_filter_bf16<2, false>), dim3(nt), dim3(256), 0, s, g);
+        if (split) launch_timed(k_filter_bf16<2, true>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        else launch_timed(k_filter_bf16<2, false>, dim3(nt), dim3(256), s, nullptr, e1, g);
     } else {
-        if (split) hipLaunchKernelGGL((k_filter_bf16<3, true>), dim3(nt), dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((k_filter_bf16<3, false>), dim3(nt), dim3(256), 0, s, g);
+        if (split) launch_timed(k_filter_bf16<3, true>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        else launch_timed(k_filter_bf16<3, false>, dim3(nt), dim3(256), s, nullptr, e1, g);
     }
     if (gw.plan_used) {
         gw.plan_used[0] = 64; gw.plan_used[1] = 64; gw.plan_used[2] = g.ksplit; gw.plan_used[3] = split ? 2 : 0;
     }
-    if (gw.ev_main) (void)hipEventRecord(gw.ev_main, s);
+    if (timed) (void)hipEventRecord(gw.ev_end, s);
     return (int)hipGetLastError();
 }
 
@@ -362,10 +364,10 @@ chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int
         const zf* yp = (k == 1) ? yk : yo;
         const int ldp = (k == 1) ? ldk : ldo;
         GemmWs gs = gw;
-        gs.ev_main = h->ktimer.begin(st, n, w, nterms == 2 ? CHFSI_BF16X3 : CHFSI_BF16X6, &gs.plan_used);
+        h->ktimer.begin(n, w, nterms == 2 ? CHFSI_BF16X3 : CHFSI_BF16X6, gs);
         if (launch_filter_step_bf16(st, n, w, Hb, ldh, nterms, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ysplit, gs))
             return CHFSI_ERR_DEVICE;
-        h->ktimer.end(st);
+        h->ktimer.end(gs);
         flops += 8.0 * (double)n * (double)n * (double)w;
         matvecs += w;
     }

@@ -98,28 +98,28 @@ KernelTimer::~KernelTimer()
     for (auto& e : pool) (void)hipEventDestroy(e);
 }
 
-hipEvent_t KernelTimer::begin(hipStream_t s, int n, int ncols, int prec, int** plan_slot)
+void KernelTimer::begin(int n, int ncols, int prec, GemmWs& gs)
 {
-    if (plan_slot) *plan_slot = nullptr;
-    if (!enabled) return nullptr;
+    gs.ev_start = gs.ev_main = gs.ev_end = nullptr;
+    gs.plan_used = nullptr;
+    if (!enabled) return;
     while (pool.size() < used + 3) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { enabled = false; return nullptr; }
+        if (hipEventCreate(&e) != hipSuccess) { enabled = false; return; }
         pool.push_back(e);
     }
     const size_t r = used / 3;
     if (recs.size() <= r) recs.resize(r + 1);
     recs[r] = Rec{n, ncols, prec, {0, 0, 0, 0}};
-    if (plan_slot) *plan_slot = recs[r].plan;
-    (void)hipEventRecord(pool[used], s);
-    return pool[used + 1];
+    gs.plan_used = recs[r].plan;
+    gs.ev_start = pool[used];
+    gs.ev_main = pool[used + 1];
+    gs.ev_end = pool[used + 2];
 }
 
-void KernelTimer::end(hipStream_t s)
+void KernelTimer::end(const GemmWs& gs)
 {
-    if (!enabled || pool.size() < used + 3) return;
-    (void)hipEventRecord(pool[used + 2], s);
-    used += 3;
+    if (gs.ev_start) used += 3;
 }
 
 double KernelTimer::collect(int* launches, double* step_ms)
@@ -512,9 +512,9 @@ chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma,
         GemmWs gs = gw;
         const int pr = sizeof(C2) == 16 ? CHFSI_FP64 : CHFSI_FP32;
         apply_tuned_plan(h, pr, n, w, gs);
-        gs.ev_main = h->ktimer.begin(st, n, w, pr, &gs.plan_used);
+        h->ktimer.begin(n, w, pr, gs);
         TRY(step_fn(st, n, w, Hm, ldh, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], gs));
-        h->ktimer.end(st);
+        h->ktimer.end(gs);
         flops += 8.0 * (double)n * (double)n * (double)w;
         matvecs += w;
     }
