@@ -1,7 +1,8 @@
 // Cholesky factorisation S = L L^H (lower) of the reduction to standard form (Section 3.2), blocked
 // right-looking with 64-column panels:
-//   k_chol_diag   one workgroup factors the 64 x 64 diagonal block in LDS, writes L11 and stores
-//                 L11^{-1} (tri64.h) for this factorisation and the later triangular solves;
+//   k_chol_diag   one workgroup factors the 64 x 64 diagonal block (register resident), writes L11
+//                 and stores L11^{-1} (tri64.h) for this factorisation and the later triangular
+//                 solves;
 //   L21           L21 = A21 L11^{-H}, in place, as an MFMA product with the stored inverse (trsm.hip);
 //   trailing      A22 <- A22 - L21 L21^H with the MFMA complex GEMM of gemm.hip.
 // A non-positive (or non-finite) pivot sets *info to its 1-based column, as LAPACK's potrf does;
@@ -13,6 +14,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "gemm_tile.h"
 #include "tri64.h"
 
 namespace {
@@ -28,103 +30,140 @@ __device__ inline double readlane_d(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-__device__ inline zd zsub_mul_conj(zd acc, zd a, zd b)   // acc - a conj(b)
+// acc - a conj(b) with fused multiply-adds
+__device__ inline zd zfms_conj(zd acc, zd a, zd b)
 {
-    acc.x -= a.x * b.x + a.y * b.y;
-    acc.y -= a.y * b.x - a.x * b.y;
+    acc.x = __builtin_fma(-a.x, b.x, acc.x);
+    acc.x = __builtin_fma(-a.y, b.y, acc.x);
+    acc.y = __builtin_fma(-a.y, b.x, acc.y);
+    acc.y = __builtin_fma(a.x, b.y, acc.y);
     return acc;
 }
 
-// Factors the nb x nb (nb <= 64) diagonal block at A in LDS (one workgroup), writes L11 to A and
-// L11^{-1} (64 x 64, column-major, zero above the diagonal, identity beyond nb) to D.  col0: global
-// index of the block's first column (for the pivot reported in *info).
+// Factors the nb x nb (nb <= 64) diagonal block at A (one workgroup), writes L11 to A and L11^{-1}
+// (64 x 64, column-major, zero above the diagonal, identity beyond nb) to D.  col0: global index of
+// the block's first column (for the pivot reported in *info).
+//
+// Right-looking over 16 panels of 4 columns.  Lane = row: wave w keeps its row's entries of the
+// column blocks q = w, w + 4, w + 8, w + 12 in registers, so that only the panels pass through LDS.
+//   * Panel s is factored by the wave that holds it (pivots and panel rows broadcast with
+//     v_readlane); each pivot is formed from the previous one's reciprocal,
+//     d_{c+1} = a_{c+1,c+1} - |u|^2 / d_c with u the unscaled entry below the previous pivot, so
+//     that the column updates stay off the chain of pivots.
+//   * The holder of block s + 1 applies panel s to that block and factors it at once (look-ahead)
+//     and applies panel s to its other blocks one step later; the others apply panel s to their
+//     later blocks.  Panels live in a ring of four LDS buffers, so one barrier per panel suffices.
+//   * Entries above the diagonal are updated like the others (no branches) and never read.
+// The inverse follows from the factor in LDS (tri64.h) with the pivots' reciprocals.
 __global__ __launch_bounds__(256) void k_chol_diag(int nb, int col0, zd* __restrict__ A, int lda,
                                                    int* __restrict__ info, zd* __restrict__ D)
 {
-    __shared__ zd L[CB * CP];    // diagonal block, factored in place (lower)
-    __shared__ zd X[CB * CP];    // L11^{-1}
-    const int tid = threadIdx.x;
-    // lower triangle (the upper is never read), identity padding beyond nb: all 16 loads of a
-    // thread are issued (clamped into the block) before any is used
-    {
-        zd v[CB * CB / 256];
+    __shared__ zd L[CB * CP];     // the factor, row-major (pitch CP), zero above the diagonal
+    __shared__ zd X[CB * CP];     // L^{-1}
+    __shared__ zd Pn[4][4][CB];   // panel ring: Pn[s & 3][c][row]
+    __shared__ double Rv[CB];     // 1 / L_kk
+    __shared__ int fail_min;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int fail = CB;                // first non-positive pivot met by this wave (wave-uniform)
+    if (tid == 0) fail_min = CB;
+    // lower triangle (the upper is never read), identity padding beyond nb; all 16 loads of a lane
+    // (clamped into the block) are issued before any is used
+    zd r[4][4];
 #pragma unroll
-        for (int p = 0; p < CB * CB / 256; ++p) {
-            const int e = tid + 256 * p, i = e % CB, j = e / CB;
-            v[p] = A[(size_t)min(i, nb - 1) + (size_t)min(j, nb - 1) * lda];
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = 4 * (wave + 4 * t) + c;
+            r[t][c] = A[(size_t)min(lane, nb - 1) + (size_t)min(j, nb - 1) * lda];
         }
 #pragma unroll
-        for (int p = 0; p < CB * CB / 256; ++p) {
-            const int e = tid + 256 * p, i = e % CB, j = e / CB;
-            zd w = make_double2(i == j ? 1.0 : 0.0, 0.0);
-            if (i < nb && j < nb && i >= j) {
-                w.x = v[p].x;
-                w.y = i == j ? 0.0 : v[p].y;
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = 4 * (wave + 4 * t) + c;
+            zd w = make_double2(lane == j ? 1.0 : 0.0, 0.0);
+            if (lane < nb && j < nb && lane >= j) {
+                w.x = r[t][c].x;
+                w.y = lane == j ? 0.0 : r[t][c].y;
             }
-            L[i * CP + j] = w;
+            r[t][c] = w;
         }
-    }
+    auto factor = [&](int s, zd (&b)[4]) {
+        double d = readlane_d(b[0].x, 4 * s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int kc = 4 * s + c;
+            fail = (!(d > 0.0) && kc < nb) ? min(fail, kc) : fail;
+            const double dd = d > 0.0 ? d : 1.0;
+            double un = 0.0, a1 = 0.0;
+            if (c < 3) {
+                const double ux = readlane_d(b[c].x, kc + 1), uy = readlane_d(b[c].y, kc + 1);
+                un = ux * ux + uy * uy;
+                a1 = readlane_d(b[c + 1].x, kc + 1);
+            }
+            const double inv = rsqrt_nr(dd), sd = dd * inv;
+            if (c < 3) d = __builtin_fma(-un, inv * inv, a1);
+            Rv[kc] = inv;   // the same value from every lane
+            const bool diag = lane == kc;
+            b[c].x = diag ? sd : b[c].x * inv;
+            b[c].y = diag ? 0.0 : b[c].y * inv;
+#pragma unroll
+            for (int j = c + 1; j < 4; ++j) {
+                const zd l = make_double2(readlane_d(b[c].x, 4 * s + j), readlane_d(b[c].y, 4 * s + j));
+                b[j] = zfms_conj(b[j], b[c], l);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Pn[s & 3][c][lane] = b[c];
+    };
+    // block q (held in b) -= (this row's entries of panel s) (block q's rows of panel s)^H
+    auto update = [&](int s, zd (&b)[4], int q) {
+        zd p[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) p[c] = Pn[s & 3][c][lane];
+#pragma unroll
+        for (int c2 = 0; c2 < 4; ++c2) {
+            const int j = 4 * q + c2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c2] = zfms_conj(b[c2], p[c], Pn[s & 3][c][j]);
+        }
+    };
+    if (wave == 0) factor(0, r[0]);
     __syncthreads();
-    // right-looking Cholesky, four columns at a time: wave 0 factors the 64 x 4 column panel in
-    // registers (lane = row; the diagonal and the panel rows are broadcast with v_readlane), then
-    // all threads apply the rank-4 update to the trailing lower triangle (lane = row i, the waves
-    // take every fourth column j; the entries of row j are broadcast reads)
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int k = 0; k < CB; k += 4) {
-        if (tid < 64) {
-            zd v[4];
+#pragma clang loop unroll(full)
+    for (int s = 0; s < 15; ++s) {
+        const int nxt = s + 1;
+        if (wave == (nxt & 3)) {
+            update(s, r[nxt >> 2], nxt);
+            factor(nxt, r[nxt >> 2]);
+        } else {
+            if (s >= 1 && wave == (s & 3)) {   // deferred: panel s - 1 on this wave's blocks after s
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = L[lane * CP + k + c];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int kc = k + c;
-                const double d = readlane_d(v[c].x, kc);
-                if (lane == 0 && !(d > 0.0) && kc < nb && info) atomicCAS(info, 0, col0 + kc + 1);
-                const double inv = rsqrt_nr(d > 0.0 ? d : 1.0), sd = (d > 0.0 ? d : 1.0) * inv;
-                if (lane > kc) v[c] = make_double2(v[c].x * inv, v[c].y * inv);
-                else if (lane == kc) v[c] = make_double2(sd, 0.0);
-#pragma unroll
-                for (int j = c + 1; j < 4; ++j) {   // columns k + j of the panel, rows >= k + j
-                    const zd l = make_double2(readlane_d(v[c].x, k + j), readlane_d(v[c].y, k + j));
-                    if (lane >= k + j) v[j] = zsub_mul_conj(v[j], v[c], l);
-                }
+                for (int t = 0; t < 4; ++t)
+                    if (wave + 4 * t > s) update(s - 1, r[t], wave + 4 * t);
             }
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (lane >= k + c) L[lane * CP + k + c] = v[c];
-        }
-        __syncthreads();
-        const int r0t = k + 4;
-        if (lane >= r0t) {
-            zd a[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) a[c] = L[lane * CP + k + c];
-            // columns j = r0t + wave + 4 t, j <= lane, four at a time so that their LDS reads overlap
-            for (int j0 = r0t + wave; j0 <= lane; j0 += 16) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = j0 + 4 * u;
-                    if (j <= lane) {
-                        zd acc = L[lane * CP + j];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc = zsub_mul_conj(acc, a[c], L[j * CP + k + c]);
-                        L[lane * CP + j] = acc;
-                    }
-                }
-            }
+            for (int t = 0; t < 4; ++t)
+                if (wave + 4 * t > nxt) update(s, r[t], wave + 4 * t);
         }
         __syncthreads();
     }
-    #pragma unroll
+    if (fail < CB && lane == 0) atomicMin(&fail_min, fail);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = 4 * (wave + 4 * t) + c;
+            L[lane * CP + j] = lane >= j ? r[t][c] : make_double2(0.0, 0.0);
+            if (lane < nb && j < nb && lane >= j) A[(size_t)lane + (size_t)j * lda] = r[t][c];
+        }
+    __syncthreads();
+    if (tid == 0 && fail_min < CB && info) atomicCAS(info, 0, col0 + fail_min + 1);
+    tri64::lower_inverse(L, Rv, X);
+#pragma unroll
     for (int e = tid; e < CB * CB; e += 256) {
         const int i = e % CB, j = e / CB;
-        if (i < nb && j < nb && i >= j) A[(size_t)i + (size_t)j * lda] = L[i * CP + j];
-    }
-    tri64::lower_inverse(L, X);
-    #pragma unroll
-    for (int e = tid; e < CB * CB; e += 256) {
-        const int i = e % CB, j = e / CB;
-        D[i + (size_t)j * CB] = X[i * CP + j];
+        D[i + (size_t)j * CB] = i >= j ? X[i * CP + j] : make_double2(0.0, 0.0);
     }
 }
 
