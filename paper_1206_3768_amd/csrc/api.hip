@@ -27,7 +27,7 @@ namespace {
         if (s_ != CHFSI_SUCCESS) return s_;    \
     } while (0)
 
-void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
+void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec, int filter_ksplit)
 {
     const size_t nn = (size_t)n * n, nm = (size_t)n * m, mm = (size_t)m * m;
     if (gen) {
@@ -66,9 +66,11 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
     b.feat = ar.take<float>((size_t)m * MLP_NF + 16);
     b.dpred = ar.take<float>(m + 16);
     b.eigw = ar.get(eig_work_bytes(m));
-    // split-K partials: the largest of the filter (n x m, K = n) and the Gram products (m x m, K = n)
+    // split-K partials: the largest of the filter (n x m, K = n; automatic or tuned plan) and the
+    // Gram products (m x m, K = n)
     size_t ws = std::max(zgemm_ws_bytes(n, m, n, 16), zgemm_ws_bytes(m, m, n, 16));
     ws = std::max(ws, zgemm_ws_bytes(n, m, m, 16));
+    ws = std::max(ws, (size_t)filter_ksplit * n * m * 16);
     b.gw.bytes = ws;
     b.gw.ws = ar.get(ws);
 }
@@ -180,8 +182,14 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
 
 chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
 {
+    // the largest K split of a tuned filter plan that a step of this order may take
+    int fks = 1;
+    for (const TuneEntry& e : h->plans) {
+        const double r = e.n > n ? (double)e.n / n : (double)n / e.n;
+        if (r <= 1.5) fks = std::max(fks, e.ksplit);
+    }
     ar.begin(true);
-    layout(ar, b, n, m, k, gen, prec);
+    layout(ar, b, n, m, k, gen, prec, fks);
     const size_t need = ar.off;
     if (need > ar.cap) {
         (void)hipStreamSynchronize(h->stream);
@@ -190,7 +198,7 @@ chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m,
     }
     ar.begin(false);
     b = SolveBufs();
-    layout(ar, b, n, m, k, gen, prec);
+    layout(ar, b, n, m, k, gen, prec, fks);
     b.gw.cnt = h->tile_cnt;
     b.gw.ncnt = h->tile_cnt_len;
     return ar.failed ? CHFSI_ERR_ALLOC : CHFSI_SUCCESS;

@@ -183,14 +183,15 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GDims g, typename CT<T>::
 
 struct Plan { int bm, bn, ksplit, kchunk, tiles_m, tiles_n, mode; };
 
-// Tile/split choice.  A plan forced by the caller (autotuned) wins if the workspace allows it;
-// otherwise 64 x 64 (64 x 32 for narrow blocks) tiles, and K slices of at least 256 until there
-// are enough workgroups for two per CU on 256 CUs, with the partials summed by a second kernel.
+// Tile/split choice.  A plan forced by the caller (autotuned) wins if the workspace allows it.
+// Otherwise the largest tile (64 x 64, 64 x 32 / 32 x 64, 32 x 32; no 64-wide side on a dimension
+// of 32 or less) that still gives one workgroup per CU (256 CUs), else 32 x 32; then K slices of at least 64 until there are two workgroups per
+// CU, the partials summed by a second kernel.  Small products (the Gram matrices and rotations of
+// the dense steps) would otherwise run on a fraction of the CUs.
 Plan make_plan(int M, int N, int K, const GemmWs& gw, int elem_bytes)
 {
+    constexpr long CUS = 256;
     Plan p;
-    p.bm = 64;
-    p.bn = N <= 32 ? 32 : 64;
     int ks = 1;
     p.mode = 1;
     const bool forced = gw.plan_bm > 0;
@@ -199,12 +200,20 @@ Plan make_plan(int M, int N, int K, const GemmWs& gw, int elem_bytes)
         p.bn = gw.plan_bn;
         ks = gw.plan_ksplit > 0 ? gw.plan_ksplit : 1;
         p.mode = gw.plan_mode;
+    } else {
+        auto count = [&](int bm, int bn) { return (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
+        const bool wide_m = M > 32, wide_n = N > 32;   // a 64-wide side would be half empty otherwise
+        p.bm = 32;
+        p.bn = 32;
+        if (wide_m && wide_n && count(64, 64) >= CUS) { p.bm = 64; p.bn = 64; }
+        else if (wide_m && (M >= N || !wide_n) && count(64, 32) >= CUS) { p.bm = 64; p.bn = 32; }
+        else if (wide_n && (N > M || !wide_m) && count(32, 64) >= CUS) { p.bm = 32; p.bn = 64; }
     }
     p.tiles_m = (M + p.bm - 1) / p.bm;
     p.tiles_n = (N + p.bn - 1) / p.bn;
     const long tiles = (long)p.tiles_m * p.tiles_n;
     if (!forced)
-        while (tiles * ks < 512 && (long)K / (2 * ks) >= 256) ks *= 2;
+        while (tiles * ks < 2 * CUS && (long)K / (2 * ks) >= 64) ks *= 2;
     if (!gw.ws || (p.mode == 2 && (!gw.cnt || tiles > gw.ncnt))) ks = 1;
     while (ks > 1 && (size_t)ks * M * N * (size_t)elem_bytes > gw.bytes) ks /= 2;
     int kc = (K + ks - 1) / ks;
