@@ -111,22 +111,65 @@ __global__ void k_philox_block(uint64_t seed, uint64_t stream, int n, int m, zd*
     }
 }
 
-// y[j] = sum_i conj(V[i, j]) x[i], one wave per column (4 columns per 256-thread block)
+// y[j] = sum_i conj(V[i, j]) x[i], one wave per column (4 columns per 256-thread block); four
+// independent partial sums per lane keep four loads in flight
 __global__ __launch_bounds__(256) void k_coldots(int n, int ncols, const zd* V, int ldv, const zd* x, zd* y)
 {
     const int lane = threadIdx.x & 63;
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= ncols) return;
     const zd* v = V + (size_t)j * ldv;
-    double sr = 0, si = 0;
-    for (int i = lane; i < n; i += 64) {
-        const zd a = v[i], b = x[i];
-        sr += a.x * b.x + a.y * b.y;
-        si += a.x * b.y - a.y * b.x;
+    double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+    int i = lane;
+    for (; i + 192 < n; i += 256) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const zd a = v[i + 64 * u], b = x[i + 64 * u];
+            sr[u] += a.x * b.x + a.y * b.y;
+            si[u] += a.x * b.y - a.y * b.x;
+        }
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) y[j] = make_double2(sr, si);
+    for (; i < n; i += 64) {
+        const zd a = v[i], b = x[i];
+        sr[0] += a.x * b.x + a.y * b.y;
+        si[0] += a.x * b.y - a.y * b.x;
+    }
+    double tr = (sr[0] + sr[1]) + (sr[2] + sr[3]), ti = (si[0] + si[1]) + (si[2] + si[3]);
+    tr = wave_sum(tr);
+    ti = wave_sum(ti);
+    if (lane == 0) y[j] = make_double2(tr, ti);
+}
+
+// the same for a few columns: one 256-thread block per column
+__global__ __launch_bounds__(256) void k_coldots_block(int n, const zd* V, int ldv, const zd* x, zd* y)
+{
+    __shared__ double sm[8];
+    const int j = blockIdx.x;
+    const zd* v = V + (size_t)j * ldv;
+    double sr[2] = {0, 0}, si[2] = {0, 0};
+    int i = threadIdx.x;
+    for (; i + 256 < n; i += 512) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const zd a = v[i + 256 * u], b = x[i + 256 * u];
+            sr[u] += a.x * b.x + a.y * b.y;
+            si[u] += a.x * b.y - a.y * b.x;
+        }
+    }
+    for (; i < n; i += 256) {
+        const zd a = v[i], b = x[i];
+        sr[0] += a.x * b.x + a.y * b.y;
+        si[0] += a.x * b.y - a.y * b.x;
+    }
+    double tr = wave_sum(sr[0] + sr[1]), ti = wave_sum(si[0] + si[1]);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sm[w] = tr;
+        sm[4 + w] = ti;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        y[j] = make_double2((sm[0] + sm[1]) + (sm[2] + sm[3]), (sm[4] + sm[5]) + (sm[6] + sm[7]));
 }
 
 // x[i] += alpha sum_j V[i, j] c[j]
@@ -395,7 +438,10 @@ int launch_philox_block(hipStream_t s, unsigned long long seed, unsigned long lo
 int launch_coldots(hipStream_t s, int n, int ncols, const zd* V, int ldv, const zd* x, zd* y)
 {
     if (ncols <= 0) return 0;
-    hipLaunchKernelGGL(k_coldots, dim3((ncols + 3) / 4), dim3(256), 0, s, n, ncols, V, ldv, x, y);
+    if (ncols <= 256)   // too few columns to fill the device one wave each
+        hipLaunchKernelGGL(k_coldots_block, dim3(ncols), dim3(256), 0, s, n, V, ldv, x, y);
+    else
+        hipLaunchKernelGGL(k_coldots, dim3((ncols + 3) / 4), dim3(256), 0, s, n, ncols, V, ldv, x, y);
     return (int)hipGetLastError();
 }
 
