@@ -437,7 +437,11 @@ chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int
                                 const GemmWs& gw, PhaseTimer* tm, double eig_stop)
 {
     hipStream_t st = h->stream;
-    TRY(launch_zgemm(st, OP_N, OP_N, n, ma, n, 1.0, H, ldh, Y, ldy, 0.0, HY, n, gw));
+    {   // H Y has the shape of a filter step: the filter's tuned plan
+        GemmWs g2 = gw;
+        apply_tuned_plan(h, CHFSI_FP64, n, ma, g2);
+        TRY(launch_zgemm(st, OP_N, OP_N, n, ma, n, 1.0, H, ldh, Y, ldy, 0.0, HY, n, g2));
+    }
     TRY(launch_zgemm(st, OP_C, OP_N, ma, ma, n, 1.0, Y, ldy, HY, n, 0.0, G, ma, gw));
     int sweeps = 0;
     const int rc = eig_jacobi(st, ma, G, ma, theta_dev, eig_work, eig_host, &sweeps, eig_stop);
