@@ -380,7 +380,7 @@ chfsi_status st_loop_enqueue(chfsi_handle h, SolveState& s)
     TRY(hipMemsetAsync(b.info, 0, sizeof(int) * 8, st));
     // (the eigensolver's pinned host buffer is free until Rayleigh-Ritz)
     TRYS(step_orthonormalize(h, n, ma, Ya, n, s.nlocked, b.V, n, b.G, b.Cm, b.dinvG, b.dsc, b.info, b.gw,
-                             s.h_eig()));
+                             s.h_eig(), b.T));
     mark(s, PH_QR, st, false);
     mark(s, PH_RR, st, true);
     // the Rayleigh quotient is diagonalised to a tenth of the locking threshold: a Ritz vector

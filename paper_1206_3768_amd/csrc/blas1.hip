@@ -229,6 +229,34 @@ __global__ __launch_bounds__(256) void k_colabssum(int n, const zd* A, int lda, 
     if (threadIdx.x == 0) r[blockIdx.x] = s;
 }
 
+// r[j] = sum_i |A_ij - delta_ij|, one block per column
+__global__ __launch_bounds__(256) void k_colabssum_off_identity(int n, const zd* A, int lda, double* r)
+{
+    __shared__ double sm[4];
+    const int j = blockIdx.x;
+    const zd* a = A + (size_t)j * lda;
+    double s = 0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        zd v = a[i];
+        if (i == j) v.x -= 1.0;
+        s += sqrt(zabs2(v));
+    }
+    s = block_sum256(s, sm);
+    if (threadIdx.x == 0) r[j] = s;
+}
+
+// G (m x m) <- F: the strict upper triangle of G, (G_jj - 1) / 2 on the diagonal, zero below
+__global__ void k_first_order_factor(int m, zd* G, int ldg)
+{
+    const size_t total = (size_t)m * m;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        zd* g = G + (size_t)i + (size_t)j * ldg;
+        if (i > j) *g = make_double2(0.0, 0.0);
+        else if (i == j) *g = make_double2(0.5 * (g->x - 1.0), 0.0);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_max_reduce(int n, const double* v, double* out)
 {
     __shared__ double sm[256];
@@ -487,6 +515,20 @@ int launch_max_rowsum_abs(hipStream_t s, int n, const zd* A, int lda, double* ou
 {
     hipLaunchKernelGGL(k_colabssum, dim3(n), dim3(256), 0, s, n, A, lda, out + 1);
     hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, n, out + 1, out);
+    return (int)hipGetLastError();
+}
+
+int launch_max_rowsum_off_identity(hipStream_t s, int n, const zd* A, int lda, double* out)
+{
+    hipLaunchKernelGGL(k_colabssum_off_identity, dim3(n), dim3(256), 0, s, n, A, lda, out + 1);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, n, out + 1, out);
+    return (int)hipGetLastError();
+}
+
+int launch_first_order_factor(hipStream_t s, int m, zd* G, int ldg)
+{
+    if (m <= 0) return 0;
+    hipLaunchKernelGGL(k_first_order_factor, dim3(grid_for((size_t)m * m)), dim3(256), 0, s, m, G, ldg);
     return (int)hipGetLastError();
 }
 

@@ -111,6 +111,10 @@ int launch_colnorms(hipStream_t s, int n, int m, const zd* Y, int ldy, double* r
 int launch_scale_cols_inv(hipStream_t s, int n, int m, zd* Y, int ldy, const double* nrm);   // Y[:, j] /= nrm[j]
 int launch_max_colnorm(hipStream_t s, int n, const zd* A, int lda, double* out);            // max_j ||A[:, j]||
 int launch_max_rowsum_abs(hipStream_t s, int n, const zd* A, int lda, double* out);         // ||A||_inf
+// out[0] = max_i sum_j |A_ij - delta_ij| (A Hermitian n x n; out: n + 1 doubles)
+int launch_max_rowsum_off_identity(hipStream_t s, int n, const zd* A, int lda, double* out);
+// G <- F = strict upper triangle of G + diag((G_jj - 1) / 2): the first-order factor of G = I + E
+int launch_first_order_factor(hipStream_t s, int m, zd* G, int ldg);
 int launch_add_diag(hipStream_t s, int m, zd* G, int ldg, const double* shift_dev, double factor);
 int launch_fro2(hipStream_t s, int n, int m, const zd* Y, int ldy, double* out);            // ||Y||_F^2
 // Lanczos helpers

@@ -124,7 +124,7 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
                           double& beta_k, int& k_used);
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
                                  zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw,
-                                 double* host_tmp = nullptr);
+                                 double* host_tmp = nullptr, zd* T = nullptr);
 chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* HY, zd* T,
                                 zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
                                 const GemmWs& gw, PhaseTimer* tm, double eig_stop = 0.0);

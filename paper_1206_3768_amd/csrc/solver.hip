@@ -395,10 +395,11 @@ chfsi_status step_lanczos(chfsi_handle h, int n, const zd* H, int ldh, int k, un
 // With host_tmp (host memory, one double) the first Gram matrix decides: when its largest
 // off-diagonal row sum is below 1/2, Gershgorin bounds kappa(Y) by sqrt(3) and plain Cholesky QR
 // twice (no shift) is already accurate to rounding, so the shifted pass is left out (one host
-// synchronisation instead of one Cholesky QR pass).
+// synchronisation instead of one Cholesky QR pass).  With T (device, n x ma scratch) as well, the
+// last pass is a first-order correction when its Gram matrix is the identity to 1e-9 (below).
 chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, int nl, const zd* YL, int ldyl,
                                  zd* G, zd* Cm, zd* dinv, double* dsc, int* info_dev, const GemmWs& gw,
-                                 double* host_tmp)
+                                 double* host_tmp, zd* T)
 {
     hipStream_t st = h->stream;
     if (ma <= 0) return CHFSI_SUCCESS;
@@ -421,6 +422,23 @@ chfsi_status step_orthonormalize(chfsi_handle h, int n, int ma, zd* Y, int ldy, 
             shifted = !(host_tmp[0] - 1.0 < 0.5);
         }
         if (pass == 0 && shifted) TRY(launch_add_diag_const(st, ma, G, ma, shift));
+        // The last pass starts from a block orthonormal to working accuracy: G = I + E with E
+        // of the order of the previous pass's rounding.  Then R = I + F + O(|E|^2), F the strict
+        // upper triangle of E plus half its diagonal, and Y <- Y (I - F) is orthonormal to
+        // O(|E|^2): one product instead of a factorisation and a triangular solve, taken when
+        // max_i sum_j |E_ij| <= 1e-9 (checked on the host).
+        const bool last = pass == (shifted ? 2 : 1);
+        if (last && pass > 0 && T && host_tmp) {
+            TRY(launch_max_rowsum_off_identity(st, ma, G, ma, dsc));
+            TRY(hipMemcpyAsync(host_tmp, dsc, sizeof(double), hipMemcpyDeviceToHost, st));
+            TRY(hipStreamSynchronize(st));
+            if (host_tmp[0] <= 1e-9) {
+                TRY(launch_first_order_factor(st, ma, G, ma));
+                TRY(launch_zlacpy(st, n, ma, Y, ldy, T, n));
+                TRY(launch_zgemm(st, OP_N, OP_N, n, ma, ma, -1.0, T, n, G, ma, 1.0, Y, ldy, gw));
+                continue;
+            }
+        }
         // G = L L^H = R^H R with R = L^H; Y <- Y R^{-1} = Y L^{-H}
         TRY(chol_lower(st, ma, G, ma, info_dev + pass, dinv, gw));
         TRY(trsm_right_lower_h(st, n, ma, G, ma, dinv, Y, ldy, gw));
