@@ -104,7 +104,7 @@ def bench_kpoints(h, count: int = 32) -> dict:
             p["X"].copy_(x)
         torch.cuda.synchronize()
 
-    seq_ms, seq_lam, seq_loops, seq_flops, seq_filter_ms = 0.0, [], [], 0.0, 0.0
+    seq_ms, seq_lam, seq_loops, seq_flops, seq_filter_ms, seq_phase_ms = 0.0, [], [], 0.0, 0.0, 0.0
     for p in probs:   # warm-up of the sequential path on the first problem
         reset()
         h.solve(p["A"], p["S"], p["X"], True, chfsi.default_params(nev=p["nev"], nex=p["nex"], deg=12, tol=1e-10))
@@ -122,10 +122,14 @@ def bench_kpoints(h, count: int = 32) -> dict:
         seq_loops.append(r.stats["loops"])
         seq_flops += r.stats["filter_flops"]
         seq_filter_ms += r.stats["t_filter_kernels"]
+        seq_phase_ms += r.stats["t_filter"]
     reset()
     plan, plan_ms = h.autotune_batched(probs)
     out = {"count": count, "n_range": [min(sizes), max(sizes)], "sequential_ms": round(seq_ms, 1),
            "sequential_filter_tflops": round(seq_flops / seq_filter_ms / 1e9, 2),
+           # the whole filter phase (main kernels, split-K reductions, copies), as the batched
+           # filter_tflops below is measured
+           "sequential_filter_phase_tflops": round(seq_flops / seq_phase_ms / 1e9, 2),
            "autotuned_tile": list(plan), "autotune_step_ms": round(plan_ms, 3)}
     prm = chfsi.default_params(nev=1, nex=0, deg=12, tol=1e-10)
     for use_graph in (True, False):
