@@ -85,7 +85,8 @@ def bench_kpoints(h, count: int = 32) -> dict:
     """Batched SCF cycle: `count` k-point problems (n uniform in [1500, 6000], nev = ceil(0.06 n),
     nex = ceil(0.2 nev), warm start from the unperturbed eigenvectors, perturbation 1e-3), solved
     one after another with chfsi_solve and as one batch with chfsi_solve_batched (persistent
-    filter launch with the autotuned tile, graph replay and without it)."""
+    filter launch with the autotuned tile, graph replay and without it, the dense steps of the
+    problems spread over three streams with a host thread each)."""
     import torch
     from paper_1206_3768_amd import chfsi, synth
     t0 = time.perf_counter()
@@ -132,8 +133,10 @@ def bench_kpoints(h, count: int = 32) -> dict:
            "sequential_filter_phase_tflops": round(seq_flops / seq_phase_ms / 1e9, 2),
            "autotuned_tile": list(plan), "autotune_step_ms": round(plan_ms, 3)}
     prm = chfsi.default_params(nev=1, nex=0, deg=12, tol=1e-10)
+    lanes = 3   # streams (host threads) for the per-problem dense steps
+    out["lanes"] = lanes
     for use_graph in (True, False):
-        h.set_batched_plan(*plan, use_graph=use_graph)
+        h.set_batched_plan(*plan, use_graph=use_graph, lanes=lanes)
         best = None
         for _ in range(2):
             reset()

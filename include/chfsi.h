@@ -144,10 +144,10 @@ chfsi_status chfsi_solve(chfsi_handle h, int n, const void* A, int lda, const vo
  * filter step of all of them is one persistent launch over a work list of output tiles of every
  * problem (tile plan from chfsi_autotune_batched / chfsi_set_batched_plan), the steps of a loop
  * replayed as one captured HIP graph; QR, Rayleigh-Ritz, locking and verification run per problem,
- * spread over the handle's lanes (streams, chfsi_set_batched_plan; one by default, and the reduction
- * of a problem completes before more work is enqueued).  Per problem the results match chfsi_solve
- * with the same parameters
- * up to rounding.  Up to 64 problems share a launch; larger batches run in chunks of 64.
+ * spread over the handle's lanes (streams, chfsi_set_batched_plan; three by default), one host
+ * thread per lane during those steps, since they wait on the host; the reduction of a problem
+ * completes before more work is enqueued.  The call is not reentrant on one handle.  Per problem
+ * the results match chfsi_solve with the same parameters up to rounding.  Up to 64 problems share a launch; larger batches run in chunks of 64.
  * stats: [count], nullable; t_total of every entry is the wall time of the whole call, phase
  * times are not recorded (chfsi_batched_info has the filter time).  Returns the first
  * non-success status of any problem; the others are still solved. */
@@ -157,8 +157,9 @@ chfsi_status chfsi_solve_batched(chfsi_handle h, int count, const chfsi_problem*
 /* Tile plan of the persistent multi-problem filter kernel of chfsi_solve_batched (bm, bn in
  * {32, 64}; ksplit and fused are ignored; plan NULL keeps the current one), whether each loop's
  * filter steps replay a captured HIP graph (use_graph != 0, the default) or are launched one by
- * one, and over how many streams (lanes, 1 .. 8; 0 keeps the current value, default 1) the
- * per-problem dense steps are spread. */
+ * one, and over how many streams (lanes, 1 .. 8; 0 keeps the current value, default 3) the
+ * per-problem dense steps are spread (with more than one, each lane's dense steps run on a host
+ * thread of their own). */
 chfsi_status chfsi_set_batched_plan(chfsi_handle h, const chfsi_tile_plan* plan, int use_graph, int lanes);
 
 /* Project autotuner of the persistent multi-problem filter kernel: times one filter step over all

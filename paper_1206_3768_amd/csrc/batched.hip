@@ -4,14 +4,18 @@
 // work list of output tiles of every problem; the steps of a loop are captured once in a HIP graph
 // and replayed, their work lists read from a device table that is refreshed before each replay.
 // The small dense steps (QR, Rayleigh-Ritz, locking, verification) stay per problem, spread over
-// several streams so that those of different problems overlap on the device.
+// several streams ("lanes"), each driven by a host thread of its own: those steps wait on the host
+// (eigensolver sweeps, QR pass decisions, the lock decision), so only separate threads let the
+// latency-bound kernels of different problems overlap on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "chfsi.h"
@@ -24,7 +28,7 @@ namespace {
 
 constexpr int BATCH_MAXP = 64;   // problems per persistent launch (larger batches are chunked)
 constexpr int NUM_XCD = 8;       // gfx950: workgroup w runs on XCD w % 8
-constexpr int MAX_LANES = 8;     // streams for the per-problem dense steps (default 1)
+constexpr int MAX_LANES = 8;     // streams for the per-problem dense steps (default 3)
 
 // One problem of a filter step: Yo = alpha (H Yk - shift Yk) + beta Yp on columns [0, w).
 struct BatchProb {
@@ -151,6 +155,24 @@ chfsi_status ensure_lanes(chfsi_handle h)
         Lane l;
         if (hipStreamCreateWithFlags(&l.st, hipStreamNonBlocking) != hipSuccess) return CHFSI_ERR_DEVICE;
         if (hipEventCreateWithFlags(&l.ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(l.st);
+            return CHFSI_ERR_DEVICE;
+        }
+        l.sub = new (std::nothrow) chfsi_handle_s();
+        bool ok = l.sub != nullptr;
+        if (ok) {
+            l.sub->device = h->device;
+            l.sub->stream = l.st;
+            l.sub->tile_cnt_len = 1 << 16;
+            ok = hipMalloc((void**)&l.sub->tile_cnt, sizeof(int) * l.sub->tile_cnt_len) == hipSuccess;
+            if (!ok) l.sub->tile_cnt = nullptr;
+            ok = ok && hipMemsetAsync(l.sub->tile_cnt, 0, sizeof(int) * l.sub->tile_cnt_len, l.st) == hipSuccess &&
+                 hipStreamSynchronize(l.st) == hipSuccess;
+        }
+        if (!ok) {
+            if (l.sub && l.sub->tile_cnt) (void)hipFree(l.sub->tile_cnt);
+            delete l.sub;
+            (void)hipEventDestroy(l.ev);
             (void)hipStreamDestroy(l.st);
             return CHFSI_ERR_DEVICE;
         }
@@ -319,6 +341,55 @@ chfsi_status fail(Slot& z, chfsi_status rc)
     return rc;
 }
 
+// The loop's dense steps (QR, Rayleigh-Ritz, lock decision, verification) of the problems in `act`,
+// one host thread per lane, each through its lane's handle; every problem stays on its lane.
+chfsi_status run_lanes_threaded(chfsi_handle h, std::vector<Slot>& sl, const std::vector<int>& act,
+                                std::vector<chfsi_status>& rcs)
+{
+    const int nl = std::min(h->batch_lanes, (int)h->lanes.size());
+    for (int l = 0; l < nl; ++l) {
+        chfsi_handle sub = h->lanes[l].sub;
+        sub->plans = h->plans;
+        sub->model = h->model;
+        sub->has_model = h->has_model;
+    }
+    auto work = [&](int l) {
+        chfsi_handle sub = h->lanes[l].sub;
+        if (hipSetDevice(h->device) != hipSuccess) {
+            for (int i : act)
+                if (sl[i].lane == l) rcs[i] = fail(sl[i], CHFSI_ERR_DEVICE);
+            return;
+        }
+        for (int i : act) {
+            Slot& z = sl[i];
+            if (z.lane != l) continue;
+            chfsi_status rc = st_loop_enqueue(sub, z.s);
+            if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
+            if (z.s.done) continue;
+            rc = st_loop_complete(sub, z.s);
+            if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(sub, z.s);
+            if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
+            if (z.s.done || !z.s.want_final) continue;
+            rc = st_final_complete(sub, z.s);
+            if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+        }
+    };
+    std::vector<std::thread> th;
+    int started = 0;
+    try {
+        for (int l = 1; l < nl; ++l) {
+            th.emplace_back(work, l);
+            ++started;
+        }
+    } catch (...) {
+        // fewer threads than lanes: the calling thread takes the lanes left over
+    }
+    work(0);
+    for (int l = started + 1; l < nl; ++l) work(l);
+    for (auto& t : th) t.join();
+    return CHFSI_SUCCESS;
+}
+
 chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, const chfsi_params& base,
                          chfsi_stats* stats, int first_index)
 {
@@ -342,6 +413,10 @@ chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, 
         chfsi_status rc = st_define(z.s, q.n, (const zd*)q.A, q.lda, (const zd*)q.S, q.lds, (zd*)q.X, q.ldx,
                                     q.x_is_guess, q.lambda, q.resid, pk);
         if (rc == CHFSI_SUCCESS) rc = st_setup(h, z.s, h->barena[first_index + i], h->bpin[first_index + i]);
+        if (rc == CHFSI_SUCCESS && h->batch_lanes > 1) {   // split-K counters of the problem's lane
+            z.s.b.gw.cnt = h->lanes[z.lane].sub->tile_cnt;
+            z.s.b.gw.ncnt = h->lanes[z.lane].sub->tile_cnt_len;
+        }
         if (rc == CHFSI_SUCCESS) rc = st_init_enqueue(h, z.s);
         if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
     }
@@ -372,25 +447,32 @@ chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, 
         TRY(hipEventRecord(h->bev[2], h->stream));
         for (auto& l : h->lanes) TRY(hipStreamWaitEvent(l.st, h->bev[2], 0));
         // QR and Rayleigh-Ritz of every problem, then the host decisions
-        for (int i : act) {
-            bind.use(sl[i].lane);
-            const chfsi_status rc = st_loop_enqueue(h, sl[i].s);
-            if (rc != CHFSI_SUCCESS) rcs[i] = fail(sl[i], rc);
-        }
-        for (int i : act) {
-            Slot& z = sl[i];
-            if (z.s.done) continue;
-            bind.use(z.lane);
-            chfsi_status rc = st_loop_complete(h, z.s);
-            if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(h, z.s);
-            if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
-        }
-        for (int i : act) {
-            Slot& z = sl[i];
-            if (z.s.done || !z.s.want_final) continue;
-            bind.use(z.lane);
-            const chfsi_status rc = st_final_complete(h, z.s);
-            if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+        if (h->batch_lanes > 1) {
+            // one host thread per lane: the dense steps wait on the host (eigensolver sweeps,
+            // the pass decisions of QR, the lock decision), so only separate threads let those of
+            // different problems overlap on the device
+            TRYS(run_lanes_threaded(h, sl, act, rcs));
+        } else {
+            for (int i : act) {
+                bind.use(sl[i].lane);
+                const chfsi_status rc = st_loop_enqueue(h, sl[i].s);
+                if (rc != CHFSI_SUCCESS) rcs[i] = fail(sl[i], rc);
+            }
+            for (int i : act) {
+                Slot& z = sl[i];
+                if (z.s.done) continue;
+                bind.use(z.lane);
+                chfsi_status rc = st_loop_complete(h, z.s);
+                if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(h, z.s);
+                if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+            }
+            for (int i : act) {
+                Slot& z = sl[i];
+                if (z.s.done || !z.s.want_final) continue;
+                bind.use(z.lane);
+                const chfsi_status rc = st_final_complete(h, z.s);
+                if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+            }
         }
         float ms = 0;
         if (hipEventElapsedTime(&ms, h->bev[0], h->bev[1]) == hipSuccess) h->batch_filter_ms += ms;

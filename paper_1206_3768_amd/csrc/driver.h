@@ -67,6 +67,9 @@ struct TuneEntry { int prec, n, m; int bm, bn, ksplit, mode; };
 struct Lane {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
+    // handle through which one host thread runs the dense steps of the lane's problems: the lane's
+    // stream, its own split-K counters, read-only copies of the tuned plans and the degree model
+    chfsi_handle sub = nullptr;
 };
 
 // A captured filter graph of the batched solver: `steps` persistent launches reading their work
@@ -106,7 +109,7 @@ struct chfsi_handle_s {
     double batch_filter_ms = 0, batch_flops = 0;
     int batch_graph_launches = 0, batch_kernel_launches = 0;
     bool batch_use_graph = true;   // replay each loop's filter steps as one captured graph
-    int batch_lanes = 1;           // streams the problems of a batch are spread over
+    int batch_lanes = 3;           // streams (and host threads) the dense steps of a batch are spread over
     hipEvent_t bev[3] = {nullptr, nullptr, nullptr};   // filter start / end, lane join
 };
 

@@ -220,6 +220,11 @@ chfsi_status chfsi_destroy(chfsi_handle h)
     }
     if (h->btable) (void)hipFree(h->btable);
     for (auto& l : h->lanes) {
+        if (l.sub) {
+            if (l.sub->tile_cnt) (void)hipFree(l.sub->tile_cnt);
+            l.sub->model = nullptr;   // the parent's
+            delete l.sub;
+        }
         if (l.ev) (void)hipEventDestroy(l.ev);
         if (l.st) (void)hipStreamDestroy(l.st);
     }
