@@ -103,30 +103,35 @@ __global__ __launch_bounds__(256) void k_eig_compress(int k, int M, const zd* __
     }
 }
 
-// Kernel A: workgroup w diagonalises the subproblem of block pair w of round `round`.
-__global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, const zd* __restrict__ Gp,
+// Kernel A: workgroup w diagonalises the subproblem of block pair w of round `round` (512 threads:
+// two per 2 x 2 block, so that two waves per SIMD hide the latency of the rotation updates).
+__global__ __launch_bounds__(512) void k_eig_inner(int M, int nb, int round, const zd* __restrict__ Gp,
                                                    zd* __restrict__ J, const double* __restrict__ scale)
 {
-    __shared__ zd A[ES * EP];
+    __shared__ zd A2[2][ES * EP];
     __shared__ zd V[ES * EP];
     __shared__ double rc[ES / 2];
     __shared__ zd rs[ES / 2];
-    __shared__ int rot[ES];            // rot[r] != 0: some pair of round r is rotated
+    __shared__ int rot[ES];
     const int tid = threadIdx.x;
     int P, Q;
     rr_pair(nb, round, blockIdx.x, P, Q);
     #pragma unroll
-    for (int e = tid; e < ES * ES; e += 256) {
+    for (int e = tid; e < ES * ES; e += 512) {
         const int u = e % ES, v = e / ES;
-        A[u * EP + v] = Gp[(size_t)sub_index(P, Q, u) + (size_t)sub_index(P, Q, v) * M];
+        A2[0][u * EP + v] = Gp[(size_t)sub_index(P, Q, u) + (size_t)sub_index(P, Q, v) * M];
         V[u * EP + v] = make_double2(u == v ? 1.0 : 0.0, 0.0);
     }
     if (tid < ES) rot[tid] = 0;
     const double tol2 = scale[1];   // squared rotation threshold
-    // this thread's 2 x 2 block (pair bi, pair bj) and its two rows of V (rows bi, bi + 16; pair bj)
-    const int bi = tid / (ES / 2), bj = tid % (ES / 2);
+    // this thread's 2 x 2 block (pair bi, pair bj), its row `half` (pi or qi) and row bi + 16 half
+    // of V (pair bj); the subproblem is double-buffered, since both rows of a block read all four
+    // of its entries
+    const int bi = (tid & 255) / (ES / 2), bj = tid % (ES / 2), half = tid >> 8;
+    int cur = 0;
     __syncthreads();
     for (int r = 0; r < ES - 1; ++r) {
+        const zd* A = A2[cur];
         if (tid < ES / 2) {
             int p, q;
             rr_pair(ES, r, tid, p, q);
@@ -151,43 +156,40 @@ __global__ __launch_bounds__(256) void k_eig_inner(int M, int nb, int round, con
         }
         __syncthreads();
         if (rot[r]) {
+            zd* An = A2[cur ^ 1];
             int pi, qi, pj, qj;
             rr_pair(ES, r, bi, pi, qi);
             rr_pair(ES, r, bj, pj, qj);
             const double ci = rc[bi], cj = rc[bj];
             const zd si = rs[bi], sj = rs[bj];
             const zd b00 = A[pi * EP + pj], b01 = A[pi * EP + qj], b10 = A[qi * EP + pj], b11 = A[qi * EP + qj];
-            // T = B R_j,  R = [[c, s], [-conj(s), c]]
+            // T = B R_j,  R = [[c, s], [-conj(s), c]];  B' = R_i^H T,  R^H = [[c, -s], [conj(s), c]]
             const zd nsj = make_double2(-sj.x, sj.y);   // -conj(s_j)
             const zd t00 = zaxpy(cj, b00, nsj, b01), t01 = zaxpy(cj, b01, sj, b00);
             const zd t10 = zaxpy(cj, b10, nsj, b11), t11 = zaxpy(cj, b11, sj, b10);
-            // B' = R_i^H T,  R^H = [[c, -s], [conj(s), c]]
             const zd msi = make_double2(-si.x, -si.y), csi = zconjd(si);
-            zd o00 = zaxpy(ci, t00, msi, t10), o01 = zaxpy(ci, t01, msi, t11);
-            zd o10 = zaxpy(ci, t10, csi, t00), o11 = zaxpy(ci, t11, csi, t01);
-            if (bi == bj) {   // the rotated 2 x 2 diagonal block is diagonal and real
-                o01 = make_double2(0.0, 0.0);
-                o10 = o01;
-                o00.y = 0.0;
-                o11.y = 0.0;
+            if (half == 0) {   // row pi
+                zd o00 = zaxpy(ci, t00, msi, t10), o01 = zaxpy(ci, t01, msi, t11);
+                if (bi == bj) { o01 = make_double2(0.0, 0.0); o00.y = 0.0; }   // the rotated diagonal block is real diagonal
+                An[pi * EP + pj] = o00;
+                An[pi * EP + qj] = o01;
+            } else {           // row qi
+                zd o10 = zaxpy(ci, t10, csi, t00), o11 = zaxpy(ci, t11, csi, t01);
+                if (bi == bj) { o10 = make_double2(0.0, 0.0); o11.y = 0.0; }
+                An[qi * EP + pj] = o10;
+                An[qi * EP + qj] = o11;
             }
-            A[pi * EP + pj] = o00;
-            A[pi * EP + qj] = o01;
-            A[qi * EP + pj] = o10;
-            A[qi * EP + qj] = o11;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {   // V <- V R
-                const int u = bi + h * (ES / 2);
-                const zd vp = V[u * EP + pj], vq = V[u * EP + qj];
-                V[u * EP + pj] = zaxpy(cj, vp, nsj, vq);
-                V[u * EP + qj] = zaxpy(cj, vq, sj, vp);
-            }
+            const int u = bi + half * (ES / 2);   // V <- V R on row u
+            const zd vp = V[u * EP + pj], vq = V[u * EP + qj];
+            V[u * EP + pj] = zaxpy(cj, vp, nsj, vq);
+            V[u * EP + qj] = zaxpy(cj, vq, sj, vp);
+            cur ^= 1;
         }
         __syncthreads();
     }
     zd* Jw = J + (size_t)blockIdx.x * ES * ES;
     #pragma unroll
-    for (int e = tid; e < ES * ES; e += 256) {
+    for (int e = tid; e < ES * ES; e += 512) {
         const int u = e % ES, v = e / ES;
         Jw[e] = V[u * EP + v];
     }
@@ -405,7 +407,7 @@ int eig_jacobi(hipStream_t s, int m, zd* G, int ldg, double* theta, void* work, 
         bool done = false;
         while (!done && sw < 40) {
             for (int r = 0; r < nb - 1; ++r) {
-                hipLaunchKernelGGL(k_eig_inner, dim3(npair), dim3(256), 0, s, M, nb, r, (const zd*)Gp, J,
+                hipLaunchKernelGGL(k_eig_inner, dim3(npair), dim3(512), 0, s, M, nb, r, (const zd*)Gp, J,
                                    (const double*)scl);
                 hipLaunchKernelGGL(k_eig_apply, dim3(npair * npair + (M / ES) * npair), dim3(256), 0, s, M, nb, r,
                                    Gp, Wp, (const zd*)J);
