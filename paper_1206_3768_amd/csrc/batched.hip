@@ -363,15 +363,19 @@ chfsi_status run_lanes_threaded(chfsi_handle h, std::vector<Slot>& sl, const std
         for (int i : act) {
             Slot& z = sl[i];
             if (z.lane != l) continue;
-            chfsi_status rc = st_loop_enqueue(sub, z.s);
-            if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
-            if (z.s.done) continue;
-            rc = st_loop_complete(sub, z.s);
-            if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(sub, z.s);
-            if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
-            if (z.s.done || !z.s.want_final) continue;
-            rc = st_final_complete(sub, z.s);
-            if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+            try {   // nothing may escape a thread (host allocations of the steps can throw)
+                chfsi_status rc = st_loop_enqueue(sub, z.s);
+                if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
+                if (z.s.done) continue;
+                rc = st_loop_complete(sub, z.s);
+                if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(sub, z.s);
+                if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
+                if (z.s.done || !z.s.want_final) continue;
+                rc = st_final_complete(sub, z.s);
+                if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
+            } catch (...) {
+                rcs[i] = fail(z, CHFSI_ERR_ALLOC);
+            }
         }
     };
     std::vector<std::thread> th;
