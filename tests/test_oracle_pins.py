@@ -364,3 +364,89 @@ def test_adam_first_step_is_signed_lr(orc):
     m = np.zeros(3); v = np.zeros(3)
     orc.adam_step(P, g, m, v, 1, lr=0.01, eps=0.0)
     assert np.allclose(P, [1.0 - 0.01, -2.0 + 0.01, 0.5 - 0.01], atol=1e-15)
+
+
+# ---- cold-start lower bound a (Algorithm 1's damped interval, spectral-CDF reading) ------------
+
+def test_bounds_cold_start_a_exact_index(orc):
+    # Direct pin of the rule: a = the smallest theta_j whose cumulative weight sum_{i<=j} |z_1i|^2
+    # reaches m/n.  Dyadic weights make the running sums exact, so the ">=" boundary is tested
+    # exactly: with m/n = 1/4 the sum reaches it at j = 1 (a ">" would move a to j = 2).
+    theta = np.array([-0.9, -0.6, -0.1, 0.3, 0.8])
+    zw = np.array([0.125, 0.125, 0.25, 0.25, 0.25])
+    mu1, a, b = orc.bounds(theta, zw, 0.05, 16, 64)        # m/n = 0.25
+    assert (mu1, b) == (-0.9, 0.8 + 0.05)
+    assert a == theta[1]
+    mu1, a, b = orc.bounds(theta, zw, 0.05, 17, 64)        # just above 1/4: next index
+    assert a == theta[2]
+    mu1, a, b = orc.bounds(theta, zw, 0.05, 32, 64)        # 1/2: sum 0.5 at j = 2
+    assert a == theta[2]
+    # the first weight alone reaches m/n: a would equal mu1, so the midpoint (mu1 + b)/2 is taken
+    mu1, a, b = orc.bounds(theta, zw, 0.05, 8, 64)         # m/n = 1/8
+    assert a == 0.5 * (-0.9 + (0.8 + 0.05))
+    # weights that never reach m/n leave a at the largest Ritz value (strictly below b)
+    mu1, a, b = orc.bounds(theta, zw * 0.5, 0.05, 40, 64)
+    assert a == theta[-1]
+
+
+def test_bounds_cold_start_a_from_full_lanczos_on_diagonal(orc):
+    # Full Lanczos on a diagonal H recovers every eigenvalue, and the squared first components of
+    # T_n's eigenvectors are the weights of the start vector on the eigenvectors (e_j), i.e.
+    # |v_1[j]|^2 with v_1 the normalised Philox stream-2 vector, whose words numpy's Philox bit
+    # generator reproduces.  The index of a then follows from numpy alone.
+    n, seed = 24, 11
+    rng = np.random.default_rng(3)
+    h = rng.permutation(np.linspace(-1.0, 1.0, n) + 0.01 * rng.standard_normal(n))
+    H = np.diag(h).astype(complex)
+    theta, zw, bk = orc.lanczos(H, n, seed=seed)
+    v = np.empty(n, dtype=complex)
+    u = lambda w: float(int(w) >> 11) * 2.0**-53
+    for i in range(n):
+        c = [i >> 1, 2, 0, 0]
+        c0 = [c[0] - 1, 2, 0, 0] if c[0] > 0 else [2**64 - 1, 1, 0, 0]
+        words = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
+                                 counter=np.array(c0, dtype=np.uint64)).random_raw(4)
+        k = 2 * (i & 1)
+        v[i] = complex(2 * u(words[k]) - 1, 2 * u(words[k + 1]) - 1)
+    w = np.abs(v) ** 2 / np.sum(np.abs(v) ** 2)
+    order = np.argsort(h)
+    assert np.allclose(theta, h[order], atol=1e-12)
+    assert np.allclose(zw, w[order], atol=1e-12)
+    for m in (3, 7, 12):
+        cum = np.cumsum(w[order])
+        j = int(np.argmax(cum >= m / n - 1e-12))
+        mu1, a, b = orc.bounds(theta, zw, bk, m, n)
+        expect = h[order][j] if j > 0 else 0.5 * (mu1 + b)
+        assert abs(a - expect) <= 1e-12, (m, j, a, expect)
+
+
+# ---- degree network forward pass, written out from the documented parameter layout ------------
+
+def _mlp_forward_numpy(P, X, dmin=4.0, dmax=30.0):
+    # W[out][in] row-major: W1[64][5] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[1][64] b4[1]
+    o = 0
+    layers = []
+    for nin, nout in ((5, 64), (64, 64), (64, 64), (64, 1)):
+        W = P[o:o + nout * nin].reshape(nout, nin); o += nout * nin
+        b = P[o:o + nout]; o += nout
+        layers.append((W, b))
+    assert o == P.size
+    h = X
+    for W, b in layers[:-1]:
+        h = np.maximum(h @ W.T + b, 0.0)
+    z = (h @ layers[-1][0].T + layers[-1][1])[:, 0]
+    return dmin + (dmax - dmin) / (1.0 + np.exp(-z))
+
+
+def test_mlp_forward_matches_numpy_layout(orc):
+    rng = np.random.default_rng(5)
+    P = rng.standard_normal(orc.mlp_nparams()) * 0.3
+    X = rng.standard_normal((40, 5)) * 2.0
+    got = orc.mlp_forward(P, X)
+    ref = _mlp_forward_numpy(P, X)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    # a transposed weight layout gives a different network: the pin is sensitive to it
+    W1 = P[:320].reshape(64, 5)
+    Pt = P.copy()
+    Pt[:320] = W1.T.reshape(-1)
+    assert np.max(np.abs(_mlp_forward_numpy(Pt, X) - ref)) > 1e-3
