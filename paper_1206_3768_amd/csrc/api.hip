@@ -227,7 +227,7 @@ chfsi_status st_setup(chfsi_handle h, SolveState& s, Arena& ar, PinBuf& pin)
     if (s.p.degree_policy == CHFSI_DEG_LEARNED && !h->has_model) return CHFSI_ERR_ARG;
     TRYS(prepare_bufs(h, ar, s.b, s.n, s.m, s.k, s.S != nullptr, s.prec));
     const size_t nd = SolveState::pinned_doubles(s.m, s.k);
-    if (!pin.reserve(sizeof(double) * nd + sizeof(int) * (32 + 2 * (size_t)s.m))) return CHFSI_ERR_ALLOC;
+    if (!pin.reserve(sizeof(double) * nd + sizeof(int) * SolveState::pinned_ints(s.m))) return CHFSI_ERR_ALLOC;
     s.hd = (double*)pin.p;
     s.hi = (int*)(pin.p + sizeof(double) * nd);
     std::memset(s.hi, 0, sizeof(int) * 32);
@@ -254,11 +254,6 @@ chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
         TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.info, s.hi, b.gw));
         s.H = b.H;
         s.ldh = n;
-        // The reduction completes before the caller enqueues more work.  A batch solved over several
-        // streams overlapped the reductions of different problems otherwise, and in that mode some
-        // problems ended with a factor inconsistent with their H (no device error; cause not
-        // identified); every other phase overlaps correctly.
-        TRY(hipStreamSynchronize(st));
     }
     double* hn = s.h_norms();
     hn[1] = 1.0;
@@ -355,7 +350,7 @@ chfsi_status st_order_columns(chfsi_handle h, SolveState& s, std::vector<int>& d
     for (int j = 0; j < ma; ++j) { dsorted[j] = d[ord[j]]; ident &= ord[j] == j; }
     s.permuted = !ident;
     if (!ident) {
-        int* perm = s.hi + 32;   // pinned staging [2 m]: order, inverse
+        int* perm = s.h_perm();   // pinned staging [2 m]: order, inverse
         for (int j = 0; j < ma; ++j) { perm[j] = ord[j]; perm[ma + ord[j]] = j; }
         TRY(hipMemcpyAsync(s.b.iperm, perm, sizeof(int) * 2 * ma, hipMemcpyHostToDevice, st));
         TRY(launch_permute_cols(st, n, ma, s.Ya(), n, s.b.T, n, s.b.iperm));

@@ -241,16 +241,6 @@ chfsi_status get_graph(chfsi_handle h, int steps, int bm, int bn, int grid, hipG
     return CHFSI_SUCCESS;
 }
 
-// binds the handle's stream to a lane for the per-problem steps; restores it
-struct LaneBinding {
-    chfsi_handle h;
-    hipStream_t st0;
-    explicit LaneBinding(chfsi_handle hh) : h(hh), st0(hh->stream) {}
-    void use(int lane) { h->stream = h->lanes[lane].st; }
-    void main() { h->stream = st0; }
-    ~LaneBinding() { main(); }
-};
-
 struct Slot {
     SolveState s;
     int lane = 0;
@@ -324,7 +314,7 @@ chfsi_status batched_filter(chfsi_handle h, std::vector<Slot>& sl, const std::ve
         Slot& z = sl[i];
         SolveState& s = z.s;
         const int ma = s.ma();
-        int* flag = s.hi + 32 + s.m;   // pinned staging [m]
+        int* flag = s.h_flags();   // pinned staging [m], disjoint from the column order's
         bool any = false;
         for (int j = 0; j < ma; ++j) { flag[j] = z.dsorted[j] % 2; any |= flag[j] != 0; }
         if (!any) continue;
@@ -341,10 +331,8 @@ chfsi_status fail(Slot& z, chfsi_status rc)
     return rc;
 }
 
-// The loop's dense steps (QR, Rayleigh-Ritz, lock decision, verification) of the problems in `act`,
-// one host thread per lane, each through its lane's handle; every problem stays on its lane.
-chfsi_status run_lanes_threaded(chfsi_handle h, std::vector<Slot>& sl, const std::vector<int>& act,
-                                std::vector<chfsi_status>& rcs)
+// Copies what the lane handles read from the main handle (tuned plans, degree model).
+void refresh_lanes(chfsi_handle h)
 {
     const int nl = std::min(h->batch_lanes, (int)h->lanes.size());
     for (int l = 0; l < nl; ++l) {
@@ -353,6 +341,19 @@ chfsi_status run_lanes_threaded(chfsi_handle h, std::vector<Slot>& sl, const std
         sub->model = h->model;
         sub->has_model = h->has_model;
     }
+}
+
+// Runs step(sub, slot) for every problem in `act` through the handle of its lane (the lane's stream,
+// split-K counters and pinned state), one host thread per lane when there are several: the
+// per-problem phases wait on the host (the reduction's pivot check, eigensolver sweeps, QR pass
+// decisions, the lock decision), so only separate threads let those of different problems overlap
+// on the device.  A problem whose step fails is marked done with its status.  The main handle is
+// never touched by a lane thread.
+template <class F>
+void run_on_lanes(chfsi_handle h, std::vector<Slot>& sl, const std::vector<int>& act,
+                  std::vector<chfsi_status>& rcs, F step)
+{
+    const int nl = std::min(h->batch_lanes, (int)h->lanes.size());
     auto work = [&](int l) {
         chfsi_handle sub = h->lanes[l].sub;
         if (hipSetDevice(h->device) != hipSuccess) {
@@ -362,22 +363,19 @@ chfsi_status run_lanes_threaded(chfsi_handle h, std::vector<Slot>& sl, const std
         }
         for (int i : act) {
             Slot& z = sl[i];
-            if (z.lane != l) continue;
+            if (z.lane != l || z.s.done) continue;
             try {   // nothing may escape a thread (host allocations of the steps can throw)
-                chfsi_status rc = st_loop_enqueue(sub, z.s);
-                if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
-                if (z.s.done) continue;
-                rc = st_loop_complete(sub, z.s);
-                if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(sub, z.s);
-                if (rc != CHFSI_SUCCESS) { rcs[i] = fail(z, rc); continue; }
-                if (z.s.done || !z.s.want_final) continue;
-                rc = st_final_complete(sub, z.s);
+                const chfsi_status rc = step(sub, z);
                 if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
             } catch (...) {
                 rcs[i] = fail(z, CHFSI_ERR_ALLOC);
             }
         }
     };
+    if (nl <= 1) {
+        work(0);
+        return;
+    }
     std::vector<std::thread> th;
     int started = 0;
     try {
@@ -391,7 +389,26 @@ chfsi_status run_lanes_threaded(chfsi_handle h, std::vector<Slot>& sl, const std
     work(0);
     for (int l = started + 1; l < nl; ++l) work(l);
     for (auto& t : th) t.join();
-    return CHFSI_SUCCESS;
+}
+
+// reduction to standard form, norms and Lanczos of one problem (its lane's stream)
+chfsi_status init_step(chfsi_handle sub, Slot& z)
+{
+    chfsi_status rc = st_init_enqueue(sub, z.s);
+    if (rc == CHFSI_SUCCESS) rc = st_init_complete(sub, z.s);
+    return rc;
+}
+
+// the loop's dense steps: QR, Rayleigh-Ritz, lock decision and, once nev pairs are locked, the
+// verification
+chfsi_status loop_step(chfsi_handle sub, Slot& z)
+{
+    chfsi_status rc = st_loop_enqueue(sub, z.s);
+    if (rc != CHFSI_SUCCESS || z.s.done) return rc;
+    rc = st_loop_complete(sub, z.s);
+    if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(sub, z.s);
+    if (rc != CHFSI_SUCCESS || z.s.done || !z.s.want_final) return rc;
+    return st_final_complete(sub, z.s);
 }
 
 chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, const chfsi_params& base,
@@ -403,34 +420,32 @@ chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, 
         h->barena.resize(first_index + count);
         h->bpin.resize(first_index + count);
     }
-    LaneBinding bind(h);
+    const int nl = std::max(1, std::min(h->batch_lanes, (int)h->lanes.size()));
+    refresh_lanes(h);
     auto t0 = std::chrono::steady_clock::now();
-    // set-up and initial phases (reduction, Lanczos) of every problem
+    // buffers of every problem (one arena and one pinned staging buffer each), then the initial
+    // phases (reduction, Lanczos) on the problems' lanes
+    std::vector<int> all;
     for (int i = 0; i < count; ++i) {
         const chfsi_problem& q = probs[i];
         chfsi_params pk = base;
         pk.nev = q.nev;
         pk.nex = q.nex;
         Slot& z = sl[i];
-        z.lane = i % h->batch_lanes;
-        bind.use(z.lane);
+        z.lane = i % nl;
         chfsi_status rc = st_define(z.s, q.n, (const zd*)q.A, q.lda, (const zd*)q.S, q.lds, (zd*)q.X, q.ldx,
                                     q.x_is_guess, q.lambda, q.resid, pk);
         if (rc == CHFSI_SUCCESS) rc = st_setup(h, z.s, h->barena[first_index + i], h->bpin[first_index + i]);
-        if (rc == CHFSI_SUCCESS && h->batch_lanes > 1) {   // split-K counters of the problem's lane
+        if (rc == CHFSI_SUCCESS) {   // split-K counters of the problem's lane
             z.s.b.gw.cnt = h->lanes[z.lane].sub->tile_cnt;
             z.s.b.gw.ncnt = h->lanes[z.lane].sub->tile_cnt_len;
+            all.push_back(i);
+        } else {
+            rcs[i] = fail(z, rc);
         }
-        if (rc == CHFSI_SUCCESS) rc = st_init_enqueue(h, z.s);
-        if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
     }
-    for (int i = 0; i < count; ++i) {
-        Slot& z = sl[i];
-        if (z.s.done) continue;
-        bind.use(z.lane);
-        const chfsi_status rc = st_init_complete(h, z.s);
-        if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
-    }
+    // the arenas may have been (re)allocated: nothing of them is in flight on any stream
+    run_on_lanes(h, sl, all, rcs, init_step);
     for (;;) {
         std::vector<int> act;
         for (int i = 0; i < count; ++i)
@@ -438,11 +453,9 @@ chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, 
         if (act.empty()) break;
         // column order by degree on each problem's lane, then the lanes join the main stream
         for (int i : act) {
-            bind.use(sl[i].lane);
-            const chfsi_status rc = st_order_columns(h, sl[i].s, sl[i].dsorted);
+            const chfsi_status rc = st_order_columns(h->lanes[sl[i].lane].sub, sl[i].s, sl[i].dsorted);
             if (rc != CHFSI_SUCCESS) return rc;
         }
-        bind.main();
         for (auto& l : h->lanes) {
             TRY(hipEventRecord(l.ev, l.st));
             TRY(hipStreamWaitEvent(h->stream, l.ev, 0));
@@ -450,44 +463,17 @@ chfsi_status solve_chunk(chfsi_handle h, int count, const chfsi_problem* probs, 
         TRYS(batched_filter(h, sl, act));
         TRY(hipEventRecord(h->bev[2], h->stream));
         for (auto& l : h->lanes) TRY(hipStreamWaitEvent(l.st, h->bev[2], 0));
-        // QR and Rayleigh-Ritz of every problem, then the host decisions
-        if (h->batch_lanes > 1) {
-            // one host thread per lane: the dense steps wait on the host (eigensolver sweeps,
-            // the pass decisions of QR, the lock decision), so only separate threads let those of
-            // different problems overlap on the device
-            TRYS(run_lanes_threaded(h, sl, act, rcs));
-        } else {
-            for (int i : act) {
-                bind.use(sl[i].lane);
-                const chfsi_status rc = st_loop_enqueue(h, sl[i].s);
-                if (rc != CHFSI_SUCCESS) rcs[i] = fail(sl[i], rc);
-            }
-            for (int i : act) {
-                Slot& z = sl[i];
-                if (z.s.done) continue;
-                bind.use(z.lane);
-                chfsi_status rc = st_loop_complete(h, z.s);
-                if (rc == CHFSI_SUCCESS && z.s.want_final) rc = st_final_enqueue(h, z.s);
-                if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
-            }
-            for (int i : act) {
-                Slot& z = sl[i];
-                if (z.s.done || !z.s.want_final) continue;
-                bind.use(z.lane);
-                const chfsi_status rc = st_final_complete(h, z.s);
-                if (rc != CHFSI_SUCCESS) rcs[i] = fail(z, rc);
-            }
-        }
+        // QR, Rayleigh-Ritz, the host decisions and the verification of every problem
+        run_on_lanes(h, sl, act, rcs, loop_step);
         float ms = 0;
         if (hipEventElapsedTime(&ms, h->bev[0], h->bev[1]) == hipSuccess) h->batch_filter_ms += ms;
     }
     chfsi_status first = CHFSI_SUCCESS;
     for (int i = 0; i < count; ++i) {
         Slot& z = sl[i];
-        bind.use(z.lane);
         chfsi_stats stt;
         std::memset(&stt, 0, sizeof(stt));
-        if (rcs[i] == CHFSI_SUCCESS || rcs[i] == CHFSI_ERR_NUMERIC) st_finish(h, z.s, stt);
+        if (rcs[i] == CHFSI_SUCCESS || rcs[i] == CHFSI_ERR_NUMERIC) st_finish(h->lanes[z.lane].sub, z.s, stt);
         else stt.status = rcs[i];
         const chfsi_status si = rcs[i] == CHFSI_SUCCESS ? z.s.status : rcs[i];
         stt.status = si;

@@ -53,7 +53,7 @@ struct SolveState {
     SolveBufs b;
     PhaseTimer* tm = nullptr;          // phase events (single solves)
     double* hd = nullptr;              // pinned host doubles, see the accessors below
-    int* hi = nullptr;                 // pinned host ints: info words [0, 16), staging [32, 32 + 2 m)
+    int* hi = nullptr;                 // pinned host ints, see h_perm / h_flags
     bool permuted = false;             // the active columns are in the filter's degree order
     // algorithm state
     const zd* H = nullptr;
@@ -78,6 +78,13 @@ struct SolveState {
     double* h_res() { return hd + 3 * m + 2 + 2 * k; }       // [m]
     double* h_eig() { return hd + 4 * m + 2 + 2 * k; }       // [eig_host_doubles(m)]
     static size_t pinned_doubles(int m, int k) { return 4 * (size_t)m + 2 + 2 * (size_t)k + eig_host_doubles(m); }
+    // pinned ints: info words [0, 16); the filter's column order and its inverse [32, 32 + 2 m);
+    // the odd-degree flags of the batched filter [32 + 2 m, 32 + 3 m).  The two staging regions are
+    // disjoint: the host writes the flags of a loop while the copy of that loop's column order may
+    // still be pending on another stream.
+    int* h_perm() { return hi + 32; }
+    int* h_flags() { return hi + 32 + 2 * (size_t)m; }
+    static size_t pinned_ints(int m) { return 32 + 3 * (size_t)m; }
     int ma() const { return m - nlocked; }
     zd* Ya() { return b.V + (size_t)nlocked * n; }
 };

@@ -149,25 +149,60 @@ def test_batched_more_problems_than_one_launch_holds(hd):
         assert np.abs(X.conj().T @ kp.S @ X - np.eye(X.shape[1])).max() <= 1e-12
 
 
-def test_batched_over_several_streams_matches_one_stream(hd):
-    """The per-problem dense steps spread over four streams (four host threads) give the same
-    converged pairs as one stream."""
+def test_batched_over_several_streams_matches_one_stream(hd, orc):
+    """Every per-problem phase (reduction and Lanczos included) spread over four and eight streams,
+    one host thread each, gives the converged pairs of one stream, and each problem matches the
+    exact spectrum of its pencil (and the oracle on the smallest three)."""
+    import scipy.linalg as sla
     from paper_1206_3768_amd import chfsi
     rng = np.random.default_rng(21)
     sizes = [int(v) for v in rng.integers(700, 1600, size=12)]
     kps = _problems(sizes, seed=13)
     out = {}
-    for lanes in (1, 4):
+    for lanes in (1, 4, 8):
         hd.set_batched_plan(64, 64, use_graph=True, lanes=lanes)
         probs = _upload(kps)
         st, res = hd.solve_batched(probs, _params())
+        print(f"lanes {lanes}: statuses {[r.status for r in res]}", flush=True)
         assert st == 0, [r.status for r in res]
-        out[lanes] = res
+        out[lanes] = (res, [chfsi.to_numpy(p["X"]) for p in probs])
     hd.set_batched_plan(64, 64, use_graph=True, lanes=3)   # the library default
-    for kp, a, b in zip(kps, out[1], out[4]):
-        assert a.stats["loops"] == b.stats["loops"]
-        assert np.all(np.abs(a.lam[:kp.nev] - b.lam[:kp.nev]) <= 1e-12 * np.maximum(np.abs(a.lam[:kp.nev]), 1e-3))
-        assert b.resid[:kp.nev].max() <= 1e-10
+    for k, kp in enumerate(kps):
+        ev = sla.eigh(kp.A, kp.S, eigvals_only=True, subset_by_index=[0, kp.nev - 1])
+        a = out[1][0][k]
+        for lanes in (4, 8):
+            b, Xb = out[lanes][0][k], out[lanes][1][k]
+            assert a.stats["loops"] == b.stats["loops"]
+            assert np.all(np.abs(a.lam[:kp.nev] - b.lam[:kp.nev]) <= 1e-12 * np.maximum(np.abs(a.lam[:kp.nev]), 1e-3))
+            _check_pair_set(kp, b.lam, b.resid, Xb, ev)
+    for k in np.argsort(sizes)[:3]:
+        kp = kps[k]
+        ref = orc.solve(kp.A, kp.S, nev=kp.nev, nex=kp.nex, deg=12, tol=1e-10, X0=kp.X0, seed=4)
+        assert ref.status == 0
+        b = out[4][0][k]
+        assert np.all(np.abs(b.lam[:kp.nev] - ref.lam[:kp.nev]) <= 1e-10 * np.maximum(np.abs(ref.lam[:kp.nev]), 1e-3))
+        assert abs(b.stats["loops"] - ref.stats["loops"]) <= 1
+
+
+def test_batched_per_vector_degrees_more_problems_than_lanes(hd):
+    """Analytic per-vector degrees make the filter reorder the columns of every problem by degree
+    (a column order staged through pinned memory) and copy odd-degree columns back (flags staged
+    through pinned memory).  Eight problems on three lanes, so several share a lane; each must equal
+    its single-problem solve."""
+    from paper_1206_3768_amd import chfsi
+    kps = _problems([420, 515, 388, 610, 457, 530, 366, 480], seed=17)
+    hd.set_batched_plan(64, 64, use_graph=True, lanes=3)
+    prm = _params(degree_policy=chfsi.DEG_ANALYTIC)
+    probs = _upload(kps)
+    st, res = hd.solve_batched(probs, prm)
+    assert st == 0, [r.status for r in res]
+    for kp, pr, r in zip(kps, probs, res):
+        one = hd.solve(chfsi.to_device(kp.A), chfsi.to_device(kp.S), chfsi.to_device(kp.X0), True,
+                       _params(nev=kp.nev, nex=kp.nex, degree_policy=chfsi.DEG_ANALYTIC))
+        assert one.status == 0
+        assert r.stats["loops"] == one.stats["loops"] and r.stats["matvecs"] == one.stats["matvecs"]
+        assert np.all(np.abs(one.lam[:kp.nev] - r.lam[:kp.nev]) <= 1e-12 * np.maximum(np.abs(r.lam[:kp.nev]), 1e-3))
+        _check_pair_set(kp, r.lam, r.resid, chfsi.to_numpy(pr["X"]), one.lam)
 
 
 def test_batched_error_in_one_problem_leaves_the_others(hd):
