@@ -69,8 +69,83 @@ def _load():
     lib.orc_mlp_loss_grad.argtypes = [dp, ip, dp, dp, C.c_double, C.c_double, dp]
     lib.orc_mlp_loss_grad.restype = C.c_double
     lib.orc_adam_step.argtypes = [ip, dp, dp, dp, dp, ip, C.c_double, C.c_double, C.c_double, C.c_double]
+    lib.orc_set_library_hooks.argtypes = [dp, dp, dp]
     _lib = lib
     return lib
+
+
+# ---- optional library primitives ----------------------------------------------------------------
+# The C reference writes its dense product, triangular solves and Cholesky factor as plain loops,
+# which stream the whole matrix once per column: fine up to a few thousand, hours at order 8192.
+# use_library_products(True) routes exactly those three primitives to numpy's matmul and LAPACK
+# (scipy ztrsm / zpotrf) -- library routines with the same definitions -- while every step of the
+# method above them stays the C code.
+
+_GEMM_T = C.CFUNCTYPE(None, C.c_char, C.c_char, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p,
+                      C.c_int, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int)
+_TRSM_T = C.CFUNCTYPE(None, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int)
+_CHOL_T = C.CFUNCTYPE(C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int)
+_hooks = None
+
+
+def _view(ptr: int, rows: int, cols: int, ld: int) -> np.ndarray:
+    """Column-major rows x cols matrix with leading dimension ld at address ptr (no copy)."""
+    if rows == 0 or cols == 0:
+        return np.zeros((rows, cols), dtype=np.complex128, order="F")
+    buf = (C.c_double * (2 * (ld * (cols - 1) + rows))).from_address(ptr)
+    return np.ndarray((rows, cols), dtype=np.complex128, buffer=buf, strides=(16, 16 * ld))
+
+
+def _gemm_cb(ta, tb, m, n, k, ar, ai, A, lda, B, ldb, br, bi, Cp, ldc):
+    ta, tb = ta.decode(), tb.decode()
+    out = _view(Cp, m, n, ldc)
+    if k == 0:
+        prod = np.zeros((m, n), dtype=np.complex128)
+    else:
+        a = _view(A, m, k, lda) if ta == "N" else _view(A, k, m, lda).conj().T
+        b = _view(B, k, n, ldb) if tb == "N" else _view(B, n, k, ldb).conj().T
+        prod = a @ b
+    res = complex(ar, ai) * prod
+    if br != 0.0 or bi != 0.0:
+        res += complex(br, bi) * out
+    out[...] = res
+
+
+def _trsm_cb(conj_trans, n, nrhs, L, ldl, B, ldb):
+    import scipy.linalg as sla
+    if n == 0 or nrhs == 0:
+        return
+    lo = _view(L, n, n, ldl)
+    b = _view(B, n, nrhs, ldb)
+    b[...] = sla.solve_triangular(lo, b, lower=True, trans="C" if conj_trans else "N", check_finite=False)
+
+
+def _chol_cb(n, S, lds, L, ldl):
+    import scipy.linalg as sla
+    s = _view(S, n, n, lds)
+    lo = _view(L, n, n, ldl)
+    try:
+        f = sla.cholesky(np.tril(s), lower=True, check_finite=False)
+    except np.linalg.LinAlgError:
+        return 1
+    if not np.all(np.isfinite(f)):
+        return 1
+    lo[...] = np.tril(f)
+    return 0
+
+
+def use_library_products(on: bool = True) -> None:
+    """Routes the reference's dense products, triangular solves and Cholesky factor to numpy /
+    LAPACK (on) or back to its plain loops (off)."""
+    global _hooks
+    lib = _load()
+    if on:
+        _hooks = (_GEMM_T(_gemm_cb), _TRSM_T(_trsm_cb), _CHOL_T(_chol_cb))
+        lib.orc_set_library_hooks(C.cast(_hooks[0], C.c_void_p), C.cast(_hooks[1], C.c_void_p),
+                                  C.cast(_hooks[2], C.c_void_p))
+    else:
+        lib.orc_set_library_hooks(None, None, None)
+        _hooks = None
 
 
 def _p(a: np.ndarray):

@@ -39,6 +39,29 @@ typedef double complex zc;
 #define IDX(i, j, ld) ((size_t)(i) + (size_t)(j) * (size_t)(ld))
 
 /* ------------------------------------------------------------------------------------------------
+ * Optional library primitives.  The dense product, the triangular solve and the Cholesky factor
+ * below are written out as plain loops; a caller may route them to library routines of the same
+ * definition instead (BLAS/LAPACK on the host), which the order-8192 problems need: the plain loops
+ * stream the whole matrix once per column.  Every step of the method above these primitives stays
+ * as written here.  NULL (the default) selects the plain loops.
+ * ---------------------------------------------------------------------------------------------- */
+typedef void (*orc_gemm_hook)(char ta, char tb, int m, int n, int k, double alpha_re, double alpha_im,
+                              const zc* A, int lda, const zc* B, int ldb, double beta_re, double beta_im,
+                              zc* C, int ldc);
+typedef void (*orc_trsm_hook)(int conj_trans, int n, int nrhs, const zc* L, int ldl, zc* B, int ldb);
+typedef int (*orc_chol_hook)(int n, const zc* S, int lds, zc* L, int ldl);
+static orc_gemm_hook g_gemm_hook = 0;
+static orc_trsm_hook g_trsm_hook = 0;
+static orc_chol_hook g_chol_hook = 0;
+
+void orc_set_library_hooks(orc_gemm_hook g, orc_trsm_hook t, orc_chol_hook c)
+{
+    g_gemm_hook = g;
+    g_trsm_hook = t;
+    g_chol_hook = c;
+}
+
+/* ------------------------------------------------------------------------------------------------
  * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11):
  * ten rounds of two 64x64->128-bit multiplies with the published multipliers and Weyl key bumps.
  * ---------------------------------------------------------------------------------------------- */
@@ -91,6 +114,11 @@ static inline zc opB(char tb, const zc* B, int ldb, int p, int j)
 void orc_zgemm(char ta, char tb, int m, int n, int k, zc alpha, const zc* A, int lda,
                const zc* B, int ldb, zc beta, zc* C, int ldc)
 {
+    if (g_gemm_hook) {
+        if (m > 0 && n > 0)
+            g_gemm_hook(ta, tb, m, n, k, creal(alpha), cimag(alpha), A, lda, B, ldb, creal(beta), cimag(beta), C, ldc);
+        return;
+    }
     const int RB = 256;
     const int nrb = (m + RB - 1) / RB;
     #pragma omp parallel for collapse(2) schedule(dynamic)
@@ -135,6 +163,7 @@ static double znrm2(int n, const zc* x)
  * ---------------------------------------------------------------------------------------------- */
 int orc_cholesky(int n, const zc* S, int lds, zc* L, int ldl)
 {
+    if (g_chol_hook) return g_chol_hook(n, S, lds, L, ldl);
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i) L[IDX(i, j, ldl)] = 0;
     zc* v = (zc*)malloc(sizeof(zc) * (size_t)n);
@@ -166,6 +195,7 @@ int orc_cholesky(int n, const zc* S, int lds, zc* L, int ldl)
 /* Solve L X = B in place (L lower triangular, B n x nrhs), forward substitution per column. */
 void orc_trsm_lower(int n, int nrhs, const zc* L, int ldl, zc* B, int ldb)
 {
+    if (g_trsm_hook) { g_trsm_hook(0, n, nrhs, L, ldl, B, ldb); return; }
     #pragma omp parallel for schedule(dynamic)
     for (int j = 0; j < nrhs; ++j) {
         zc* x = B + IDX(0, j, ldb);
@@ -181,6 +211,7 @@ void orc_trsm_lower(int n, int nrhs, const zc* L, int ldl, zc* B, int ldb)
 /* Solve L^H X = B in place, back substitution per column. */
 void orc_trsm_lower_h(int n, int nrhs, const zc* L, int ldl, zc* B, int ldb)
 {
+    if (g_trsm_hook) { g_trsm_hook(1, n, nrhs, L, ldl, B, ldb); return; }
     #pragma omp parallel for schedule(dynamic)
     for (int j = 0; j < nrhs; ++j) {
         zc* x = B + IDX(0, j, ldb);
@@ -437,47 +468,63 @@ void orc_bounds(int kk, const double* theta, const double* zw, double beta_k, in
  *   sigma_{k+1} = 1 / (2/sigma_1 - sigma_k),
  *   Y_{k+1} = (2 sigma_{k+1} / e) (H - cI) Y_k - sigma_k sigma_{k+1} Y_{k-1},
  * so that Y_d = T_d((H - cI)/e) Y_0 / T_d((mu1 - c)/e).  Column i stops after deg[i] steps
- * (deg == NULL: every column takes deg_uniform steps); the sigma sequence is shared.
+ * (deg == NULL: every column takes deg_uniform steps); the sigma sequence is shared.  Each step is
+ * one product of H with the block of the columns still filtering.
  * ---------------------------------------------------------------------------------------------- */
 void orc_filter(int n, const zc* H, int ldh, int m, zc* Y, int ldy, const int* deg, int deg_uniform,
                 double a, double b, double mu1)
 {
     const double c = 0.5 * (a + b), e = 0.5 * (b - a);
     const double sigma1 = e / (mu1 - c);
-    #pragma omp parallel for schedule(dynamic)
-    for (int col = 0; col < m; ++col) {
-        int d = deg ? deg[col] : deg_uniform;
-        if (d <= 0) continue;
-        zc* y = Y + IDX(0, col, ldy);
-        zc* prev = (zc*)malloc(sizeof(zc) * (size_t)n);
-        zc* cur = (zc*)malloc(sizeof(zc) * (size_t)n);
-        zc* nxt = (zc*)malloc(sizeof(zc) * (size_t)n);
-        for (int i = 0; i < n; ++i) prev[i] = y[i];
-        /* cur = (sigma1/e) (H prev - c prev) */
-        for (int i = 0; i < n; ++i) cur[i] = -c * prev[i];
-        for (int p = 0; p < n; ++p) {
-            zc x = prev[p];
-            const zc* hp = H + IDX(0, p, ldh);
-            for (int i = 0; i < n; ++i) cur[i] += hp[i] * x;
-        }
-        for (int i = 0; i < n; ++i) cur[i] *= sigma1 / e;
-        double sigma = sigma1;
-        for (int k = 1; k < d; ++k) {
-            double sigma_new = 1.0 / (2.0 / sigma1 - sigma);
-            for (int i = 0; i < n; ++i) nxt[i] = -c * cur[i];
-            for (int p = 0; p < n; ++p) {
-                zc x = cur[p];
-                const zc* hp = H + IDX(0, p, ldh);
-                for (int i = 0; i < n; ++i) nxt[i] += hp[i] * x;
-            }
-            for (int i = 0; i < n; ++i)
-                nxt[i] = (2.0 * sigma_new / e) * nxt[i] - sigma * sigma_new * prev[i];
-            zc* t = prev; prev = cur; cur = nxt; nxt = t;
-            sigma = sigma_new;
-        }
-        for (int i = 0; i < n; ++i) y[i] = cur[i];
-        free(prev); free(cur); free(nxt);
+    int dmax = 0;
+    for (int j = 0; j < m; ++j) {
+        int d = deg ? deg[j] : deg_uniform;
+        if (d > dmax) dmax = d;
     }
+    if (dmax <= 0 || n <= 0) return;
+    const size_t nm = (size_t)n * m;
+    zc* prev = (zc*)malloc(sizeof(zc) * nm);   /* Y_{k-2} */
+    zc* cur = (zc*)malloc(sizeof(zc) * nm);    /* Y_{k-1} */
+    zc* nxt = (zc*)malloc(sizeof(zc) * nm);    /* Y_k */
+    zc* G = (zc*)malloc(sizeof(zc) * nm);      /* the active columns of Y_{k-1} */
+    zc* Z = (zc*)malloc(sizeof(zc) * nm);      /* H times them */
+    int* act = (int*)malloc(sizeof(int) * (size_t)(m > 0 ? m : 1));
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < n; ++i) cur[IDX(i, j, n)] = Y[IDX(i, j, ldy)];
+    double sigma = sigma1;
+    for (int k = 1; k <= dmax; ++k) {
+        /* step k advances the columns whose degree is at least k */
+        int w = 0;
+        for (int j = 0; j < m; ++j)
+            if ((deg ? deg[j] : deg_uniform) >= k) act[w++] = j;
+        for (int q = 0; q < w; ++q)
+            memcpy(G + IDX(0, q, n), cur + IDX(0, act[q], n), sizeof(zc) * (size_t)n);
+        orc_zgemm('N', 'N', n, w, n, 1.0, H, ldh, G, n, 0.0, Z, n);   /* Z = H Y_{k-1} */
+        double alpha, beta, sigma_new;
+        if (k == 1) {            /* Y_1 = (sigma_1 / e) (H - cI) Y_0 */
+            sigma_new = sigma1;
+            alpha = sigma1 / e;
+            beta = 0.0;
+        } else {                 /* Y_k = (2 sigma_k / e)(H - cI) Y_{k-1} - sigma_{k-1} sigma_k Y_{k-2} */
+            sigma_new = 1.0 / (2.0 / sigma1 - sigma);
+            alpha = 2.0 * sigma_new / e;
+            beta = -sigma * sigma_new;
+        }
+        #pragma omp parallel for schedule(static)
+        for (int q = 0; q < w; ++q) {
+            const int j = act[q];
+            for (int i = 0; i < n; ++i) {
+                zc v = alpha * (Z[IDX(i, q, n)] - c * cur[IDX(i, j, n)]);
+                if (k > 1) v += beta * prev[IDX(i, j, n)];
+                nxt[IDX(i, j, n)] = v;
+            }
+            if ((deg ? deg[j] : deg_uniform) == k)   /* the column's last step: Y_d */
+                for (int i = 0; i < n; ++i) Y[IDX(i, j, ldy)] = nxt[IDX(i, j, n)];
+        }
+        sigma = sigma_new;
+        zc* t = prev; prev = cur; cur = nxt; nxt = t;
+    }
+    free(prev); free(cur); free(nxt); free(G); free(Z); free(act);
 }
 
 /* Residual norms r_i = || (HY)_i - theta_i Y_i ||_2. */

@@ -450,3 +450,34 @@ def test_mlp_forward_matches_numpy_layout(orc):
     Pt = P.copy()
     Pt[:320] = W1.T.reshape(-1)
     assert np.max(np.abs(_mlp_forward_numpy(Pt, X) - ref)) > 1e-3
+
+
+def test_library_primitives_give_the_plain_results(orc):
+    # routing the dense product, triangular solves and Cholesky factor to numpy / LAPACK (used for
+    # the order-8192 reference values) must not change what the reference computes
+    spec = synth.SequenceSpec(n=160, n_low=8, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=6,
+                              nev=10, nex=6)
+    p = synth.designed_pencil(spec)
+    A = p.A + 1e-2 * synth.hermitian_noise(np.random.default_rng(4), 160)
+    A = 0.5 * (A + A.conj().T)
+    Y0 = cgauss(160, 7)
+    plain = orc.solve(A, p.S, nev=10, nex=6, deg=11, tol=1e-10, seed=3)
+    fplain = orc.cheb_filter(A, Y0, -0.2, 1.3, -1.1, deg=[5, 0, 9, 1, 9, 3, 2])
+    L0, _ = orc.cholesky(p.S)
+    orc.use_library_products(True)
+    try:
+        lib = orc.solve(A, p.S, nev=10, nex=6, deg=11, tol=1e-10, seed=3)
+        flib = orc.cheb_filter(A, Y0, -0.2, 1.3, -1.1, deg=[5, 0, 9, 1, 9, 3, 2])
+        L1, st = orc.cholesky(p.S)
+        B = cgauss(160, 5)
+        X1 = orc.trsm_lower(L1, B)
+        X2 = orc.trsm_lower(L1, B, conj_trans=True)
+        G = orc.zgemm("C", "N", B, Y0, alpha=0.5 - 2j, beta=0.0)
+    finally:
+        orc.use_library_products(False)
+    assert st == 0 and np.allclose(L1, L0, atol=1e-14)
+    assert np.allclose(X1, orc.trsm_lower(L0, B), atol=1e-12) and np.allclose(X2, orc.trsm_lower(L0, B, True), atol=1e-12)
+    assert np.allclose(G, (0.5 - 2j) * (B.conj().T @ Y0), atol=1e-12)
+    assert np.max(np.abs(flib - fplain)) <= 1e-12 * np.abs(fplain).max()
+    assert plain.status == 0 and lib.status == 0 and plain.stats["loops"] == lib.stats["loops"]
+    assert np.max(np.abs(lib.lam[:10] - plain.lam[:10])) <= 1e-13
