@@ -1,31 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark: Chebyshev-filtered subspace iteration on one MI355X.
 
-Workload (default, ``seq2048``): the 10-cycle sequence of correlated generalized problems,
-complex128, n = 2048, S = I + G G^H / n, A_0 in designed form with the lowest 5 % of the spectrum
-clustered, A_{l+1} = A_l + 1e-2 0.5^l (E + E^H)/2, nev = 128, nex = 64, degree 12, FP64.
+Workload (default, ``seq8192``): the 5-cycle sequence of correlated generalized problems,
+complex128, n = 8192, S = I + G G^H / n, A_0 in designed form with 1/8 of the spectrum clustered in
+[-1, -0.5], A_{l+1} = A_l + 5e-3 0.6^l (E + E^H)/2, nev = 400, nex = 80, FP64 filter of degree 12.
+``seq2048`` is the 10-cycle n = 2048 sequence (nev 128, nex 64, eps_l = 1e-2 0.5^l).
 
 A step is one warm-started solve of one cycle (reduction, Lanczos, filter/QR/Rayleigh-Ritz/locking
-loop, back-transform and verification), with the inputs resident in HBM.  Before the timed
-region the whole sequence is solved once (cycle 0 from a random block, each later cycle from the
-previous solution); timed step s re-solves cycle 1 + (s mod 9) from the stored solution of the
+loop, back-transform and verification), with the inputs resident in HBM.  Before the timed region
+the whole sequence is solved once (cycle 0 from a random block, each later cycle from the previous
+solution); timed step s re-solves cycle 1 + (s mod (cycles - 1)) from the stored solution of the
 cycle before it.
 
 Printed JSON (one line): value = filter TFLOP/s over the timed steps (8 n^2 flops per filtered
 vector and degree, divided by the filter phase time), ms_per_step = time to solution per cycle,
-roofline of the dominant kernel (the FP64 filter step) from hipEvents around each of its launches
-(achieved and frac in the standard complex count of 8 flops per multiply-add; mfma_frac in the 6
-flops the three-product kernel executes), and the CPU reference timed on a bounded sample.  Extra fields: random-start times and the
-warm/random speed-up per cycle, the mixed-precision filter variants on the same cycles, and the
-other workloads: the batched k-point cycle (32 problems, sequential vs one batch), the learned
-per-vector degree against fixed degrees (n = 4096 sequence) and the mixed-precision filters at
-n = 8192 with per-eigenvalue errors against FP64.
+the roofline of the dominant kernel (the FP64 filter step) from the dispatches' own timestamps
+(the main kernel alone and the whole step with its split-K reduction), and the CPU reference timed
+on a bounded sample.  Extras: the n = 8192 sequence at degrees 8/12/16/20 with the FP64, FP32,
+BF16x3 and BF16x6 filters and their per-eigenpair errors against the CPU reference's eigenvalues
+(tests/golden/c3_oracle_eigenvalues.json), the n = 2048 sequence (warm vs random start, mixed
+precision), the batched k-point cycle (32 problems, sequential vs one batch) and the learned
+per-vector degree against fixed degrees and the analytic rule (20-cycle n = 4096 sequence).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import statistics
 import sys
 import time
@@ -37,15 +39,40 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # TFLOP/s, MI355X dense matrix peaks
 HBM_PEAK_GBS = 8000.0
+GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "c3_oracle_eigenvalues.json")
+WORKLOADS = {
+    "seq8192": "seq8192: 5-cycle correlated generalized sequence, complex128, n=8192, nev=400, nex=80, "
+               "degree 12, warm start, FP64 filter",
+    "seq2048": "seq2048: 10-cycle correlated generalized sequence, complex128, n=2048, nev=128, nex=64, "
+               "degree 12, warm start, FP64 filter",
+}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def spec_of(workload: str):
+    from paper_1206_3768_amd import synth
+    if workload == "seq8192":
+        return synth.config_mixed_precision()
+    return synth.config_generalized_sequence()
+
+
 def load_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source (else None)."""
+    """The committed rocprofv3 counter summary of `kernel` on this workload, if it was taken on the
+    current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", f"filter_f64_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -54,39 +81,199 @@ def load_traffic(workload: str, kernel: str):
     from paper_1206_3768_amd.traffic import kernel_source_hash
     if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("kernel") != kernel:
         return None
-    return t.get("bytes_per_launch")
+    return t
 
 
-def cpu_baseline(seq_spec, pencils_host, x_prev, lam_prev) -> dict:
-    """The CPU reference as it stands, on a bounded sample of the same workload: one filter of the
-    full n x m block at the workload's degree (gives the TFLOP/s figure) and one warm-started solve
-    of cycle 1 (time to solution)."""
+def golden_c3():
+    """Eigenvalues of the n = 8192 sequence computed by the CPU reference (dict cycle -> array)."""
+    if not os.path.exists(GOLDEN_C3):
+        return {}
+    with open(GOLDEN_C3) as fh:
+        g = json.load(fh)
+    return {c["cycle"]: np.array([float(v) for v in c["lam"]]) for c in g["cycles"]}
+
+
+def pair_errors(lam, ref):
+    """Per-eigenpair relative errors |lam_i - ref_i| / max(|ref_i|, 1e-3) and their summary."""
+    e = np.abs(lam[:len(ref)] - ref) / np.maximum(np.abs(ref), 1e-3)
+    hist = {}
+    for lo in range(-17, -9):
+        hist[f"1e{lo}"] = int(np.sum((e >= 10.0 ** lo) & (e < 10.0 ** (lo + 1))))
+    hist["below_1e-17"] = int(np.sum(e < 1e-17))
+    hist["above_1e-10"] = int(np.sum(e >= 1e-10))
+    return e, {"max": float(e.max()), "median": float(np.median(e)), "argmax": int(np.argmax(e)), "decades": hist}
+
+
+def cpu_baseline(workload: str, seq_spec, A_host) -> dict:
+    """The CPU reference as it stands (plain loops, all host threads) on a bounded sample of the
+    workload: one filter of the first `cols` columns of the block at the workload's degree with the
+    workload's H = A_1 of the sequence."""
     import oracle
-    n, m, d = seq_spec.n, seq_spec.nev + seq_spec.nex, seq_spec.deg
+    n, d = seq_spec.n, seq_spec.deg
+    cols = 8 if n > 4096 else seq_spec.nev + seq_spec.nex
     rng = np.random.default_rng(0)
-    Y = (rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))) / np.sqrt(2)
-    H = pencils_host[0].A
+    Y = (rng.standard_normal((n, cols)) + 1j * rng.standard_normal((n, cols))) / np.sqrt(2)
     t0 = time.perf_counter()
-    oracle.cheb_filter(H, Y, -0.3, 1.5, -1.0, deg=d)
+    oracle.cheb_filter(A_host, Y, -0.3, 1.5, -1.0, deg=d)
     tf = time.perf_counter() - t0
-    flops = 8.0 * n * n * m * d
-    pen = pencils_host[1]
+    flops = 8.0 * n * n * cols * d
+    return {"value": round(flops / tf / 1e12, 5), "unit": "TFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{workload}: oracle filter (plain loops, FP64) of a {n} x {cols} block at degree {d} with "
+                      f"the sequence's A_1 ({tf:.2f} s, {flops / 1e9:.1f} GFLOP)", "seconds": round(tf, 2)}
+
+
+def roofline(rows: np.ndarray, workload: str) -> dict:
+    """Dominant filter kernel (the (precision, tile, split mode) group with the largest summed
+    main-kernel time): algorithmic flops per launch over its average dispatch duration, alone and with
+    its split-K reduction; HBM traffic from the committed counter summary when it matches the sources."""
+    groups = {}
+    for nn, w, pr, bm, bn, ks, mode, t_main, t_step in rows:
+        key = (int(pr), int(bm), int(bn), int(mode))   # one kernel symbol per (tile, split mode)
+        g = groups.setdefault(key, [0.0, 0.0, 0.0, 0, 0.0, 0.0])
+        g[0] += 8.0 * nn * nn * w
+        g[1] += t_main * 1e-3
+        g[2] += t_step * 1e-3
+        g[3] += 1
+        g[4] += 16.0 * nn * nn + 3.0 * 16.0 * nn * w      # algorithmic bytes: H, Y_k, Y_{k-1} read, Y_{k+1} written
+        g[5] = nn
+    key, (g_flops, g_time, g_step, g_count, g_bytes, g_n) = max(groups.items(), key=lambda kv: kv[1][1])
+    achieved = g_flops / g_time / 1e12
+    achieved_step = g_flops / g_step / 1e12
+    kernel = f"k_zgemm<double, 0, 0, 1, {key[1]}, {key[2]}, {key[3]}>"
+    tr = load_traffic(workload, kernel)
+    alg_bytes = g_bytes / g_count
+    out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
+           "frac": round(achieved / PEAK["f64"], 4),
+           "traffic": tr["bytes_per_launch"] if tr else None,
+           "kernel": kernel, "flops_per_launch": g_flops / g_count, "avg_launch_ms": g_time / g_count * 1e3,
+           "launches": g_count,
+           # the whole filter step: the main kernel and, for a split-K plan, the kernel summing its
+           # partial tiles and applying the recurrence
+           "step_achieved": round(achieved_step, 3), "step_frac": round(achieved_step / PEAK["f64"], 4),
+           "avg_step_ms": g_step / g_count * 1e3,
+           # the three-product complex MFMA executes 6 of the 8 counted flops per complex multiply-add
+           "mfma_frac": round(0.75 * achieved / PEAK["f64"], 4),
+           "algorithmic_bytes_per_launch": alg_bytes,
+           "all_filter_launches": {"count": int(len(rows)),
+                                   "tflops": round(float(np.sum(8.0 * rows[:, 0] ** 2 * rows[:, 1]) /
+                                                         np.sum(rows[:, 7] * 1e-3) / 1e12), 3),
+                                   "tflops_with_reduce": round(float(np.sum(8.0 * rows[:, 0] ** 2 * rows[:, 1]) /
+                                                                     np.sum(rows[:, 8] * 1e-3) / 1e12), 3)}}
+    if tr:
+        out["traffic_over_algorithmic"] = round(tr["bytes_per_launch"] / alg_bytes, 3)
+        out["traffic_source"] = f"profiles/filter_f64_{workload}_traffic.json"
+    return out
+
+
+def timed_sequence(seq, spec, steps: int, warmup: int):
+    """Warm-started FP64 solves of cycles 1 .. cycles-1 in turn; returns results and launch logs."""
+    import torch
+    cycles = [1 + (s % (spec.cycles - 1)) for s in range(warmup + steps)]
+    work = seq.new_block()
+    for c in cycles[:warmup]:
+        seq.solve(c, warm=True, X=work)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = oracle.solve(pen.A, pen.S, nev=seq_spec.nev, nex=seq_spec.nex, deg=d, tol=1e-10, X0=x_prev,
-                     bounds=(lam_prev[0], lam_prev[-1]), seed=seq_spec.seed)
-    ts = time.perf_counter() - t0
-    return {"value": flops / tf / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"oracle filter of one {n}x{m} block at degree {d} ({tf:.2f} s) and one warm-started "
-                      f"solve of cycle 1 ({ts:.2f} s, {r.stats['loops']} loops, status {r.status})",
-            "time_to_solution_ms": ts * 1e3, "filter_s": tf}
+    timed, launch_rows = [], []
+    for c in cycles[warmup:]:
+        timed.append(seq.solve(c, warm=True, X=work))
+        launch_rows.append(seq.h.filter_launch_log())   # host-side copy of this solve's event log
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rows = np.concatenate(launch_rows) if launch_rows else np.zeros((0, 9))
+    return timed, rows, wall, work
+
+
+def phase_summary(timed) -> dict:
+    phase = {k: round(sum(r.stats[k] for r in timed) / len(timed), 3)
+             for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid", "t_lock", "t_back", "t_total")}
+    return phase
+
+
+def bench_c3_sweep(seq, spec, golden) -> dict:
+    """The n = 8192 sequence at degrees 8, 12, 16, 20 with every filter precision: warm cycles
+    1..cycles-1, time to solution, loops, matrix-vector products, precision switches, and the
+    per-eigenpair error of every converged eigenvalue against the CPU reference."""
+    out = {"workload": f"n={spec.n} generalized sequence, nev {spec.nev}, nex {spec.nex}, warm cycles 1..{spec.cycles - 1}",
+           "reference": "tests/golden/c3_oracle_eigenvalues.json (CPU oracle, FP64)" if golden else None}
+    work = seq.new_block()
+    for d in (8, 12, 16, 20):
+        base = None
+        for name in ("fp64", "fp32", "bf16x3", "bf16x6"):
+            seq.solve(1, warm=True, X=work, filter_precision=name, deg=d)   # untimed: workspace, H copies
+            rs = [seq.solve(c, warm=True, X=work, filter_precision=name, deg=d) for c in range(1, spec.cycles)]
+            tot = sum(r.wall_ms for r in rs)
+            if name == "fp64":
+                base = tot
+            rec = {"all_converged": all(r.status == 0 for r in rs), "time_to_solution_ms": round(tot, 1),
+                   "speedup_vs_fp64": round(base / tot, 3) if base else None,
+                   "filter_ms": round(sum(r.stats["t_filter"] for r in rs), 1),
+                   "matvecs": sum(r.stats["matvecs"] for r in rs), "loops": [r.stats["loops"] for r in rs],
+                   "precision_switches": [r.stats["precision_switches"] for r in rs],
+                   "max_resid": float(max(r.resid[:spec.nev].max() for r in rs))}
+            if golden:
+                per = {}
+                for r in rs:
+                    if r.status == 0 and r.cycle in golden:
+                        _, summ = pair_errors(r.lam, golden[r.cycle])
+                        per[str(r.cycle)] = summ
+                rec["rel_eig_err_vs_oracle"] = per
+            out[f"d{d}_{name}"] = rec
+            log(f"c3 degree {d} {name}: {rec['time_to_solution_ms']} ms, loops {rec['loops']}")
+    return out
+
+
+def bench_seq2048(h, steps: int = 9) -> dict:
+    """The n = 2048 sequence: timed warm solves, the dominant kernel, warm vs random start, the
+    low-precision filters and the analytic degree on the same cycles, phase times."""
+    from paper_1206_3768_amd import sequence
+    spec = spec_of("seq2048")
+    seq = sequence.Sequence(spec, handle=h)
+    ref = seq.run_reference()
+    if any(r.status != 0 for r in ref):
+        return {"failed": "reference pass"}
+    timed, rows, wall, work = timed_sequence(seq, spec, steps, 1)
+    flops = sum(r.stats["filter_flops"] for r in timed)
+    t_filter = sum(r.stats["t_filter"] for r in timed) * 1e-3
+    out = {"workload": WORKLOADS["seq2048"], "filter_tflops": round(flops / t_filter / 1e12, 3),
+           "ms_per_step": round(wall / len(timed) * 1e3, 3), "roofline": roofline(rows, "seq2048")}
+    warm_ms = {}
+    for r in timed:
+        warm_ms.setdefault(r.cycle, r.wall_ms)
+    rnd = {c: seq.solve(c, warm=False, X=work) for c in range(1, spec.cycles)}
+    out["warm_vs_random"] = {
+        str(c): {"t_app_ms": round(warm_ms.get(c, float("nan")), 3), "t_rnd_ms": round(rnd[c].wall_ms, 3),
+                 "speedup": round(rnd[c].wall_ms / warm_ms[c], 3) if c in warm_ms else None,
+                 "loops_app": next((r.stats["loops"] for r in timed if r.cycle == c), None),
+                 "loops_rnd": rnd[c].stats["loops"]} for c in range(1, spec.cycles)}
+    mixed = {}
+    for name in ("fp32", "bf16x6", "bf16x3"):
+        rs = [seq.solve(c, warm=True, X=work, filter_precision=name) for c in range(1, spec.cycles)]
+        mixed[name] = {"all_converged": all(r.status == 0 for r in rs),
+                       "time_to_solution_ms_total": round(sum(r.wall_ms for r in rs), 3),
+                       "fp64_total_ms": round(sum(warm_ms.get(r.cycle, float("nan")) for r in rs), 3),
+                       "max_resid": float(max(r.resid[:spec.nev].max() for r in rs)),
+                       "loops": [r.stats["loops"] for r in rs],
+                       "precision_switches": [r.stats["precision_switches"] for r in rs]}
+    out["mixed_precision"] = mixed
+    an = [seq.solve(c, warm=True, X=work, degree_policy=1) for c in range(1, spec.cycles)]
+    out["analytic_degree"] = {"time_to_solution_ms_total": round(sum(r.wall_ms for r in an), 3),
+                              "all_converged": all(r.status == 0 for r in an),
+                              "matvecs": [r.stats["matvecs"] for r in an]}
+    phase = phase_summary(timed)
+    out["phase_ms_per_solve"] = phase
+    out["solve_only_ms_per_solve"] = round(sum(phase[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr",
+                                                                   "t_resid", "t_lock")), 3)
+    return out
 
 
 def bench_kpoints(h, count: int = 32) -> dict:
     """Batched SCF cycle: `count` k-point problems (n uniform in [1500, 6000], nev = ceil(0.06 n),
     nex = ceil(0.2 nev), warm start from the unperturbed eigenvectors, perturbation 1e-3), solved
     one after another with chfsi_solve and as one batch with chfsi_solve_batched (persistent
-    filter launch with the autotuned tile, graph replay and without it, the dense steps of the
-    problems spread over three streams with a host thread each)."""
+    filter launch with the autotuned tile, graph replay and without it, the per-problem phases
+    spread over three streams with a host thread each)."""
     import torch
     from paper_1206_3768_amd import chfsi, synth
     t0 = time.perf_counter()
@@ -106,10 +293,9 @@ def bench_kpoints(h, count: int = 32) -> dict:
         torch.cuda.synchronize()
 
     seq_ms, seq_lam, seq_loops, seq_flops, seq_filter_ms, seq_phase_ms = 0.0, [], [], 0.0, 0.0, 0.0
-    for p in probs:   # warm-up of the sequential path on the first problem
-        reset()
-        h.solve(p["A"], p["S"], p["X"], True, chfsi.default_params(nev=p["nev"], nex=p["nex"], deg=12, tol=1e-10))
-        break
+    reset()
+    p = probs[0]   # warm-up of the sequential path on the first problem
+    h.solve(p["A"], p["S"], p["X"], True, chfsi.default_params(nev=p["nev"], nex=p["nex"], deg=12, tol=1e-10))
     reset()
     for p in probs:
         prm = chfsi.default_params(nev=p["nev"], nex=p["nex"], deg=12, tol=1e-10)
@@ -128,135 +314,106 @@ def bench_kpoints(h, count: int = 32) -> dict:
     plan, plan_ms = h.autotune_batched(probs)
     out = {"count": count, "n_range": [min(sizes), max(sizes)], "sequential_ms": round(seq_ms, 1),
            "sequential_filter_tflops": round(seq_flops / seq_filter_ms / 1e9, 2),
-           # the whole filter phase (main kernels, split-K reductions, copies), as the batched
-           # filter_tflops below is measured
            "sequential_filter_phase_tflops": round(seq_flops / seq_phase_ms / 1e9, 2),
            "autotuned_tile": list(plan), "autotune_step_ms": round(plan_ms, 3)}
     prm = chfsi.default_params(nev=1, nex=0, deg=12, tol=1e-10)
-    lanes = 3   # streams (host threads) for the per-problem dense steps
-    out["lanes"] = lanes
-    for use_graph in (True, False):
-        h.set_batched_plan(*plan, use_graph=use_graph, lanes=lanes)
-        best = None
-        for _ in range(2):
-            reset()
-            t = time.perf_counter()
-            st, res = h.solve_batched(probs, prm)
-            ms = (time.perf_counter() - t) * 1e3
-            if st != 0:
-                raise RuntimeError(f"batched k-point solve failed: status {st}")
-            best = ms if best is None else min(best, ms)
-        info = h.batched_info()
-        dl = max(float(np.max(np.abs(r.lam[:p["nev"]] - l) / np.maximum(np.abs(l), 1e-3)))
-                 for r, p, l in zip(res, probs, seq_lam))
-        out["graph" if use_graph else "no_graph"] = {
-            "batched_ms": round(best, 1), "speedup_vs_sequential": round(seq_ms / best, 3),
-            "filter_ms": round(info["filter_ms"], 1),
-            "filter_tflops": round(info["filter_flops"] / info["filter_ms"] / 1e9, 2),
-            "graph_replays": info["graph_launches"], "persistent_launches": info["kernel_launches"],
-            "max_rel_eig_diff_vs_sequential": dl,
-            "max_resid": max(float(r.resid[:p["nev"]].max()) for r, p in zip(res, probs)),
-            "loops_equal_to_sequential": [r.stats["loops"] for r in res] == seq_loops}
-    h.set_batched_plan(64, 64, use_graph=True)
+    for lanes in (3, 1):
+        for use_graph in ((True, False) if lanes == 3 else (True,)):
+            h.set_batched_plan(*plan, use_graph=use_graph, lanes=lanes)
+            best = None
+            for _ in range(2):
+                reset()
+                t = time.perf_counter()
+                st, res = h.solve_batched(probs, prm)
+                ms = (time.perf_counter() - t) * 1e3
+                if st != 0:
+                    raise RuntimeError(f"batched k-point solve failed: status {st}")
+                best = ms if best is None else min(best, ms)
+            info = h.batched_info()
+            dl = max(float(np.max(np.abs(r.lam[:p["nev"]] - l) / np.maximum(np.abs(l), 1e-3)))
+                     for r, p, l in zip(res, probs, seq_lam))
+            key = ("graph" if use_graph else "no_graph") + ("" if lanes == 3 else "_one_lane")
+            out[key] = {
+                "lanes": lanes, "batched_ms": round(best, 1), "speedup_vs_sequential": round(seq_ms / best, 3),
+                "filter_ms": round(info["filter_ms"], 1),
+                "filter_tflops": round(info["filter_flops"] / info["filter_ms"] / 1e9, 2),
+                "graph_replays": info["graph_launches"], "persistent_launches": info["kernel_launches"],
+                "max_rel_eig_diff_vs_sequential": dl,
+                "max_resid": max(float(r.resid[:p["nev"]].max()) for r, p in zip(res, probs)),
+                "loops_equal_to_sequential": [r.stats["loops"] for r in res] == seq_loops}
+    h.set_batched_plan(64, 64, use_graph=True, lanes=3)
     return out
 
 
-def bench_learned_degree(h, cycles: int = 10) -> dict:
-    """Learned per-vector degree against every fixed degree and the analytic rule on the held-out
-    seed 0 of the n = 4096 standard sequence (warm cycles 1 .. cycles-1), FP64 and FP32 filters."""
+def bench_learned_degree(h, cycles: int = 20) -> dict:
+    """Learned per-vector degree against every fixed degree and the analytic rule (same margin) on
+    the held-out seed 0 of the n = 4096 standard sequence (warm cycles 1 .. cycles-1), FP64 and FP32
+    filters."""
     from paper_1206_3768_amd import chfsi, degree_model, sequence, synth
     blob = degree_model.load()
     if blob is None:
         return {"skipped": "no trained network"}
     h.set_degree_model(blob)
     seq = sequence.Sequence(synth.config_learned_degree(seed=0, n=4096, cycles=cycles), handle=h)
+    margin = degree_model.LEARNED_MARGIN
     res = {}
-    for d in (12, 16, 20, 25):
+    for d in (8, 12, 16, 20, 25):
         res[f"fixed{d}"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=d)
-    res["analytic+2"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=2)
+    res["analytic"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=0)
+    res[f"analytic+{margin}"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=margin)
     res["learned"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED)
     for d in (16, 20, 25):
         res[f"fixed{d}_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=d, precision=chfsi.FP32)
+    res[f"analytic+{margin}_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=margin,
+                                                             precision=chfsi.FP32)
     res["learned_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED, precision=chfsi.FP32)
     h.set_degree_model(None)
     out = {k: {"time_to_solution_ms": round(v["ms"], 1), "matvecs": v["matvecs"], "loops": v["loops"],
                "filter_ms": round(v["filter_ms"], 1), "all_converged": v["ok"], "max_resid": v["max_resid"]}
            for k, v in res.items()}
-    best = min((k for k in res if k.startswith("fixed") and not k.endswith("fp32")), key=lambda k: res[k]["ms"])
+    fixed64 = [k for k in res if k.startswith("fixed") and not k.endswith("fp32")]
+    best = min(fixed64, key=lambda k: res[k]["ms"])
+    best32 = min((k for k in res if k.startswith("fixed") and k.endswith("fp32")), key=lambda k: res[k]["ms"])
+    an = f"analytic+{margin}"
+    out["margin"] = margin
     out["best_fixed"] = best
     out["learned_vs_best_fixed_time"] = round(res[best]["ms"] / res["learned"]["ms"], 3)
-    out["learned_fp32_vs_best_fixed_time"] = round(res[best]["ms"] / res["learned_fp32"]["ms"], 3)
     out["learned_vs_best_fixed_matvecs"] = round(res[best]["matvecs"] / res["learned"]["matvecs"], 3)
-    best32 = min((k for k in res if k.startswith("fixed") and k.endswith("fp32")), key=lambda k: res[k]["ms"])
+    out["learned_vs_analytic_time"] = round(res[an]["ms"] / res["learned"]["ms"], 3)
+    out["learned_vs_analytic_matvecs"] = round(res[an]["matvecs"] / res["learned"]["matvecs"], 3)
     out["best_fixed_fp32"] = best32
+    out["learned_fp32_vs_best_fixed_fp64_time"] = round(res[best]["ms"] / res["learned_fp32"]["ms"], 3)
     out["learned_fp32_vs_best_fixed_fp32_time"] = round(res[best32]["ms"] / res["learned_fp32"]["ms"], 3)
+    out["learned_fp32_vs_analytic_fp32_time"] = round(res[an + "_fp32"]["ms"] / res["learned_fp32"]["ms"], 3)
     out["workload"] = f"n=4096 standard sequence, seed 0, warm cycles 1..{cycles - 1}, nev 256, nex 64"
-    return out
-
-
-def bench_mixed_precision(h, cycles: int = 5) -> dict:
-    """Mixed-precision filters on the n = 8192 generalized sequence (nev 400, nex 80, degree 12):
-    time to solution per warm cycle and the largest error of every eigenvalue against FP64."""
-    from paper_1206_3768_amd import chfsi, sequence, synth
-    spec = synth.config_mixed_precision(cycles=cycles)
-    seq = sequence.Sequence(spec, handle=h)
-    ref = seq.run_reference()
-    if any(r.status != 0 for r in ref):
-        return {"failed": "reference pass"}
-    work = seq.new_block()
-    out = {"workload": f"n={spec.n} generalized sequence, nev {spec.nev}, nex {spec.nex}, degree {spec.deg}, "
-                       f"warm cycles 1..{cycles - 1}"}
-    base = None
-    for name in ("fp64", "fp32", "bf16x6", "bf16x3"):
-        rs = [seq.solve(c, warm=True, X=work, filter_precision=name) for c in range(1, cycles)]
-        rs = [seq.solve(c, warm=True, X=work, filter_precision=name) for c in range(1, cycles)]   # second pass timed
-        errs = [np.abs(r.lam[:spec.nev] - seq.lam[r.cycle][:spec.nev]) / np.maximum(np.abs(seq.lam[r.cycle][:spec.nev]), 1e-3)
-                for r in rs if r.status == 0]
-        tot = sum(r.wall_ms for r in rs)
-        if name == "fp64":
-            base = tot
-        out[name] = {"all_converged": all(r.status == 0 for r in rs), "time_to_solution_ms": round(tot, 1),
-                     "speedup_vs_fp64": round(base / tot, 3) if base else None,
-                     "filter_ms": round(sum(r.stats["t_filter"] for r in rs), 1),
-                     "matvecs": sum(r.stats["matvecs"] for r in rs),
-                     "loops": [r.stats["loops"] for r in rs],
-                     "max_rel_eig_err_vs_fp64_per_cycle": [float(e.max()) for e in errs],
-                     "median_rel_eig_err_vs_fp64": float(np.median(np.concatenate(errs))) if errs else None,
-                     "max_resid": float(max(r.resid[:spec.nev].max() for r in rs))}
     return out
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=9)
+    ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="seq2048", choices=["seq2048"])
+    ap.add_argument("--workload", default="seq8192", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the random-start and mixed-precision runs")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed headline solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported: the solver drives "
               "one GPU and has no multi-GPU path", file=sys.stderr)
         return 2
     import torch
-    from paper_1206_3768_amd import chfsi, sequence, synth
+    from paper_1206_3768_amd import chfsi, sequence
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
-    spec = synth.config_generalized_sequence()
-    n, m = spec.n, spec.nev + spec.nex
+    spec = spec_of(args.workload)
+    n = spec.n
     log(f"generating {spec.cycles} cycles, n={n}, nev={spec.nev}, nex={spec.nex}")
     t0 = time.perf_counter()
-    seq = sequence.Sequence(spec, keep_host=not args.no_cpu_baseline)
-    log(f"inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
-
-    # filter-step tile plans: the table written by the project autotuner (paper_1206_3768_amd/autotune.py)
-    from paper_1206_3768_amd import autotune
-    tuned = {f"{'fp64' if e['prec'] == 0 else 'fp32'}/{e['m']}": e["plan"]
-             for e in json.load(open(autotune.TABLE))["plans"] if e["n"] == n} if seq.tuned_entries else {}
-    log(f"{seq.tuned_entries} tuned plans loaded; n={n}: " + json.dumps(tuned))
+    seq = sequence.Sequence(spec, keep_host=False)
+    log(f"inputs resident in HBM ({time.perf_counter() - t0:.1f} s); {seq.tuned_entries} tuned plans loaded")
 
     ref = seq.run_reference()
     bad = [r.cycle for r in ref if r.status != 0]
@@ -265,19 +422,7 @@ def main() -> int:
         return 1
     log("reference pass: loops per cycle " + " ".join(str(r.stats["loops"]) for r in ref))
 
-    cycles = [1 + (s % (spec.cycles - 1)) for s in range(args.warmup + args.steps)]
-    work = seq.new_block()
-    for c in cycles[:args.warmup]:
-        seq.solve(c, warm=True, X=work)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    timed, launch_rows = [], []
-    for c in cycles[args.warmup:]:
-        timed.append(seq.solve(c, warm=True, X=work))
-        launch_rows.append(seq.h.filter_launch_log())   # host-side copy of this solve's event log
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    rows = np.concatenate(launch_rows) if launch_rows else np.zeros((0, 9))
+    timed, rows, wall, work = timed_sequence(seq, spec, args.steps, args.warmup)
     for r in timed:
         if r.status != 0 or r.resid[:spec.nev].max() > 1e-10:
             log(f"timed solve of cycle {r.cycle} failed: status {r.status}, max resid {r.resid[:spec.nev].max():.2e}")
@@ -285,19 +430,10 @@ def main() -> int:
     flops = sum(r.stats["filter_flops"] for r in timed)
     t_filter = sum(r.stats["t_filter"] for r in timed) * 1e-3
     value = flops / t_filter / 1e12
-    # dominant filter kernel: the (precision, tile plan) group with the largest summed launch time
-    groups = {}
-    for nn, w, pr, bm, bn, ks, mode, t_main, t_step in rows:
-        key = (int(pr), int(bm), int(bn), int(mode))   # one kernel symbol per (tile, split mode)
-        g = groups.setdefault(key, [0.0, 0.0, 0])
-        g[0] += 8.0 * nn * nn * w
-        g[1] += t_main * 1e-3
-        g[2] += 1
-    key, (g_flops, g_time, g_count) = max(groups.items(), key=lambda kv: kv[1][1])
-    achieved = g_flops / g_time / 1e12
-    kernel = f"k_zgemm<double, 0, 0, 1, {key[1]}, {key[2]}, {key[3]}>"
+    rl = roofline(rows, args.workload)
     log(f"timed {args.steps} warm solves: {wall / args.steps * 1e3:.2f} ms/solve, filter phase {value:.2f} TFLOP/s; "
-        f"dominant kernel {kernel}: {g_count} launches, {achieved:.2f} TFLOP/s")
+        f"dominant kernel {rl['kernel']}: {rl['launches']} launches, {rl['achieved']:.2f} TFLOP/s "
+        f"({rl['step_achieved']:.2f} with its reduction)")
 
     out = {
         "metric": "Filter TFLOP/s + time-to-solution @res<=1e-10, mixed/learned vs FP64",
@@ -312,78 +448,42 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "seq2048: 10-cycle correlated generalized sequence, complex128, n=2048, "
-                               "nev=128, nex=64, degree 12, warm start, FP64",
-                   "n": n, "nev": spec.nev, "nex": spec.nex, "deg": spec.deg, "cycles": spec.cycles},
+        "config": {"workload": WORKLOADS[args.workload], "n": n, "nev": spec.nev, "nex": spec.nex, "deg": spec.deg,
+                   "cycles": spec.cycles},
         "time_to_solution_ms": {"median": round(statistics.median(r.wall_ms for r in timed), 3),
                                 "per_cycle": {str(r.cycle): round(r.wall_ms, 3) for r in timed}},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK["f64"], 4), "traffic": load_traffic(args.workload, kernel),
-                     "kernel": kernel, "flops_per_launch": g_flops / g_count,
-                     # the kernel forms each complex product from three real MFMA products (Gauss), so
-                     # the MFMA pipes execute 6 of the 8 counted flops per complex multiply-add
-                     "mfma_flops_per_launch": 0.75 * g_flops / g_count,
-                     "mfma_frac": round(0.75 * achieved / PEAK["f64"], 4),
-                     "avg_launch_ms": g_time / g_count * 1e3, "launches": g_count,
-                     "all_filter_launches": {"count": int(len(rows)),
-                                             "tflops": round(float(np.sum(8.0 * rows[:, 0] ** 2 * rows[:, 1]) /
-                                                                   np.sum(rows[:, 7] * 1e-3) / 1e12), 3)}},
-        "tuned_plans": tuned,
+        "roofline": rl,
+        "phase_ms_per_solve": phase_summary(timed),
+        "loops_per_cycle": {str(r.cycle): r.stats["loops"] for r in ref},
     }
+    golden = golden_c3() if args.workload == "seq8192" else {}
+    if golden:
+        errs = {}
+        for r in ref:
+            if r.cycle in golden:
+                _, errs[str(r.cycle)] = pair_errors(r.lam, golden[r.cycle])
+        out["rel_eig_err_vs_oracle_fp64"] = errs
 
     if not args.no_extras:
-        # E4 protocol: random start vs warm start per cycle
-        rnd = {}
-        for c in range(1, spec.cycles):
-            r = seq.solve(c, warm=False, X=work)
-            rnd[c] = r
-        warm_ms = {}
-        for r in timed:
-            warm_ms.setdefault(r.cycle, r.wall_ms)
-        out["warm_vs_random"] = {
-            str(c): {"t_app_ms": round(warm_ms.get(c, float("nan")), 3), "t_rnd_ms": round(rnd[c].wall_ms, 3),
-                     "speedup": round(rnd[c].wall_ms / warm_ms[c], 3) if c in warm_ms else None,
-                     "loops_app": next((r.stats["loops"] for r in timed if r.cycle == c), None),
-                     "loops_rnd": rnd[c].stats["loops"]} for c in range(1, spec.cycles)}
-        # mixed-precision filters on the same warm-started cycles
-        mixed = {}
-        for name in ("fp32", "bf16x6", "bf16x3"):
-            rs = [seq.solve(c, warm=True, X=work, filter_precision=name) for c in range(1, spec.cycles)]
-            ok = all(r.status == 0 for r in rs)
-            errs = [float(np.max(np.abs(r.lam[:spec.nev] - seq.lam[r.cycle][:spec.nev]) /
-                                 np.maximum(np.abs(seq.lam[r.cycle][:spec.nev]), 1e-3))) for r in rs if r.status == 0]
-            mixed[name] = {"all_converged": ok,
-                           "time_to_solution_ms_total": round(sum(r.wall_ms for r in rs), 3),
-                           "fp64_total_ms": round(sum(warm_ms.get(r.cycle, float("nan")) for r in rs), 3),
-                           "max_rel_eig_err_vs_fp64": max(errs) if errs else None,
-                           "max_resid": float(max(r.resid[:spec.nev].max() for r in rs)),
-                           "loops": [r.stats["loops"] for r in rs],
-                           "precision_switches": [r.stats["precision_switches"] for r in rs]}
-        out["mixed_precision"] = mixed
-        an = [seq.solve(c, warm=True, X=work, degree_policy=1) for c in range(1, spec.cycles)]
-        out["analytic_degree"] = {"time_to_solution_ms_total": round(sum(r.wall_ms for r in an), 3),
-                                  "all_converged": all(r.status == 0 for r in an),
-                                  "matvecs": [r.stats["matvecs"] for r in an]}
-        phase = {k: round(sum(r.stats[k] for r in timed) / len(timed), 3)
-                 for k in ("t_reduce", "t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid", "t_lock", "t_back",
-                           "t_total")}
-        out["phase_ms_per_solve"] = phase
-        # the paper's convention (standard problem, Lanczos to locking) beside the end-to-end time
-        out["solve_only_ms_per_solve"] = round(sum(phase[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr",
-                                                                       "t_resid", "t_lock")), 3)
-
-    if not args.no_extras:
+        if args.workload == "seq8192":
+            log("n=8192: degrees x precisions ...")
+            out["c3_degrees_precisions"] = bench_c3_sweep(seq, spec, golden)
+        A1 = None if args.no_cpu_baseline else chfsi.to_numpy(seq.A[1])
+        seq.A.clear()
+        torch.cuda.empty_cache()
+        if args.workload != "seq2048":
+            log("n=2048 sequence ...")
+            out["seq2048"] = bench_seq2048(seq.h)
         log("k-point batch ...")
         out["batched_kpoints"] = bench_kpoints(seq.h)
-        log("learned degree (n=4096) ...")
+        log("learned degree (n=4096, 20 cycles) ...")
         out["learned_degree"] = bench_learned_degree(seq.h)
-        log("mixed precision (n=8192) ...")
-        out["mixed_precision_n8192"] = bench_mixed_precision(seq.h)
+    else:
+        A1 = None if args.no_cpu_baseline else chfsi.to_numpy(seq.A[1])
 
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle) on a bounded sample ...")
-        x_prev = chfsi.to_numpy(seq.X[0])
-        out["cpu_baseline"] = cpu_baseline(spec, seq.host, x_prev, seq.lam[0])
+        out["cpu_baseline"] = cpu_baseline(args.workload, spec, A1)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -3,9 +3,15 @@ that hold at any size (the oracle is too slow here): the pencils of cycle 0 are 
 so their exact spectrum is known, and residuals are recomputed on the host for sampled columns,
 independently of the library.
 
-  c2: n = 2048 generalized, nev 128, nex 64, degree 12, FP64 (the bench's workload);
-  c3: n = 8192 generalized, nev 400, nex 80, degree 12, FP32 filter with FP64 everything else.
+  c2: n = 2048 generalized, nev 128, nex 64, degree 12, FP64;
+  c3: n = 8192 generalized, nev 400, nex 80, degree 12 (the bench's headline workload), with the
+      FP64, FP32, BF16x3 and BF16x6 filters; cycle 0 against its designed spectrum, and the whole
+      5-cycle warm-started sequence against the eigenvalues the CPU oracle computed for it
+      (tests/golden/c3_oracle_eigenvalues.json, written by tests/golden/make_c3_golden.py).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -54,18 +60,59 @@ def test_c2_full_size_fp64_matches_designed_spectrum(hd):
     _check(res, p, spec.nev, chfsi.to_numpy(dX), [0, 1, 63, 64, 102, 103, 127])
 
 
-def test_c3_full_size_fp32_filter_matches_designed_spectrum(hd):
-    from paper_1206_3768_amd import chfsi
+@pytest.fixture(scope="module")
+def c3_cycle0():
     spec = synth.config_mixed_precision()
-    p = synth.designed_pencil(spec, keep_vectors=False)
+    return spec, synth.designed_pencil(spec, keep_vectors=False)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_c3_full_size_low_precision_filter_matches_designed_spectrum(hd, c3_cycle0, prec):
+    from paper_1206_3768_amd import chfsi
+    spec, p = c3_cycle0
     m = spec.nev + spec.nex
+    print(f"c3 cycle 0, {prec} filter", flush=True)
     dX = chfsi.to_device(np.zeros((spec.n, m), dtype=complex))
     res = hd.solve(chfsi.to_device(p.A), chfsi.to_device(p.S), dX, False,
                    chfsi.default_params(nev=spec.nev, nex=spec.nex, deg=spec.deg, tol=1e-10, seed=1,
-                                        filter_precision=chfsi.FP32))
+                                        filter_precision=chfsi.PRECISIONS[prec]))
     assert res.status == 0
     assert res.stats["precision_switches"] > 0
     _check(res, p, spec.nev, chfsi.to_numpy(dX), [0, 1, 199, 200, 398, 399])
+
+
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle_eigenvalues.json")
+
+
+@pytest.fixture(scope="module")
+def c3_sequence(hd):
+    from paper_1206_3768_amd import sequence
+    if not os.path.exists(GOLDEN_C3):
+        pytest.skip("reference eigenvalues of the n = 8192 sequence not generated")
+    with open(GOLDEN_C3) as fh:
+        gold = {c["cycle"]: np.array([float(v) for v in c["lam"]]) for c in json.load(fh)["cycles"]}
+    seq = sequence.Sequence(synth.config_mixed_precision(), handle=hd)
+    yield seq, gold
+    seq.A.clear()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_c3_sequence_every_eigenpair_against_oracle(c3_sequence, prec):
+    """The bench's headline workload: cycle 0 from a random block, each later cycle warm-started
+    from the previous solution; every one of the 400 converged eigenvalues of every cycle against
+    the CPU oracle's, and the residuals, with the FP64 filter and each low-precision filter."""
+    seq, gold = c3_sequence
+    spec = seq.spec
+    for c in range(spec.cycles):
+        print(f"c3 cycle {c}, {prec} filter", flush=True)
+        r = seq.solve(c, warm=c > 0, store=True, filter_precision=prec)
+        assert r.status == 0, (c, r.status)
+        assert r.resid[:spec.nev].max() <= 1e-10
+        if c not in gold:
+            continue
+        ref = gold[c]
+        err = np.abs(r.lam[:spec.nev] - ref)
+        assert np.all(err <= 1e-10 * np.maximum(np.abs(ref), 1e-3)), (c, float(err.max()))
 
 
 def test_c4_full_size_batch_matches_single_solves(hd):
@@ -91,3 +138,37 @@ def test_c4_full_size_batch_matches_single_solves(hd):
         for j in (0, kp.nev // 2, kp.nev - 1):
             rr = kp.A @ X[:, j] - lam[j] * (kp.S @ X[:, j])
             assert np.linalg.norm(rr) / lo <= 2e-10
+
+
+def test_ill_conditioned_n2048_sequence_against_oracle(hd, orc):
+    """The n = 2048 sequence with an overlap of condition number 1e6 (config_ill_conditioned), three
+    warm-started cycles through the Hermitian two-sided reduction: every converged eigenvalue
+    against the oracle's (its products, solves and Cholesky factor in LAPACK at this size), and
+    LAPACK's generalized solver; residuals <= 1e-10, loops within one of the oracle's."""
+    import scipy.linalg as sla
+    from paper_1206_3768_amd import chfsi
+    spec = synth.config_ill_conditioned()
+    m = spec.nev + spec.nex
+    X = Xo = bnd = bnd_o = None
+    orc.use_library_products(True)
+    try:
+        for pen in synth.sequence(spec):
+            print(f"ill-conditioned n=2048 cycle {pen.cycle}", flush=True)
+            ref = orc.solve(pen.A, pen.S, nev=spec.nev, nex=spec.nex, deg=spec.deg, tol=1e-10, seed=1, X0=Xo,
+                            bounds=bnd_o)
+            assert ref.status == 0
+            dX = chfsi.to_device(np.zeros((spec.n, m), dtype=complex) if X is None else X)
+            prm = chfsi.default_params(nev=spec.nev, nex=spec.nex, deg=spec.deg, tol=1e-10, seed=1)
+            if bnd is not None:
+                prm.have_bounds, prm.mu1, prm.a = 1, bnd[0], bnd[1]
+            r = hd.solve(chfsi.to_device(pen.A), chfsi.to_device(pen.S), dX, X is not None, prm)
+            assert r.status == 0
+            ev = sla.eigh(pen.A, pen.S, eigvals_only=True, subset_by_index=[0, spec.nev - 1])
+            for lam_ref in (ref.lam[:spec.nev], ev):
+                assert np.all(np.abs(r.lam[:spec.nev] - lam_ref) <= 1e-10 * np.maximum(np.abs(lam_ref), 1e-3))
+            assert r.resid[:spec.nev].max() <= 1e-10
+            assert abs(r.stats["loops"] - ref.stats["loops"]) <= 1
+            X = chfsi.to_numpy(dX)
+            Xo, bnd, bnd_o = ref.X, (float(r.lam[0]), float(r.lam[m - 1])), (float(ref.lam[0]), float(ref.lam[m - 1]))
+    finally:
+        orc.use_library_products(False)
