@@ -27,13 +27,14 @@ namespace {
         if (s_ != CHFSI_SUCCESS) return s_;    \
     } while (0)
 
-void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec, int filter_ksplit)
+void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec, int filter_ksplit, bool reduce_ws)
 {
     const size_t nn = (size_t)n * n, nm = (size_t)n * m, mm = (size_t)m * m;
     if (gen) {
         b.H = ar.take<zd>(nn);
         b.L = ar.take<zd>(nn);
     }
+    if (gen || reduce_ws) b.hwork = ar.take<zd>(hegst_work_elems(n));
     b.dinvL = ar.take<zd>(tri_dinv_elems(n));
     if (prec == CHFSI_FP32) b.Hf = ar.take<zf>(nn);
     if (prec == CHFSI_BF16X3 || prec == CHFSI_BF16X6) {
@@ -75,9 +76,9 @@ void layout(Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec, in
     b.gw.ws = ar.get(ws);
 }
 
-chfsi_status prepare(chfsi_handle h, SolveBufs& b, int n, int m, int k, bool gen, int prec)
+chfsi_status prepare(chfsi_handle h, SolveBufs& b, int n, int m, int k, bool gen, int prec, bool reduce_ws = false)
 {
-    return prepare_bufs(h, h->ws, b, n, m, k, gen, prec);
+    return prepare_bufs(h, h->ws, b, n, m, k, gen, prec, reduce_ws);
 }
 
 // uniform degree in [dmin, dmax] from Philox4x64-10, counter (loop, column, 4, 0), key (seed, 0)
@@ -180,7 +181,8 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
 // the phases of one solve (state.h)
 // ---------------------------------------------------------------------------------------------
 
-chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec)
+chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec,
+                          bool reduce_ws)
 {
     // the largest K split of a tuned filter plan that a step of this order may take
     int fks = 1;
@@ -189,7 +191,7 @@ chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m,
         if (r <= 1.5) fks = std::max(fks, e.ksplit);
     }
     ar.begin(true);
-    layout(ar, b, n, m, k, gen, prec, fks);
+    layout(ar, b, n, m, k, gen, prec, fks, reduce_ws);
     const size_t need = ar.off;
     if (need > ar.cap) {
         (void)hipStreamSynchronize(h->stream);
@@ -198,7 +200,7 @@ chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m,
     }
     ar.begin(false);
     b = SolveBufs();
-    layout(ar, b, n, m, k, gen, prec, fks);
+    layout(ar, b, n, m, k, gen, prec, fks, reduce_ws);
     b.gw.cnt = h->tile_cnt;
     b.gw.ncnt = h->tile_cnt_len;
     return ar.failed ? CHFSI_ERR_ALLOC : CHFSI_SUCCESS;
@@ -251,7 +253,7 @@ chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
     s.ldh = s.lda;
     s.hi[0] = 0;
     if (s.S) {
-        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.info, s.hi, b.gw));
+        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw));
         s.H = b.H;
         s.ldh = n;
     }
@@ -684,8 +686,8 @@ chfsi_status chfsi_reduce(chfsi_handle h, int n, const void* A, int lda, const v
     if (!h || !A || !S || !H || !L || n <= 0 || lda < n || lds < n) return CHFSI_ERR_ARG;
     if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
     SolveBufs b;
-    TRYS(prepare(h, b, n, 1, 1, false, CHFSI_FP64));
-    TRYS(step_reduce(h, n, (const zd*)A, lda, (const zd*)S, lds, (zd*)H, (zd*)L, b.dinvL, b.info, b.gw));
+    TRYS(prepare(h, b, n, 1, 1, false, CHFSI_FP64, true));
+    TRYS(step_reduce(h, n, (const zd*)A, lda, (const zd*)S, lds, (zd*)H, (zd*)L, b.dinvL, b.hwork, b.info, b.gw));
     TRY(hipStreamSynchronize(h->stream));
     return CHFSI_SUCCESS;
 }

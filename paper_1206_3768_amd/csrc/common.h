@@ -71,6 +71,11 @@ struct FilterStep {
     double alpha, beta, shift;
 };
 
+// Restricted products of launch_zgemm_tri (gemm.hip)
+enum { TRI_C_LOWER = 1, TRI_B_BLOCK_LOWER = 2 };
+int launch_zgemm_tri(hipStream_t s, int tri, int opa, int opb, int M, int N, int K, double alpha, const zd* A,
+                     int lda, const zd* B, int ldb, double beta, zd* C, int ldc);
+
 // FP64 complex GEMM on MFMA.  Returns hipError_t as int.
 int launch_zgemm(hipStream_t s, int opa, int opb, int M, int N, int K, double alpha, const zd* A, int lda,
                  const zd* B, int ldb, double beta, zd* C, int ldc, const GemmWs& gw);
@@ -156,6 +161,13 @@ int trsm_right_lower_h_lowertri(hipStream_t s, int n, const zd* L, int ldl, cons
 // lower triangle of C (n x n) -= A B^H, A and B n x K
 int gemm_lower_nc(hipStream_t s, int n, int K, const zd* A, int lda, const zd* B, int ldb, zd* C, int ldc,
                   const GemmWs& gw);
+
+// ---- reduction to standard form (hegst.hip) -------------------------------------------------------
+size_t hegst_work_elems(int n);
+// A (lower triangle read) <- H = L^{-1} A L^{-H} in full, L lower with its stored diagonal-block
+// inverses dinv; work: hegst_work_elems(n) elements
+int hegst_lower(hipStream_t s, int n, zd* A, int lda, const zd* L, int ldl, const zd* dinv, zd* work,
+                const GemmWs& gw);
 
 // ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
 int eig_padded_order(int m);

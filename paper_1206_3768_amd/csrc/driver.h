@@ -115,9 +115,9 @@ struct chfsi_handle_s {
 
 // steps (solver.hip)
 chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, zd* dinv,
-                         int* info_dev, const GemmWs& gw);
+                         zd* hwork, int* info_dev, const GemmWs& gw);
 chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                                 zd* dinv, int* info_dev, int* info_host, const GemmWs& gw);
+                                 zd* dinv, zd* hwork, int* info_dev, int* info_host, const GemmWs& gw);
 chfsi_status step_lanczos_enqueue(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed,
                                   zd* LV, zd* w, zd* c, double* coef_dev, double* hal, double* hbe);
 chfsi_status lanczos_finish(int k, const double* hal, const double* hbe, std::vector<double>& theta,

@@ -22,6 +22,7 @@ struct GDims {
     int lda, ldb, ldc, ldyk, ldyp;
     double alpha, beta, shift;
     int kchunk, tiles_m, tiles_n, ksplit;
+    int tri;   // TRI_* flags (single K slice only)
 };
 
 // logical tile of workgroup w such that each XCD owns one contiguous range of tiles
@@ -82,18 +83,34 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
     constexpr int MI = S::MI, NJ = S::NJ;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nt = g.tiles_m * g.tiles_n * g.ksplit;
-    const int tile = xcd_remap(blockIdx.x, nt);
-    // tile order (ks, it, jt), jt fastest: the contiguous range of tiles that one XCD receives covers
-    // one K slice, so that the XCD's L2 holds only that slice of op(B) (and the column tiles of one
-    // row block share its op(A) panel)
-    const int jt = tile % g.tiles_n;
-    const int r1 = tile / g.tiles_n;
-    const int it = r1 % g.tiles_m;
-    const int ks = r1 / g.tiles_m;
+    int it, jt, ks;
+    if (g.tri & TRI_C_LOWER) {
+        // tiles on or below the diagonal only (BM == BN), row by row: tile t is (it, jt) with
+        // t = it (it + 1) / 2 + jt, jt <= it
+        const int nt = g.tiles_m * (g.tiles_m + 1) / 2;
+        const int tile = xcd_remap(blockIdx.x, nt);
+        int r = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+        while (r * (r + 1) / 2 > tile) --r;
+        while ((r + 1) * (r + 2) / 2 <= tile) ++r;
+        it = r;
+        jt = tile - r * (r + 1) / 2;
+        ks = 0;
+    } else {
+        const int nt = g.tiles_m * g.tiles_n * g.ksplit;
+        const int tile = xcd_remap(blockIdx.x, nt);
+        // tile order (ks, it, jt), jt fastest: the contiguous range of tiles that one XCD receives
+        // covers one K slice, so that the XCD's L2 holds only that slice of op(B) (and the column
+        // tiles of one row block share its op(A) panel)
+        jt = tile % g.tiles_n;
+        const int r1 = tile / g.tiles_n;
+        it = r1 % g.tiles_m;
+        ks = r1 / g.tiles_m;
+    }
     const int i0 = it * BM, j0 = jt * BN;
-    const int kb = ks * g.kchunk;
+    int kb = ks * g.kchunk;
     const int ke = min(g.K, kb + g.kchunk);
+    // op(B) zero in the rows above the 64-block after the output column's: the products start there
+    if (g.tri & TRI_B_BLOCK_LOWER) kb = max(kb, ((j0 >> 6) + 1) << 6);
     const int wr = (wave & 1) * (BM / 2), wc = (wave >> 1) * (BN / 2);
 
     ACC accr[MI][NJ], acci[MI][NJ];
@@ -242,7 +259,7 @@ int run(hipStream_t s, GDims g, const Plan& p, const typename CT<T>::c* A, const
         typename CT<T>::c* C, const typename CT<T>::c* Yk, const typename CT<T>::c* Yp, const GemmWs& gw)
 {
     g.kchunk = p.kchunk; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.ksplit = p.ksplit;
-    const int nt = p.tiles_m * p.tiles_n * p.ksplit;
+    const int nt = (g.tri & TRI_C_LOWER) ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n * p.ksplit;
     if (gw.plan_used) {
         gw.plan_used[0] = p.bm; gw.plan_used[1] = p.bn; gw.plan_used[2] = p.ksplit; gw.plan_used[3] = p.mode;
     }
@@ -275,6 +292,38 @@ int run(hipStream_t s, GDims g, const Plan& p, const typename CT<T>::c* A, const
 }
 
 }  // namespace
+
+// C = alpha op(A) op(B) + beta C restricted by the TRI_* flags (one K slice, no workspace):
+//  TRI_C_LOWER        only the output tiles on or below the diagonal (M == N); the diagonal tiles
+//                     are computed whole, so entries just above the diagonal may be written too
+//  TRI_B_BLOCK_LOWER  op(B) is zero above its block diagonal of 64 x 64 blocks and below it only
+//                     strictly: column block c of op(B) is nonzero in rows >= 64 (c + 1) only, and
+//                     the rows above are never read
+int launch_zgemm_tri(hipStream_t s, int tri, int opa, int opb, int M, int N, int K, double alpha, const zd* A,
+                     int lda, const zd* B, int ldb, double beta, zd* C, int ldc)
+{
+    if (M <= 0 || N <= 0) return 0;
+    if ((tri & TRI_C_LOWER) && M != N) return (int)hipErrorInvalidValue;
+    GDims g = {};
+    g.M = M; g.N = N; g.K = K; g.lda = lda; g.ldb = ldb; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta;
+    g.tri = tri;
+    Plan p;
+    p.mode = 0;
+    p.ksplit = 1;
+    p.kchunk = K > 0 ? K : 16;
+    auto count = [&](int b) {
+        const long tm = (M + b - 1) / b, tn = (N + b - 1) / b;
+        return (tri & TRI_C_LOWER) ? tm * (tm + 1) / 2 : tm * tn;
+    };
+    p.bm = p.bn = (M > 32 && N > 32 && count(64) >= 256) ? 64 : 32;
+    p.tiles_m = (M + p.bm - 1) / p.bm;
+    p.tiles_n = (N + p.bn - 1) / p.bn;
+    GemmWs none;
+    if (opa == OP_N && opb == OP_N) return run<double, OP_N, OP_N, EPI_GEMM>(s, g, p, A, B, C, nullptr, nullptr, none);
+    if (opa == OP_N && opb == OP_C) return run<double, OP_N, OP_C, EPI_GEMM>(s, g, p, A, B, C, nullptr, nullptr, none);
+    return (int)hipErrorInvalidValue;
+}
 
 size_t zgemm_ws_bytes(int M, int N, int K, int elem_bytes)
 {

@@ -1,0 +1,106 @@
+// Reduction of the Hermitian-definite pencil (A, S = L L^H) to standard form H = L^{-1} A L^{-H}
+// (Section 3.2: the generalized problem is reduced with the Cholesky factor of the overlap before
+// the iterative solver runs), using the Hermitian structure of A and H throughout: only lower
+// triangles are updated, which takes n^3/2 complex multiply-adds where two triangular solves with
+// n right-hand sides take n^3.
+//
+// With L = [L11 0; L21 L22] and A = [A11 A21^H; A21 A22] (L11 a 64 x 64 block), H = L^{-1} A L^{-H}
+// splits as
+//   H11 = L11^{-1} A11 L11^{-H}
+//   Y   = A21 L11^{-H} - 1/2 L21 H11
+//   A22 <- A22 - (Y L21^H + L21 Y^H)           (= A22 - L21 H11 L21^H - W L21^H - L21 W^H)
+//   W   = Y - 1/2 L21 H11                      (= A21 L11^{-H} - L21 H11)
+//   H21 = L22^{-1} W,   H22 = L22^{-1} A22 L22^{-H}  (the same reduction of the trailing pencil)
+// (the ordering of LAPACK's blocked xHEGST).  Phase 1 runs the panels left to right, each a few
+// small products with the stored inverse D11 = L11^{-1} and one Hermitian rank-128 update of the
+// lower triangle of the trailing matrix (one product [Y L21] [L21 Y]^H on the tiles on or below
+// the diagonal).  The solves H21 = L22^{-1} W of all panels are deferred: the block-strictly-lower
+// part of H is L^{-1} W with W the block-strictly-lower matrix of the panels' W (column block c of W
+// is zero in block rows <= c, and L^{-1} keeps that), which phase 2 solves recursively on halves in
+// products with a long inner dimension.  The diagonal blocks H11 of every panel are final after
+// phase 1; a last pass mirrors the lower triangle into the upper one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+constexpr int TB = 64;   // panel width = the diagonal blocks whose inverses the Cholesky factor stores
+
+// work (ldw x 192) <- [Y | L21 | Y] for the rank-2k update of a panel (rows rows, 64 columns each)
+__global__ void k_pack_her2k(int rows, int nb, const zd* __restrict__ Y, int ldy, const zd* __restrict__ L21, int ldl,
+                             zd* __restrict__ work, int ldw)
+{
+    const size_t total = (size_t)rows * nb;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % rows), j = (int)(e / rows);
+        const zd y = Y[(size_t)i + (size_t)j * ldy];
+        work[(size_t)i + (size_t)j * ldw] = y;
+        work[(size_t)i + (size_t)(nb + j) * ldw] = L21[(size_t)i + (size_t)j * ldl];
+        work[(size_t)i + (size_t)(2 * nb + j) * ldw] = y;
+    }
+}
+
+inline int split_point(int n) { return TB * (((n + TB - 1) / TB + 1) / 2); }
+
+// X = L^{-1} W for the block-strictly-lower W (64-blocks) held in the block-strictly-lower part of
+// B (n x n); the other blocks of B are neither read nor written
+int solve_block_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* B, int ldb, const GemmWs& gw)
+{
+    if (n <= TB) return 0;
+    const int h = split_point(n);
+    int rc = solve_block_lower(s, h, L, ldl, dinv, B, ldb, gw);                   // X11
+    if (rc != 0) return rc;
+    // W21 -= L21 X11: column block c of X11 is nonzero in rows >= 64 (c + 1) only
+    rc = launch_zgemm_tri(s, TRI_B_BLOCK_LOWER, OP_N, OP_N, n - h, h, h, -1.0, L + h, ldl, B, ldb, 1.0, B + h, ldb);
+    if (rc != 0) return rc;
+    const zd* L22 = L + h + (size_t)h * ldl;
+    const zd* D22 = dinv + (size_t)(h / TB) * TB * TB;
+    rc = trsm_left_lower(s, n - h, h, L22, ldl, D22, B + h, ldb, gw);               // X21 = L22^{-1} W21
+    if (rc != 0) return rc;
+    return solve_block_lower(s, n - h, L22, ldl, D22, B + h + (size_t)h * ldb, ldb, gw);   // X22
+}
+
+}  // namespace
+
+size_t hegst_work_elems(int n) { return (size_t)n * 3 * TB; }
+
+// A (n x n, lower triangle read, Hermitian) <- H = L^{-1} A L^{-H} in full (exactly Hermitian, real
+// diagonal); L lower with the inverses of its 64 x 64 diagonal blocks in dinv (chol_lower); work:
+// hegst_work_elems(n) elements.  Returns hipError_t as int.
+int hegst_lower(hipStream_t s, int n, zd* A, int lda, const zd* L, int ldl, const zd* dinv, zd* work,
+                const GemmWs& gw)
+{
+    if (n <= 0) return 0;
+    int rc = 0;
+    for (int k0 = 0; k0 < n && rc == 0; k0 += TB) {
+        const int nb = std::min(TB, n - k0), rest = n - k0 - nb;
+        zd* A11 = A + k0 + (size_t)k0 * lda;
+        const zd* D = dinv + (size_t)(k0 / TB) * TB * TB;
+        // H11 = D A11 D^H from the lower triangle of A11 (the updates leave its upper part stale)
+        if ((rc = launch_mirror_lower(s, nb, A11, lda)) != 0) break;
+        if ((rc = tri_apply(s, TA_LEFT_N, nb, nb, D, A11, lda)) != 0) break;
+        if ((rc = tri_apply(s, TA_RIGHT_C, nb, nb, D, A11, lda)) != 0) break;
+        if (rest == 0) break;
+        zd* A21 = A11 + nb;
+        zd* A22 = A21 + (size_t)nb * lda;
+        const zd* L21 = L + (k0 + nb) + (size_t)k0 * ldl;
+        if ((rc = tri_apply(s, TA_RIGHT_C, nb, rest, D, A21, lda)) != 0) break;                 // A21 L11^{-H}
+        if ((rc = launch_zgemm(s, OP_N, OP_N, rest, nb, nb, -0.5, L21, ldl, A11, lda, 1.0, A21, lda, gw)) != 0)
+            break;                                                                               // Y
+        hipLaunchKernelGGL(k_pack_her2k, dim3((unsigned)std::min<size_t>(((size_t)rest * nb + 255) / 256, 2048)),
+                           dim3(256), 0, s, rest, nb, A21, lda, L21, ldl, work, n);
+        if ((rc = (int)hipGetLastError()) != 0) break;
+        // A22 -= [Y L21] [L21 Y]^H on the tiles on or below the diagonal
+        if ((rc = launch_zgemm_tri(s, TRI_C_LOWER, OP_N, OP_C, rest, rest, 2 * nb, -1.0, work, n, work + (size_t)nb * n,
+                                   n, 1.0, A22, lda)) != 0)
+            break;
+        if ((rc = launch_zgemm(s, OP_N, OP_N, rest, nb, nb, -0.5, L21, ldl, A11, lda, 1.0, A21, lda, gw)) != 0)
+            break;                                                                               // W
+    }
+    if (rc != 0) return rc;
+    if ((rc = solve_block_lower(s, n, L, ldl, dinv, A, lda, gw)) != 0) return rc;              // H21 of every panel
+    return launch_mirror_lower(s, n, A, lda);
+}

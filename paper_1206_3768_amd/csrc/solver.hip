@@ -2,7 +2,7 @@
 //
 // The solver follows Algorithm 1 (Chebyshev filtered subspace iteration with locking) inside the
 // reduction of Section 3.2:
-//   reduction      S = L L^H, H = L^{-1} A L^{-H}          (own blocked Cholesky and triangular solves)
+//   reduction      S = L L^H, H = L^{-1} A L^{-H}          (own blocked Cholesky, Hermitian two-sided solve)
 //   Lanczos        k steps, full reorthogonalisation      (own kernels; k x k eig on the host)
 //   loop           filter -> orthonormalise -> Rayleigh-Ritz -> residuals -> lock prefix
 //   back-transform X = L^{-H} Y and ||A x - lambda S x|| / ||A||_lo verification
@@ -309,7 +309,7 @@ void host_tridiag_eig(int k, const double* al, const double* be, std::vector<dou
 // whole reduction; the Cholesky info word is copied to *info_host (host memory, valid after the
 // stream has been synchronised; nonzero = S not positive definite, H then meaningless).
 chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                                 zd* dinv, int* info_dev, int* info_host, const GemmWs& gw)
+                                 zd* dinv, zd* hwork, int* info_dev, int* info_host, const GemmWs& gw)
 {
     hipStream_t st = h->stream;
     TRY(launch_zlacpy(st, n, n, S, lds, L, n));
@@ -318,21 +318,15 @@ chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, co
     TRY(hipMemcpyAsync(info_host, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     TRY(launch_zero_upper(st, n, L, n));
     TRY(launch_zlacpy(st, n, n, A, lda, H, n));
-    TRY(trsm_left_lower(st, n, n, L, n, dinv, H, n, gw));      // L^{-1} A
-    // (L^{-1} A) L^{-H} is Hermitian: above n = 4096 only its lower triangle is solved for (a quarter
-    // of the reduction's work saved; below, the extra launches of the split cost more than that),
-    // then the lower triangle is mirrored
-    if (n > 4096) TRY(trsm_right_lower_h_lowertri(st, n, L, n, dinv, H, n, gw));
-    else TRY(trsm_right_lower_h(st, n, n, L, n, dinv, H, n, gw));
-    TRY(launch_mirror_lower(st, n, H, n));
+    TRY(hegst_lower(st, n, H, n, L, n, dinv, hwork, gw));        // H = L^{-1} A L^{-H}, lower triangles only
     return CHFSI_SUCCESS;
 }
 
 chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, zd* dinv,
-                         int* info_dev, const GemmWs& gw)
+                         zd* hwork, int* info_dev, const GemmWs& gw)
 {
     int info = 0;
-    chfsi_status s = step_reduce_enqueue(h, n, A, lda, S, lds, H, L, dinv, info_dev, &info, gw);
+    chfsi_status s = step_reduce_enqueue(h, n, A, lda, S, lds, H, L, dinv, hwork, info_dev, &info, gw);
     if (s != CHFSI_SUCCESS) return s;
     TRY(hipStreamSynchronize(h->stream));
     return info != 0 ? CHFSI_ERR_NOT_HPD : CHFSI_SUCCESS;

@@ -19,6 +19,7 @@ struct SolveBufs {
     uint16_t* ysplit = nullptr;        // BF16 split of Y_k
     zd *G = nullptr, *Cm = nullptr;    // m x m
     zd *dinvL = nullptr, *dinvG = nullptr;   // inverted 64 x 64 diagonal blocks of L (n) and of the Gram factor (m)
+    zd* hwork = nullptr;               // panel operands of the reduction to standard form (n x 192)
     double *theta = nullptr, *r = nullptr, *E = nullptr, *lam = nullptr, *dsc = nullptr;
     int* info = nullptr;
     int* flag = nullptr;
@@ -33,7 +34,9 @@ struct SolveBufs {
 
 // device buffers of a solve of order n, block m, k Lanczos steps, carved from `ar` (grown when
 // needed); the arena of the handle for single solves, one arena per problem for batched solves
-chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec);
+// (reduce_ws: the panel operands of the reduction, which generalized problems always get)
+chfsi_status prepare_bufs(chfsi_handle h, Arena& ar, SolveBufs& b, int n, int m, int k, bool gen, int prec,
+                          bool reduce_ws = false);
 
 struct TraceRow { int loop, col; double t, lr, a, b; int d_prev, d; double r_after, thr; };
 

@@ -222,8 +222,14 @@ class Overlap:
         return hermitian_part_(M)
 
 
-def overlap(rng: np.random.Generator, n: int, rank: int = 64) -> Overlap:
-    """HPD overlap S = I + G G^H / n with G an n x rank complex Gaussian, with its square roots."""
+def overlap(rng: np.random.Generator, n: int, rank: int = 64, kappa: float = 0.0) -> Overlap:
+    """HPD overlap with its square roots.  kappa = 0: S = I + G G^H / n with G an n x rank complex
+    Gaussian (condition number about 2.4).  kappa > 1: S = I + Q diag(s - 1) Q^H with Q an n x rank
+    orthonormal block (QR of a complex Gaussian) and s logarithmically spaced from 1/kappa to 1, so
+    that S has the eigenvalue 1 (n - rank times) and s, and its condition number is exactly kappa:
+    a nearly linearly dependent basis, as the ill-conditioned overlap of a FLAPW basis."""
+    if kappa and kappa > 1.0:
+        return _overlap_conditioned(rng, n, rank, kappa)
     import torch
     g = complex_gaussian(rng, n, rank)
     gt = torch.from_numpy(np.ascontiguousarray(g))
@@ -240,6 +246,23 @@ def overlap(rng: np.random.Generator, n: int, rank: int = 64) -> Overlap:
     fh = np.where(d > 1e-12, (sq - 1.0) / safe, 0.5 - d / 8.0)
     fm = np.where(d > 1e-12, (1.0 / sq - 1.0) / safe, -0.5 + 3.0 * d / 8.0)
     return Overlap(S=S, K=np.asfortranarray(g @ U), f_half=fh, f_mhalf=fm)
+
+
+def _overlap_conditioned(rng: np.random.Generator, n: int, rank: int, kappa: float) -> Overlap:
+    import torch
+    q, _ = np.linalg.qr(complex_gaussian(rng, n, rank))
+    q = np.asfortranarray(q)
+    s = np.logspace(-math.log10(kappa), 0.0, rank)
+    d = s - 1.0                                   # S = I + Q diag(d) Q^H
+    qt = torch.from_numpy(np.ascontiguousarray(q))
+    S = empty_f(n, n)
+    # S^T = conj(Q) diag(d) Q^T
+    torch.mm(qt.conj() * torch.from_numpy(d)[None, :], qt.T, out=_tt(S))
+    hermitian_part_(S)
+    S[np.diag_indices(n)] += 1.0
+    # the Overlap factors use K diag(f / n) K^H: K = sqrt(n) Q, f = sqrt(1 + d) - 1 (S^{1/2}) and
+    # 1 / sqrt(1 + d) - 1 (S^{-1/2})
+    return Overlap(S=S, K=np.asfortranarray(q * math.sqrt(n)), f_half=np.sqrt(s) - 1.0, f_mhalf=1.0 / np.sqrt(s) - 1.0)
 
 
 def overlap_matrix(rng: np.random.Generator, n: int, rank: int = 64) -> np.ndarray:
@@ -260,6 +283,7 @@ class Pencil:
     lam_exact: Optional[np.ndarray]   # exact spectrum when A is in designed form (cycle 0)
     X_exact: Optional[np.ndarray]     # exact S-orthonormal eigenvectors (designed form), n x n
     cycle: int = 0
+    overlap: Optional["Overlap"] = None   # S with its square roots (generalized problems)
 
 
 @dataclasses.dataclass
@@ -275,6 +299,7 @@ class SequenceSpec:
     nev: int = 32
     nex: int = 16
     deg: int = 10
+    kappa: float = 0.0     # condition number of S (0: S = I + G G^H / n, about 2.4)
 
     def eps(self, cycle: int) -> float:
         return self.eps0 * self.eps_decay ** cycle
@@ -290,25 +315,31 @@ def designed_pencil(spec: SequenceSpec, keep_vectors: bool = True, vector_cols: 
     qm = q.apply(np.eye(n, m, dtype=np.complex128)) if keep_vectors else None
     a = q.sandwich(lam)
     if spec.generalized:
-        ov = overlap(_rng(spec.seed, _STREAM_G), n)
+        ov = overlap(_rng(spec.seed, _STREAM_G), n, kappa=spec.kappa)
         s = ov.S
         a = ov.sandwich_half(a)
         x = ov.apply_mhalf(qm) if keep_vectors else None
     else:
+        ov = None
         s = None
         x = qm
-    return Pencil(A=a, S=s, lam_exact=lam, X_exact=x, cycle=0)
+    return Pencil(A=a, S=s, lam_exact=lam, X_exact=x, cycle=0, overlap=ov)
 
 
 def sequence(spec: SequenceSpec, keep_vectors: bool = False) -> Iterator[Pencil]:
     """Yield the pencils of cycles 0 .. spec.cycles-1 (A_{l+1} = A_l + eps_l (E_l + E_l^H)/2).
 
-    Every term is exactly Hermitian, so every A_l is exactly Hermitian as well."""
+    With an ill-conditioned overlap (spec.kappa > 1) the perturbation is S^{1/2} ((E_l + E_l^H)/2)
+    S^{1/2}: A and S of a nearly dependent basis share its small directions, and a perturbation of
+    the operator enters both through the basis (a plain E would put eigenvalues of order
+    eps ||E|| kappa into the pencil).  Every term is exactly Hermitian, so every A_l is as well."""
     p = designed_pencil(spec, keep_vectors=keep_vectors)
     yield p
     a = p.A
     for ell in range(1, spec.cycles):
         e = hermitian_noise(_rng(spec.seed, _STREAM_E0 + ell - 1), spec.n)
+        if spec.kappa and spec.kappa > 1.0:
+            e = p.overlap.sandwich_half(e)
         a_next = empty_f(spec.n, spec.n)
         _tt(a_next).copy_(_tt(a))
         a = add_(a_next, e, spec.eps(ell - 1))
@@ -338,6 +369,14 @@ def config_mixed_precision(seed: int = 0, n: int = 8192, cycles: int = 5) -> Seq
     """5-cycle generalized sequence, n=8192, 1/8 of the spectrum clustered, eps_l = 5e-3 * 0.6^l, nev 400, nex 80."""
     return SequenceSpec(n=n, n_low=n // 8, generalized=True, cycles=cycles, eps0=5e-3, eps_decay=0.6,
                         seed=seed, nev=400 * n // 8192, nex=80 * n // 8192, deg=12)
+
+
+def config_ill_conditioned(seed: int = 0, n: int = 2048, cycles: int = 3, kappa: float = 1e6) -> SequenceSpec:
+    """The n = 2048 generalized sequence with an overlap of condition number kappa (1e6): the
+    ill-conditioned B of the paper's FLAPW problems (Section 2.1); nev 128, nex 64, degree 12."""
+    spec = config_generalized_sequence(seed=seed, n=n, cycles=cycles)
+    spec.kappa = kappa
+    return spec
 
 
 def config_learned_degree(seed: int = 0, n: int = 4096, cycles: int = 20) -> SequenceSpec:

@@ -163,9 +163,14 @@ def test_filter_closed_form_diagonal(hd, orc):
 
 # ---- reduction, Lanczos, QR, Rayleigh-Ritz ------------------------------------------------------
 
-@pytest.mark.parametrize("n", [257, 1100])   # 1100: the recursive split above 1024 with a ragged tail
-def test_reduce_parity(hd, orc, torch_dev, n):
-    spec = synth.SequenceSpec(n=n, n_low=20, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=8)
+@pytest.mark.parametrize("n,kappa", [(40, 0.0), (64, 0.0), (257, 0.0), (1100, 0.0), (300, 1e6), (700, 1e6)])
+def test_reduce_parity(hd, orc, torch_dev, n, kappa):
+    """The Hermitian two-sided reduction (64-column panels with lower-triangle rank-2k updates, then
+    one solve with a block-lower right-hand side) against the oracle's two triangular solves: one
+    panel (40, 64), several panels with a ragged last one (257), the recursive splits of the solve
+    (1100), and overlaps of condition number 1e6.  H's rounding grows with kappa(L) = sqrt(kappa)."""
+    spec = synth.SequenceSpec(n=n, n_low=max(4, n // 20), generalized=True, cycles=1, eps0=0, eps_decay=1, seed=8,
+                              kappa=kappa)
     p = synth.designed_pencil(spec, keep_vectors=False)
     Lr, st = orc.cholesky(p.S)
     Hr = orc.reduce(p.A, Lr)
@@ -173,14 +178,18 @@ def test_reduce_parity(hd, orc, torch_dev, n):
     dH = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
     dL = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
     hd.reduce(dev(p.A), dev(p.S), dH, dL)
+    H = host(dH)
+    assert np.array_equal(H, H.conj().T)
     assert relerr(host(dL), Lr) <= 1e-13
-    assert relerr(host(dH), Hr) <= 1e-12
+    assert relerr(H, Hr) <= 1e-12 * max(1.0, math.sqrt(kappa) / 10.0)
+    # the designed spectrum survives the reduction
+    assert np.max(np.abs(np.linalg.eigvalsh(H) - p.lam_exact)) <= 1e-12 * max(1.0, math.sqrt(kappa) / 10.0)
 
 
 def test_reduce_above_4096_by_sampled_identities(hd, torch_dev):
-    """n = 4160: the second triangular solve of the reduction computes only the lower triangle of
-    H (then mirrored).  Checked without the oracle (too slow at this size) on sampled entries:
-    (L L^H)_ij = S_ij and (L H L^H)_ij = A_ij, H exactly Hermitian, L lower."""
+    """n = 4160 (65 panels, several levels of the block-lower solve).  Checked without the oracle
+    (too slow at this size) on sampled entries: (L L^H)_ij = S_ij and (L H L^H)_ij = A_ij, H exactly
+    Hermitian, L lower."""
     spec = synth.SequenceSpec(n=4160, n_low=200, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=5)
     p = synth.designed_pencil(spec, keep_vectors=False)
     n = spec.n
@@ -218,6 +227,17 @@ def test_lanczos_parity(hd, orc):
         assert np.max(np.abs(th - th_r)) <= 1e-12
         assert np.max(np.abs(zw - zw_r)) <= 1e-10
         assert abs(bk - bk_r) <= 1e-10 * max(1.0, bk_r)
+
+
+def test_lanczos_parity_eight_loads_in_flight(hd, orc):
+    # above n = 3072 the matrix-vector product keeps eight loads in flight per lane
+    n = 4096
+    H = herm(n, np.random.default_rng(41)) / math.sqrt(n)
+    th_r, zw_r, bk_r = orc.lanczos(H, 25, seed=7)
+    th, zw, bk = hd.lanczos(dev(H), 25, 7)
+    assert np.max(np.abs(th - th_r)) <= 1e-12 * np.abs(th_r).max()
+    assert np.max(np.abs(zw - zw_r)) <= 1e-10
+    assert abs(bk - bk_r) <= 1e-10 * max(1.0, bk_r)
 
 
 def test_orthonormalize_parity(hd, orc):
@@ -266,6 +286,32 @@ def test_rayleigh_ritz_parity(hd, orc):
     col_err = np.max(np.abs(host(dY) - Yr), axis=0)
     assert np.all(col_err <= 1e-13 / np.minimum(gaps, 1.0) + 1e-12)
     assert np.allclose(r, rr, rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,m", [(1024, 192), (1024, 480)])
+def test_rayleigh_ritz_parity_many_jacobi_blocks(hd, orc, n, m):
+    """Rayleigh quotients of the solver's real block widths: the block-Jacobi eigensolver meets its
+    16-index blocks in round-robin order (12 blocks and 11 rounds per sweep at m = 192, 30 blocks
+    and 29 rounds at m = 480).  Eigenvalues element by element against the oracle's cyclic Jacobi of
+    the same Rayleigh quotient, within the rounding of forming it in another order (2 (n + m) u ||G||),
+    eigenvector columns of simple eigenvalues within that over the gap."""
+    rng = np.random.default_rng(m)
+    H = herm(n, rng) / math.sqrt(n)
+    Y, _, _ = orc.qr(cgauss(n, m, rng))
+    G = orc.zgemm("C", "N", Y, orc.zgemm("N", "N", H, Y))
+    w, W, _ = orc.jacobi(G)
+    Yr = Y @ W
+    normG = np.abs(w).max()
+    tol = 2.0 * (n + m) * 1.1e-16 * normG
+    dY = dev(Y)
+    th, r = hd.rayleigh_ritz(dev(H), dY)
+    assert np.max(np.abs(th - w)) <= tol, np.max(np.abs(th - w)) / normG
+    gaps = np.minimum(np.diff(np.r_[-np.inf, w]), np.diff(np.r_[w, np.inf]))
+    simple = gaps > 1e-6 * normG
+    col_err = np.max(np.abs(host(dY) - Yr), axis=0)
+    assert np.all(col_err[simple] <= 10.0 * tol / gaps[simple] + 1e-12), np.max(col_err[simple] * gaps[simple])
+    rr = orc.residuals(H @ Yr, Yr, w)
+    assert np.allclose(r, rr, rtol=1e-6, atol=10.0 * tol)
 
 
 def test_rayleigh_ritz_with_converged_columns(hd, orc):
@@ -380,6 +426,34 @@ def test_solve_generalized_above_recursion_size_matches_designed_spectrum(hd):
     dX = dev(np.zeros((spec.n, nev + nex), dtype=complex))
     res = hd.solve(dev(p.A), dev(p.S), dX, False, chfsi.default_params(nev=nev, nex=nex, deg=12, tol=1e-10, seed=2))
     _check_solution(res, p.lam_exact, nev, np.linalg.norm(p.A, 2), host(dX), p.S)
+
+
+def test_solve_ill_conditioned_sequence_matches_oracle(hd, orc):
+    """Overlap of condition number 1e6 (the ill-conditioned B of FLAPW pencils), two warm-started
+    cycles: eigenvalues against the oracle's and LAPACK's, residuals <= 1e-10, loops within one of
+    the oracle's; S-orthonormality carries the rounding of L^{-H} (kappa(L) = 1e3): 1e-11."""
+    from paper_1206_3768_amd import chfsi
+    spec = synth.SequenceSpec(n=320, n_low=16, generalized=True, cycles=2, eps0=1e-2, eps_decay=0.5, seed=8,
+                              nev=16, nex=8, deg=12, kappa=1e6)
+    X = Xo = bnd = None
+    for pen in synth.sequence(spec):
+        m = spec.nev + spec.nex
+        ref = orc.solve(pen.A, pen.S, nev=spec.nev, nex=spec.nex, deg=12, tol=1e-10, seed=2, X0=Xo, bounds=bnd)
+        assert ref.status == 0
+        dX = dev(np.zeros((spec.n, m), dtype=complex) if X is None else X)
+        prm = chfsi.default_params(nev=spec.nev, nex=spec.nex, deg=12, tol=1e-10, seed=2)
+        if bnd is not None:
+            prm.have_bounds, prm.mu1, prm.a = 1, bnd[0], bnd[1]
+        r = hd.solve(dev(pen.A), dev(pen.S), dX, X is not None, prm)
+        assert r.status == 0
+        ev = sla.eigh(pen.A, pen.S, eigvals_only=True)[:spec.nev]
+        for lam_ref in (ref.lam[:spec.nev], ev):
+            assert np.all(np.abs(r.lam[:spec.nev] - lam_ref) <= 1e-10 * np.maximum(np.abs(lam_ref), 1e-3))
+        assert r.resid[:spec.nev].max() <= 1e-10
+        Xg = host(dX)
+        assert np.abs(Xg.conj().T @ pen.S @ Xg - np.eye(m)).max() <= 1e-11
+        assert abs(r.stats["loops"] - ref.stats["loops"]) <= 1
+        X, Xo, bnd = Xg, ref.X, (float(r.lam[0]), float(r.lam[m - 1]))
 
 
 def test_solve_analytic_degree_policy(hd):

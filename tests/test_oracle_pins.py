@@ -481,3 +481,28 @@ def test_library_primitives_give_the_plain_results(orc):
     assert np.max(np.abs(flib - fplain)) <= 1e-12 * np.abs(fplain).max()
     assert plain.status == 0 and lib.status == 0 and plain.stats["loops"] == lib.stats["loops"]
     assert np.max(np.abs(lib.lam[:10] - plain.lam[:10])) <= 1e-13
+
+
+def test_ill_conditioned_overlap_generator_and_solve(orc):
+    # S with condition number exactly 1e6 (a nearly dependent basis), the designed pencil keeps its
+    # exact spectrum, and the reference solves the two-cycle sequence to the acceptance tolerances
+    # against LAPACK's generalized solver; S-orthonormality of X = L^{-H} Y carries the rounding of
+    # L^{-H}, amplified by kappa(L) = 1e3, hence 1e-11 there
+    spec = synth.SequenceSpec(n=200, n_low=10, generalized=True, cycles=2, eps0=1e-2, eps_decay=0.5, seed=8,
+                              nev=10, nex=6, kappa=1e6)
+    X, bnd = None, None
+    for pen in synth.sequence(spec, keep_vectors=True):
+        if pen.cycle == 0:
+            ev_s = np.linalg.eigvalsh(pen.S)
+            assert abs(ev_s.max() / ev_s.min() / 1e6 - 1.0) < 1e-6
+            R = pen.A @ pen.X_exact - (pen.S @ pen.X_exact) * pen.lam_exact[None, :]
+            assert np.abs(R).max() <= 1e-12
+        r = orc.solve(pen.A, pen.S, nev=10, nex=6, deg=12, tol=1e-10, seed=2, X0=X, bounds=bnd)
+        ev = sla.eigh(pen.A, pen.S, eigvals_only=True)
+        assert r.status == 0
+        assert np.all(np.abs(r.lam[:10] - ev[:10]) <= 1e-10 * np.maximum(np.abs(ev[:10]), 1e-3))
+        assert r.resid[:10].max() <= 1e-10
+        assert np.abs(r.X.conj().T @ pen.S @ r.X - np.eye(16)).max() <= 1e-11
+        if pen.cycle == 0:
+            assert np.all(np.abs(r.lam[:10] - pen.lam_exact[:10]) <= 1e-10)
+        X, bnd = r.X, (r.lam[0], r.lam[15])
