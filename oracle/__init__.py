@@ -70,6 +70,7 @@ def _load():
     lib.orc_mlp_loss_grad.restype = C.c_double
     lib.orc_adam_step.argtypes = [ip, dp, dp, dp, dp, ip, C.c_double, C.c_double, C.c_double, C.c_double]
     lib.orc_set_library_hooks.argtypes = [dp, dp, dp]
+    lib.orc_correlation.argtypes = [ip, ip, dp, ip, dp, ip, dp, ip, dp, ip, dp, dp]
     _lib = lib
     return lib
 
@@ -276,6 +277,18 @@ def residuals(HY, Y, theta) -> np.ndarray:
 
 def analytic_degree(theta, r, a, b, thr, dmin=4, dmax=30) -> int:
     return int(_load().orc_analytic_degree(theta, r, a, b, thr, dmin, dmax))
+
+
+def correlation(Xp, Xc, S=None):
+    """Scalar products O = Xp^H S Xc of successive eigenvector blocks, the sine of the angle of each
+    pair (xp_i, xc_i) and the sines of the principal angles between the spans (ascending)."""
+    Xp = _zmat(Xp); Xc = _zmat(Xc)
+    n, m = Xc.shape
+    Sm = None if S is None else _zmat(S)
+    O = np.zeros((m, m), dtype=np.complex128, order="F")
+    sp = np.zeros(m); ss = np.zeros(m)
+    _load().orc_correlation(n, m, None if Sm is None else _p(Sm), n, _p(Xp), n, _p(Xc), n, _p(O), m, _p(sp), _p(ss))
+    return O, sp, ss
 
 
 # ---- the solver --------------------------------------------------------------------------------

@@ -743,3 +743,63 @@ int orc_solve(int n, const zc* A, int lda, const zc* S, int lds, zc* X, int ldx,
 }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------------------------------
+ * Correlation of two successive problems of a sequence (Section 2.2: scalar products between the
+ * eigenvectors of neighbouring problems, and the deviation angle of each eigenvector from its
+ * counterpart, Fig. 1).  Xp, Xc: n x m, S-orthonormal columns (S = NULL: the identity).
+ *   O = Xp^H S Xc                                   (m x m, the matrix of scalar products)
+ *   sin_pair[i] = || xc_i - xp_i O_ii ||_S / || xc_i ||_S      (sine of the angle of pair i)
+ *   sin_sub[k]  = sqrt of the eigenvalues, ascending, of R^H S R with R = Xc - Xp O
+ *                 (sines of the principal angles between the two spans)
+ * The sines come from differences of vectors, never from 1 - |O|^2, so angles of 1e-8 keep their
+ * digits.
+ * ---------------------------------------------------------------------------------------------- */
+static double s_norm2(int n, const zc* S, int lds, const zc* x)
+{
+    double s = 0;
+    if (!S) {
+        for (int i = 0; i < n; ++i) s += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+        return s;
+    }
+    zc* t = (zc*)malloc(sizeof(zc) * (size_t)n);
+    orc_zgemm('N', 'N', n, 1, n, 1.0, S, lds, x, n, 0.0, t, n);
+    zc d = 0;
+    for (int i = 0; i < n; ++i) d += conj(x[i]) * t[i];
+    free(t);
+    return creal(d);
+}
+
+void orc_correlation(int n, int m, const zc* S, int lds, const zc* Xp, int ldxp, const zc* Xc, int ldxc, zc* O,
+                     int ldo, double* sin_pair, double* sin_sub)
+{
+    zc* SX = (zc*)malloc(sizeof(zc) * (size_t)n * m);
+    zc* r = (zc*)malloc(sizeof(zc) * (size_t)n);
+    zc* R = (zc*)malloc(sizeof(zc) * (size_t)n * m);
+    zc* SR = (zc*)malloc(sizeof(zc) * (size_t)n * m);
+    zc* G = (zc*)malloc(sizeof(zc) * (size_t)m * m);
+    zc* V = (zc*)malloc(sizeof(zc) * (size_t)m * m);
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    /* O = Xp^H (S Xc) */
+    if (S) orc_zgemm('N', 'N', n, m, n, 1.0, S, lds, Xc, ldxc, 0.0, SX, n);
+    else
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < n; ++i) SX[IDX(i, j, n)] = Xc[IDX(i, j, ldxc)];
+    orc_zgemm('C', 'N', m, m, n, 1.0, Xp, ldxp, SX, n, 0.0, O, ldo);
+    /* angle of each pair (xp_i, xc_i) */
+    for (int i = 0; i < m; ++i) {
+        const zc oii = O[IDX(i, i, ldo)];
+        for (int k = 0; k < n; ++k) r[k] = Xc[IDX(k, i, ldxc)] - Xp[IDX(k, i, ldxp)] * oii;
+        sin_pair[i] = sqrt(fmax(s_norm2(n, S, lds, r), 0.0) / s_norm2(n, S, lds, Xc + IDX(0, i, ldxc)));
+    }
+    /* principal angles: R = Xc - Xp O, eigenvalues of R^H S R */
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < n; ++i) R[IDX(i, j, n)] = Xc[IDX(i, j, ldxc)];
+    orc_zgemm('N', 'N', n, m, m, -1.0, Xp, ldxp, O, ldo, 1.0, R, n);
+    if (S) orc_zgemm('N', 'N', n, m, n, 1.0, S, lds, R, n, 0.0, SR, n);
+    else memcpy(SR, R, sizeof(zc) * (size_t)n * m);
+    orc_zgemm('C', 'N', m, m, n, 1.0, R, n, SR, n, 0.0, G, m);
+    orc_jacobi(m, G, m, w, V, m);
+    for (int k = 0; k < m; ++k) sin_sub[k] = sqrt(fmax(w[k], 0.0));
+    free(SX); free(r); free(R); free(SR); free(G); free(V); free(w);
+}

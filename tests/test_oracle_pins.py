@@ -506,3 +506,36 @@ def test_ill_conditioned_overlap_generator_and_solve(orc):
         if pen.cycle == 0:
             assert np.all(np.abs(r.lam[:10] - pen.lam_exact[:10]) <= 1e-10)
         X, bnd = r.X, (r.lam[0], r.lam[15])
+
+
+# ---- correlation of successive eigenvector blocks ------------------------------------------------
+
+def test_correlation_closed_form_and_scipy(orc):
+    # Xc = Xp diag(cos t) + U diag(sin t) with U S-orthonormal and S-orthogonal to Xp: every pair
+    # (xp_i, xc_i) makes the angle t_i, those are the principal angles, and O = diag(cos t)
+    spec = synth.SequenceSpec(n=160, n_low=8, generalized=True, cycles=1, eps0=0, eps_decay=1, seed=3)
+    p = synth.designed_pencil(spec)
+    X = p.X_exact                                    # S-orthonormal eigenvectors
+    t = np.array([1e-8, 1e-4, 3e-3, 0.2, 1.0, 1.4])
+    Xp, U = X[:, :6], X[:, 10:16] * np.exp(1j * np.arange(6))[None, :]
+    Xc = np.asfortranarray(Xp * np.cos(t)[None, :] + U * np.sin(t)[None, :])
+    O, sp, ss = orc.correlation(Xp, Xc, p.S)
+    assert np.allclose(O, np.diag(np.cos(t)), atol=1e-12)
+    assert np.all(np.abs(sp - np.sin(t)) <= 1e-12 * np.maximum(np.sin(t), 1e-4))
+    assert np.all(np.abs(ss - np.sort(np.sin(t))) <= 1e-12 * np.maximum(np.sort(np.sin(t)), 1e-4))
+    # general blocks: principal angles in the S inner product are scipy's angles between L^H X blocks
+    rng = np.random.default_rng(6)
+    L = np.linalg.cholesky(p.S)
+    Q1, _ = np.linalg.qr(cgauss(160, 9, rng))
+    Q2, _ = np.linalg.qr(Q1 + 0.05 * cgauss(160, 9, rng))
+    Xp = np.asfortranarray(np.linalg.solve(L.conj().T, Q1))
+    Xc = np.asfortranarray(np.linalg.solve(L.conj().T, Q2))
+    O, sp, ss = orc.correlation(Xp, Xc, p.S)
+    ref = np.sort(np.sin(sla.subspace_angles(Q1, Q2)))
+    assert np.allclose(ss, ref, atol=1e-12)
+    assert np.allclose(O, Q1.conj().T @ Q2, atol=1e-12)
+    assert np.allclose(sp, np.sqrt(np.maximum(1 - np.abs(np.diag(Q1.conj().T @ Q2)) ** 2, 0)), atol=1e-7)
+    # standard problems (S = I) and symmetry of the principal angles
+    _, _, s1 = orc.correlation(Q1, Q2)
+    _, _, s2 = orc.correlation(Q2, Q1)
+    assert np.allclose(s1, ref, atol=1e-12) and np.allclose(s1, s2, atol=1e-12)
