@@ -267,15 +267,19 @@ __global__ void k_first_order_factor(int m, zd* G, int ldg)
     }
 }
 
+// maximum that keeps a NaN once seen (fmax would drop it): a non-finite entry of the input must
+// reach the host checks instead of vanishing from the norm
+__device__ __forceinline__ double max_keep_nan(double x, double y) { return (y > x || y != y) ? y : x; }
+
 __global__ __launch_bounds__(256) void k_max_reduce(int n, const double* v, double* out)
 {
     __shared__ double sm[256];
     double m = 0;
-    for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, v[i]);
+    for (int i = threadIdx.x; i < n; i += 256) m = max_keep_nan(m, v[i]);
     sm[threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+        if (threadIdx.x < o) sm[threadIdx.x] = max_keep_nan(sm[threadIdx.x], sm[threadIdx.x + o]);
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = sm[0];

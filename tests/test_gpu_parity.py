@@ -180,7 +180,9 @@ def test_reduce_parity(hd, orc, torch_dev, n, kappa):
     hd.reduce(dev(p.A), dev(p.S), dH, dL)
     H = host(dH)
     assert np.array_equal(H, H.conj().T)
-    assert relerr(host(dL), Lr) <= 1e-13
+    # both factors carry rounding amplified by the conditioning of the factorisation, which grows
+    # like sqrt(kappa(S)) (first-order perturbation of the Cholesky factor)
+    assert relerr(host(dL), Lr) <= 1e-13 * max(1.0, math.sqrt(kappa) / 10.0)
     assert relerr(H, Hr) <= 1e-12 * max(1.0, math.sqrt(kappa) / 10.0)
     # the designed spectrum survives the reduction
     assert np.max(np.abs(np.linalg.eigvalsh(H) - p.lam_exact)) <= 1e-12 * max(1.0, math.sqrt(kappa) / 10.0)
