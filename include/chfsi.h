@@ -36,7 +36,8 @@ typedef enum {
     CHFSI_ERR_NO_CONVERGENCE = 3, /* max_loops reached; the locked prefix is valid              */
     CHFSI_ERR_NUMERIC = 4,        /* NaN/Inf in inputs or iterates, or a breakdown in QR        */
     CHFSI_ERR_DEVICE = 5,         /* a HIP runtime call failed                                  */
-    CHFSI_ERR_ALLOC = 6           /* device or host allocation failed                           */
+    CHFSI_ERR_ALLOC = 6,          /* device or host allocation failed                           */
+    CHFSI_ERR_TOO_LARGE = 7       /* input larger than the fixed scratch of chfsi_filter_noalloc */
 } chfsi_status;
 
 /* Arithmetic of the Chebyshev filter.  Every other step (reduction, Lanczos, QR, Rayleigh-Ritz,
@@ -183,6 +184,24 @@ chfsi_status chfsi_batched_info(chfsi_handle h, double* filter_ms, double* filte
  * Requires mu1 < a < b.  This is the hot path exposed for tests and benchmarks. */
 chfsi_status chfsi_filter(chfsi_handle h, int n, const void* H, int ldh, void* Y, int ldy, int m,
                           const int* deg, int deg_uniform, double a, double b, double mu1, int prec);
+
+/* Allocation-free variant of chfsi_filter, for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  FP64 filter with
+ * one degree `deg` for every column, otherwise the operation of chfsi_filter:
+ *   Y <- T_deg((H - cI)/e) Y / T_deg((mu1 - c)/e),  c = (a+b)/2, e = (b-a)/2,  mu1 < a < b.
+ * H (n x n Hermitian, leading dimension ldh >= n) and Y (n x m, ldy >= n) are device pointers on
+ * the current device; Y is filtered in place.  No handle: the work is enqueued on `hip_stream`
+ * (NULL = the null stream) and the call returns without waiting for it; the caller synchronises.
+ * The recurrence's second n x m block and the split-K partial tiles live in one fixed device array
+ * of CHFSI_NOALLOC_SCRATCH_BYTES per device, owned by the library and held until the process ends;
+ * the call makes no allocation of any kind.  The first call on a device looks up that array's
+ * address (a caller that captures a graph makes one call before capturing, m = 0 will do).
+ * Calls that overlap on one device share the array and race: serialise them (one stream).
+ * Errors: CHFSI_ERR_ARG for invalid sizes, pointers or bounds; CHFSI_ERR_TOO_LARGE when
+ * 16 n m > CHFSI_NOALLOC_SCRATCH_BYTES (nothing is enqueued); CHFSI_ERR_DEVICE if a launch fails. */
+#define CHFSI_NOALLOC_SCRATCH_BYTES (64ull << 20)
+chfsi_status chfsi_filter_noalloc(void* hip_stream, int n, const void* H, int ldh, void* Y, int ldy, int m,
+                                  int deg, double a, double b, double mu1);
 
 /* Event timing of the filter-step launches of the last chfsi_solve / chfsi_filter on this handle:
  * *total_ms = sum over launches of the time between hipEvents recorded on the handle's stream just

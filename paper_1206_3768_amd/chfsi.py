@@ -25,9 +25,10 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 DEG_FIXED, DEG_ANALYTIC, DEG_LEARNED, DEG_RANDOM = 0, 1, 2, 3
 TRACE_COLS = 10
 MLP_NPARAM = 8769
-SUCCESS, ERR_ARG, ERR_NOT_HPD, ERR_NO_CONVERGENCE, ERR_NUMERIC, ERR_DEVICE, ERR_ALLOC = range(7)
+SUCCESS, ERR_ARG, ERR_NOT_HPD, ERR_NO_CONVERGENCE, ERR_NUMERIC, ERR_DEVICE, ERR_ALLOC, ERR_TOO_LARGE = range(8)
 STATUS_NAMES = {0: "success", 1: "invalid argument", 2: "not HPD", 3: "no convergence", 4: "numeric",
-                5: "device", 6: "alloc"}
+                5: "device", 6: "alloc", 7: "exceeds the fixed scratch"}
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class ChfsiError(RuntimeError):
@@ -77,7 +78,7 @@ EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solv
             "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string",
             "chfsi_filter_kernel_time", "chfsi_autotune_filter", "chfsi_set_filter_plan",
             "chfsi_filter_launch_log", "chfsi_set_batched_plan", "chfsi_autotune_batched",
-            "chfsi_batched_info"]
+            "chfsi_batched_info", "chfsi_filter_noalloc"]
 
 
 def load():
@@ -96,6 +97,7 @@ def load():
     lib.chfsi_solve.argtypes = [vp, i, vp, i, vp, i, vp, i, i, vp, vp, C.POINTER(Params), C.POINTER(Stats)]
     lib.chfsi_solve_batched.argtypes = [vp, i, C.POINTER(Problem), C.POINTER(Params), C.POINTER(Stats)]
     lib.chfsi_filter.argtypes = [vp, i, vp, i, vp, i, i, vp, i, d, d, d, i]
+    lib.chfsi_filter_noalloc.argtypes = [vp, i, vp, i, vp, i, i, i, d, d, d]
     lib.chfsi_reduce.argtypes = [vp, i, vp, i, vp, i, vp, vp]
     lib.chfsi_lanczos.argtypes = [vp, i, vp, i, i, u, vp, vp, vp, vp]
     lib.chfsi_orthonormalize.argtypes = [vp, i, i, vp, i, i, vp, i]
@@ -154,6 +156,22 @@ def to_device(a: np.ndarray, device="cuda", dtype=None):
 def to_numpy(t) -> np.ndarray:
     """torch tensor (cols, rows) holding a column-major matrix -> numpy (rows x cols), Fortran order."""
     return np.asfortranarray(t.detach().cpu().numpy().T)
+
+
+def filter_noalloc(H, Y, a: float, b: float, mu1: float, deg: int = 10, stream=None, n: Optional[int] = None,
+                   m: Optional[int] = None, sync: bool = True) -> None:
+    """chfsi_filter_noalloc on torch device tensors: FP64 filter of Y in place, no allocation, no
+    handle; enqueued on `stream` (a torch.cuda.Stream, default the current stream)."""
+    import torch
+    n = H.shape[-1] if n is None else n
+    m = Y.shape[0] if m is None else m
+    s = torch.cuda.current_stream() if stream is None else stream
+    st = load().chfsi_filter_noalloc(C.c_void_p(s.cuda_stream), n, _ptr(H), H.shape[-1], _ptr(Y), Y.shape[-1],
+                                     m, deg, a, b, mu1)
+    if st != SUCCESS:
+        raise ChfsiError(st, "chfsi_filter_noalloc")
+    if sync:
+        s.synchronize()
 
 
 @dataclass

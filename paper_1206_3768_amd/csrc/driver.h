@@ -132,6 +132,7 @@ chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int
                                 zd* G, double* theta_dev, double* r_dev, void* eig_work, double* eig_host,
                                 const GemmWs& gw, PhaseTimer* tm, double eig_stop = 0.0);
 void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps);
+FilterStep filter_step_coefficients(int k, double a, double b, double mu1, double& sigma);
 chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
                         const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);
 chfsi_status filter_f32(chfsi_handle h, int n, const zf* Hf, int ldh, int ma, zf* Yf, int ldy, zf* Tf,

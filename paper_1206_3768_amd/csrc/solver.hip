@@ -153,6 +153,7 @@ const char* chfsi_status_string(chfsi_status s)
     case CHFSI_ERR_NUMERIC: return "non-finite values or breakdown";
     case CHFSI_ERR_DEVICE: return "HIP runtime error";
     case CHFSI_ERR_ALLOC: return "allocation failed";
+    case CHFSI_ERR_TOO_LARGE: return "input exceeds the fixed scratch of the allocation-free filter";
     }
     return "unknown status";
 }
@@ -481,26 +482,31 @@ chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int
 
 // Scaled recurrence coefficients: step 1 has alpha = sigma_1/e, beta = 0; step k+1 (k >= 1) has
 // sigma_{k+1} = 1/(2/sigma_1 - sigma_k), alpha = 2 sigma_{k+1}/e, beta = -sigma_k sigma_{k+1}.
-void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps)
+// Step k (0-based) on its own: sigma carries sigma_k from the previous call (ignored for k = 0).
+FilterStep filter_step_coefficients(int k, double a, double b, double mu1, double& sigma)
 {
     const double c = 0.5 * (a + b), e = 0.5 * (b - a);
     const double sigma1 = e / (mu1 - c);
-    steps.resize(dmax);
-    double sigma = sigma1;
-    for (int k = 0; k < dmax; ++k) {
-        FilterStep fs;
-        fs.shift = c;
-        if (k == 0) {
-            fs.alpha = sigma1 / e;
-            fs.beta = 0.0;
-        } else {
-            const double sn = 1.0 / (2.0 / sigma1 - sigma);
-            fs.alpha = 2.0 * sn / e;
-            fs.beta = -sigma * sn;
-            sigma = sn;
-        }
-        steps[k] = fs;
+    FilterStep fs;
+    fs.shift = c;
+    if (k == 0) {
+        fs.alpha = sigma1 / e;
+        fs.beta = 0.0;
+        sigma = sigma1;
+    } else {
+        const double sn = 1.0 / (2.0 / sigma1 - sigma);
+        fs.alpha = 2.0 * sn / e;
+        fs.beta = -sigma * sn;
+        sigma = sn;
     }
+    return fs;
+}
+
+void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps)
+{
+    steps.resize(dmax);
+    double sigma = 0;
+    for (int k = 0; k < dmax; ++k) steps[k] = filter_step_coefficients(k, a, b, mu1, sigma);
 }
 
 // Filters the ma columns of Y whose degrees deg[] are sorted in non-increasing order.  T is a
