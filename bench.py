@@ -70,10 +70,34 @@ def spec_of(workload: str):
     return synth.config_generalized_sequence()
 
 
-def load_traffic(workload: str, kernel: str):
+PREC_NAMES = {0: "fp64", 1: "fp32", 2: "bf16x3", 3: "bf16x6"}
+PREC_DTYPE = {0: "f64", 1: "f32", 2: "bf16x3", 3: "bf16x6"}
+PREC_PROFILE = {0: "f64", 1: "f32", 2: "bf16x3", 3: "bf16x6"}
+
+
+def kernel_symbol(prec: int, bm: int, bn: int, mode: int) -> str:
+    """Symbol of the filter-step kernel of a launch-log row (as rocprofv3 names it)."""
+    if prec == 0:
+        return f"k_zgemm<double, 0, 0, 1, {bm}, {bn}, {mode}>"
+    if prec == 1:
+        return f"k_zgemm<float, 0, 0, 1, {bm}, {bn}, {mode}>"
+    return f"k_filter_bf16<{2 if prec == 2 else 3}, {'true' if mode else 'false'}>"
+
+
+def peak_and_products(prec: int):
+    """MFMA peak of the arithmetic of `prec` (TFLOP/s) and the executed products per counted one:
+    the BF16-split filters run 3 or 6 BF16 products for each complex product of the standard count."""
+    if prec == 0:
+        return PEAK["f64"], 1
+    if prec == 1:
+        return PEAK["f32"], 1
+    return PEAK["bf16"], (3 if prec == 2 else 6)
+
+
+def load_traffic(workload: str, kernel: str, prec: int = 0):
     """The committed rocprofv3 counter summary of `kernel` on this workload, if it was taken on the
     current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"filter_f64_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"filter_{PREC_PROFILE[prec]}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -123,12 +147,15 @@ def cpu_baseline(workload: str, seq_spec, A_host) -> dict:
                       f"the sequence's A_1 ({tf:.2f} s, {flops / 1e9:.1f} GFLOP)", "seconds": round(tf, 2)}
 
 
-def roofline(rows: np.ndarray, workload: str) -> dict:
-    """Dominant filter kernel (the (precision, tile, split mode) group with the largest summed
-    main-kernel time): algorithmic flops per launch over its average dispatch duration, alone and with
-    its split-K reduction; HBM traffic from the committed counter summary when it matches the sources."""
+def roofline(rows: np.ndarray, workload: str, prec: int = 0) -> dict:
+    """Dominant filter kernel of precision `prec` (the (tile, split mode) group with the largest
+    summed main-kernel time): algorithmic flops per launch over its average dispatch duration, alone
+    and with its split-K reduction; HBM traffic from the committed counter summary when it matches
+    the sources."""
     groups = {}
     for nn, w, pr, bm, bn, ks, mode, t_main, t_step in rows:
+        if int(pr) != prec:
+            continue
         key = (int(pr), int(bm), int(bn), int(mode))   # one kernel symbol per (tile, split mode)
         g = groups.setdefault(key, [0.0, 0.0, 0.0, 0, 0.0, 0.0])
         g[0] += 8.0 * nn * nn * w
@@ -140,20 +167,23 @@ def roofline(rows: np.ndarray, workload: str) -> dict:
     key, (g_flops, g_time, g_step, g_count, g_bytes, g_n) = max(groups.items(), key=lambda kv: kv[1][1])
     achieved = g_flops / g_time / 1e12
     achieved_step = g_flops / g_step / 1e12
-    kernel = f"k_zgemm<double, 0, 0, 1, {key[1]}, {key[2]}, {key[3]}>"
-    tr = load_traffic(workload, kernel)
+    kernel = kernel_symbol(prec, key[1], key[2], key[3])
+    tr = load_traffic(workload, kernel, prec)
     alg_bytes = g_bytes / g_count
-    out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
-           "frac": round(achieved / PEAK["f64"], 4),
+    peak, products = peak_and_products(prec)
+    out = {"bound": "mfma", "achieved": round(achieved * products, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved * products / peak, 4),
            "traffic": tr["bytes_per_launch"] if tr else None,
            "kernel": kernel, "flops_per_launch": g_flops / g_count, "avg_launch_ms": g_time / g_count * 1e3,
            "launches": g_count,
            # the whole filter step: the main kernel and, for a split-K plan, the kernel summing its
            # partial tiles and applying the recurrence
-           "step_achieved": round(achieved_step, 3), "step_frac": round(achieved_step / PEAK["f64"], 4),
+           "step_achieved": round(achieved_step * products, 3),
+           "step_frac": round(achieved_step * products / peak, 4),
            "avg_step_ms": g_step / g_count * 1e3,
+           "standard_count_tflops": round(achieved, 3),
            # the three-product complex MFMA executes 6 of the 8 counted flops per complex multiply-add
-           "mfma_frac": round(0.75 * achieved / PEAK["f64"], 4),
+           "mfma_frac": round((0.75 if prec < 2 else 1.0) * achieved * products / peak, 4),
            "algorithmic_bytes_per_launch": alg_bytes,
            "all_filter_launches": {"count": int(len(rows)),
                                    "tflops": round(float(np.sum(8.0 * rows[:, 0] ** 2 * rows[:, 1]) /
@@ -162,27 +192,44 @@ def roofline(rows: np.ndarray, workload: str) -> dict:
                                                                      np.sum(rows[:, 8] * 1e-3) / 1e12), 3)}}
     if tr:
         out["traffic_over_algorithmic"] = round(tr["bytes_per_launch"] / alg_bytes, 3)
-        out["traffic_source"] = f"profiles/filter_f64_{workload}_traffic.json"
+        out["traffic_source"] = f"profiles/filter_{PREC_PROFILE[prec]}_{workload}_traffic.json"
     return out
 
 
-def timed_sequence(seq, spec, steps: int, warmup: int):
-    """Warm-started FP64 solves of cycles 1 .. cycles-1 in turn; returns results and launch logs."""
+def timed_sequence(seq, spec, steps: int, warmup: int, prec: int = 0):
+    """Warm-started solves of cycles 1 .. cycles-1 in turn (filter precision `prec`); returns
+    results and launch logs."""
     import torch
     cycles = [1 + (s % (spec.cycles - 1)) for s in range(warmup + steps)]
     work = seq.new_block()
     for c in cycles[:warmup]:
-        seq.solve(c, warm=True, X=work)
+        seq.solve(c, warm=True, X=work, filter_precision=prec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     timed, launch_rows = [], []
     for c in cycles[warmup:]:
-        timed.append(seq.solve(c, warm=True, X=work))
+        timed.append(seq.solve(c, warm=True, X=work, filter_precision=prec))
         launch_rows.append(seq.h.filter_launch_log())   # host-side copy of this solve's event log
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     rows = np.concatenate(launch_rows) if launch_rows else np.zeros((0, 9))
     return timed, rows, wall, work
+
+
+def correlation_summary(seq, spec) -> dict:
+    """Angles between the eigenvectors of successive cycles of the sequence (the stored solutions of
+    the reference pass): sines of the principal angles between the spans of the nev wanted vectors
+    and of the angle each vector turns by (chfsi_correlation), per cycle."""
+    out = {}
+    nev = spec.nev
+    for c in range(1, spec.cycles):
+        Xp, Xc = seq.X[c - 1], seq.X[c]
+        if Xp is None or Xc is None:
+            continue
+        _, sp, ss = seq.h.correlation(Xp[:nev], Xc[:nev], seq.S, n=spec.n, m=nev)
+        out[f"{c - 1}->{c}"] = {"max_sin_principal": float(ss.max()), "median_sin_principal": float(np.median(ss)),
+                                "max_sin_pair": float(sp.max()), "median_sin_pair": float(np.median(sp))}
+    return out
 
 
 def phase_summary(timed) -> dict:
@@ -397,6 +444,8 @@ def main() -> int:
     ap.add_argument("--workload", default="seq8192", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed headline solves")
+    ap.add_argument("--precision", default="fp64", choices=sorted(PREC_NAMES.values()),
+                    help="filter arithmetic of the timed solves (the headline is FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one MI355X; --gpus {args.gpus} is not supported: the solver drives "
@@ -421,8 +470,10 @@ def main() -> int:
         log(f"reference pass failed on cycles {bad}")
         return 1
     log("reference pass: loops per cycle " + " ".join(str(r.stats["loops"]) for r in ref))
+    corr = correlation_summary(seq, spec)
 
-    timed, rows, wall, work = timed_sequence(seq, spec, args.steps, args.warmup)
+    prec = {v: k for k, v in PREC_NAMES.items()}[args.precision]
+    timed, rows, wall, work = timed_sequence(seq, spec, args.steps, args.warmup, prec)
     for r in timed:
         if r.status != 0 or r.resid[:spec.nev].max() > 1e-10:
             log(f"timed solve of cycle {r.cycle} failed: status {r.status}, max resid {r.resid[:spec.nev].max():.2e}")
@@ -430,7 +481,7 @@ def main() -> int:
     flops = sum(r.stats["filter_flops"] for r in timed)
     t_filter = sum(r.stats["t_filter"] for r in timed) * 1e-3
     value = flops / t_filter / 1e12
-    rl = roofline(rows, args.workload)
+    rl = roofline(rows, args.workload, prec)
     log(f"timed {args.steps} warm solves: {wall / args.steps * 1e3:.2f} ms/solve, filter phase {value:.2f} TFLOP/s; "
         f"dominant kernel {rl['kernel']}: {rl['launches']} launches, {rl['achieved']:.2f} TFLOP/s "
         f"({rl['step_achieved']:.2f} with its reduction)")
@@ -446,15 +497,17 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": PREC_DTYPE[prec],
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "n": n, "nev": spec.nev, "nex": spec.nex, "deg": spec.deg,
+        "config": {"workload": WORKLOADS[args.workload].replace("FP64 filter", f"{args.precision.upper()} filter"),
+                   "n": n, "nev": spec.nev, "nex": spec.nex, "deg": spec.deg,
                    "cycles": spec.cycles},
         "time_to_solution_ms": {"median": round(statistics.median(r.wall_ms for r in timed), 3),
                                 "per_cycle": {str(r.cycle): round(r.wall_ms, 3) for r in timed}},
         "roofline": rl,
         "phase_ms_per_solve": phase_summary(timed),
         "loops_per_cycle": {str(r.cycle): r.stats["loops"] for r in ref},
+        "eigenvector_correlation": corr,
     }
     golden = golden_c3() if args.workload == "seq8192" else {}
     if golden:

@@ -245,6 +245,19 @@ chfsi_status chfsi_orthonormalize(chfsi_handle h, int n, int m, void* Y, int ldy
 chfsi_status chfsi_rayleigh_ritz(chfsi_handle h, int n, const void* H, int ldh, int m, void* Y,
                                  int ldy, double* theta, double* resid);
 
+/* Correlation of the eigenvectors of two neighbouring problems of a sequence (Section 2.2: the
+ * scalar products between eigenvectors of successive problems and the angle each one turns by,
+ * Fig. 1).  Xp, Xc: n x m device blocks, each S-orthonormal (S = NULL: orthonormal, standard
+ * problems); S: n x n HPD device matrix or NULL.  Outputs:
+ *   O (device, m x m, leading dimension ldo >= m) = Xp^H S Xc;
+ *   sin_pair (host [m]): sin_pair[i] = ||xc_i - O_ii xp_i||_S / ||xc_i||_S, the sine of the angle
+ *                        between xp_i and xc_i;
+ *   sin_sub (host [m]): the sines of the principal angles between span(Xp) and span(Xc),
+ *                       ascending: square roots of the eigenvalues of R^H S R, R = Xc - Xp O.
+ * Synchronous on return.  CHFSI_ERR_NUMERIC for non-finite values or a zero column of Xc. */
+chfsi_status chfsi_correlation(chfsi_handle h, int n, int m, const void* S, int lds, const void* Xp, int ldxp,
+                               const void* Xc, int ldxc, void* O, int ldo, double* sin_pair, double* sin_sub);
+
 /* Fills Y (n x m, device) with the library's random block: element e = i + j n of stream `stream`
  * is Philox4x64-10 (Salmon et al., SC'11) of counter (e/2, stream, 0, 0) and key (seed, 0); the
  * parity of e selects words (0,1) or (2,3); each word w gives a part 2 (w >> 11) 2^-53 - 1 in

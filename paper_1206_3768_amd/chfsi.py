@@ -78,7 +78,7 @@ EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solv
             "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string",
             "chfsi_filter_kernel_time", "chfsi_autotune_filter", "chfsi_set_filter_plan",
             "chfsi_filter_launch_log", "chfsi_set_batched_plan", "chfsi_autotune_batched",
-            "chfsi_batched_info", "chfsi_filter_noalloc"]
+            "chfsi_batched_info", "chfsi_filter_noalloc", "chfsi_correlation"]
 
 
 def load():
@@ -98,6 +98,7 @@ def load():
     lib.chfsi_solve_batched.argtypes = [vp, i, C.POINTER(Problem), C.POINTER(Params), C.POINTER(Stats)]
     lib.chfsi_filter.argtypes = [vp, i, vp, i, vp, i, i, vp, i, d, d, d, i]
     lib.chfsi_filter_noalloc.argtypes = [vp, i, vp, i, vp, i, i, i, d, d, d]
+    lib.chfsi_correlation.argtypes = [vp, i, i, vp, i, vp, i, vp, i, vp, i, vp, vp]
     lib.chfsi_reduce.argtypes = [vp, i, vp, i, vp, i, vp, vp]
     lib.chfsi_lanczos.argtypes = [vp, i, vp, i, i, u, vp, vp, vp, vp]
     lib.chfsi_orthonormalize.argtypes = [vp, i, i, vp, i, i, vp, i]
@@ -347,6 +348,18 @@ class Handle:
         self._check(self.lib.chfsi_rayleigh_ritz(self.h, H.shape[-1], _ptr(H), H.shape[-1], m, _ptr(Y),
                                                  Y.shape[-1], th.ctypes.data, r.ctypes.data), "chfsi_rayleigh_ritz")
         return th, r
+
+    def correlation(self, Xp, Xc, S=None, n: Optional[int] = None, m: Optional[int] = None):
+        """chfsi_correlation: (O device tensor (m, m) column-major, sin_pair, sin_sub host arrays)."""
+        import torch
+        n = Xc.shape[-1] if n is None else n
+        m = Xc.shape[0] if m is None else m
+        O = torch.empty((m, m), dtype=torch.complex128, device=Xc.device)
+        sp, ss = np.zeros(m), np.zeros(m)
+        self._check(self.lib.chfsi_correlation(self.h, n, m, _ptr(S), 0 if S is None else S.shape[-1], _ptr(Xp),
+                                               Xp.shape[-1], _ptr(Xc), Xc.shape[-1], _ptr(O), m, sp.ctypes.data,
+                                               ss.ctypes.data), "chfsi_correlation")
+        return O, sp, ss
 
     def random_block(self, seed: int, stream: int, n: int, m: int):
         import torch

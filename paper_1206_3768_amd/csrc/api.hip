@@ -745,6 +745,63 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_handle h, int n, const void* H, int ldh, 
     return info ? CHFSI_ERR_NUMERIC : CHFSI_SUCCESS;
 }
 
+// Correlation of successive eigenvector blocks (Section 2.2 and Fig. 1): O = Xp^H S Xc, the angle of
+// each pair (xp_i, xc_i) from the part of xc_i off xp_i, and the principal angles between the spans
+// from the eigenvalues of R^H S R with R = Xc - Xp O (R explicit: no cancellation for small angles).
+chfsi_status chfsi_correlation(chfsi_handle h, int n, int m, const void* Sv, int lds, const void* Xpv, int ldxp,
+                               const void* Xcv, int ldxc, void* Ov, int ldo, double* sin_pair, double* sin_sub)
+{
+    if (!h || !Xpv || !Xcv || !Ov || n <= 0 || m <= 0 || m > n || ldxp < n || ldxc < n || ldo < m ||
+        (Sv && lds < n) || !sin_pair || !sin_sub)
+        return CHFSI_ERR_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
+    SolveBufs b;
+    TRYS(prepare(h, b, n, m, 1, false, CHFSI_FP64));
+    hipStream_t st = h->stream;
+    const zd* S = (const zd*)Sv;
+    const zd* Xp = (const zd*)Xpv;
+    const zd* Xc = (const zd*)Xcv;
+    zd* O = (zd*)Ov;
+    // S times an n x m block (or the block itself for the standard problem)
+    auto s_times = [&](const zd* X, int ldx, const zd** SX, int* ldsx) -> chfsi_status {
+        if (!S) { *SX = X; *ldsx = ldx; return CHFSI_SUCCESS; }
+        TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, S, lds, X, ldx, 0.0, b.HY, n, b.gw));
+        *SX = b.HY;
+        *ldsx = n;
+        return CHFSI_SUCCESS;
+    };
+    const zd* SX = nullptr;
+    int ldsx = 0;
+    TRYS(s_times(Xc, ldxc, &SX, &ldsx));
+    TRY(launch_zgemm(st, OP_C, OP_N, m, m, n, 1.0, Xp, ldxp, SX, ldsx, 0.0, O, ldo, b.gw));
+    TRY(launch_pair_dots(st, n, m, Xc, ldxc, SX, ldsx, b.r));              // ||xc_i||_S^2
+    TRY(launch_sub_diag_scaled(st, n, m, Xc, ldxc, Xp, ldxp, O, ldo, b.T, n));
+    TRYS(s_times(b.T, n, &SX, &ldsx));
+    TRY(launch_pair_dots(st, n, m, b.T, n, SX, ldsx, b.lam));             // ||xc_i - o_ii xp_i||_S^2
+    std::vector<double> num(m), den(m), w(m);
+    TRY(hipMemcpyAsync(num.data(), b.lam, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    TRY(hipMemcpyAsync(den.data(), b.r, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    // R = Xc - Xp O, G = R^H S R
+    TRY(launch_zlacpy(st, n, m, Xc, ldxc, b.T, n));
+    TRY(launch_zgemm(st, OP_N, OP_N, n, m, m, -1.0, Xp, ldxp, O, ldo, 1.0, b.T, n, b.gw));
+    TRYS(s_times(b.T, n, &SX, &ldsx));
+    TRY(launch_zgemm(st, OP_C, OP_N, m, m, n, 1.0, b.T, n, SX, ldsx, 0.0, b.G, m, b.gw));
+    std::vector<double> ehost(eig_host_doubles(m));
+    int sweeps = 0;
+    const int rc = eig_jacobi(st, m, b.G, m, b.theta, b.eigw, ehost.data(), &sweeps);
+    if (rc == -1) return CHFSI_ERR_NUMERIC;
+    TRY(rc);
+    TRY(hipMemcpyAsync(w.data(), b.theta, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < m; ++i) {
+        if (!std::isfinite(num[i]) || !std::isfinite(den[i]) || !(den[i] > 0) || !std::isfinite(w[i]))
+            return CHFSI_ERR_NUMERIC;
+        sin_pair[i] = std::sqrt(std::max(num[i], 0.0) / den[i]);
+        sin_sub[i] = std::sqrt(std::max(w[i], 0.0));
+    }
+    return CHFSI_SUCCESS;
+}
+
 chfsi_status chfsi_zgemm(chfsi_handle h, char transa, char transb, int m, int n, int k, double alpha, const void* A,
                          int lda, const void* B, int ldb, double beta, void* C, int ldc)
 {

@@ -218,6 +218,30 @@ __global__ __launch_bounds__(256) void k_residual_norms(int n, const zd* HY, int
     if (threadIdx.x == 0) r[j] = sqrt(s);
 }
 
+// d[j] = Re(A[:, j]^H B[:, j]), one 256-thread block per column
+__global__ __launch_bounds__(256) void k_pair_dots(int n, const zd* A, int lda, const zd* B, int ldb, double* d)
+{
+    __shared__ double sm[4];
+    const zd* a = A + (size_t)blockIdx.x * lda;
+    const zd* b = B + (size_t)blockIdx.x * ldb;
+    double s = 0;
+    for (int i = threadIdx.x; i < n; i += 256) s += a[i].x * b[i].x + a[i].y * b[i].y;
+    s = block_sum256(s, sm);
+    if (threadIdx.x == 0) d[blockIdx.x] = s;
+}
+
+// D[:, j] = Xc[:, j] - O_jj Xp[:, j]  (the part of each new vector off its predecessor)
+__global__ void k_sub_diag_scaled(int n, int m, const zd* Xc, int ldc, const zd* Xp, int ldp, const zd* O, int ldo,
+                                  zd* D, int ldd)
+{
+    const size_t total = (size_t)n * m;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        const zd o = O[(size_t)j * ldo + j], p = Xp[(size_t)j * ldp + i], c = Xc[(size_t)j * ldc + i];
+        D[(size_t)j * ldd + i] = make_double2(c.x - (o.x * p.x - o.y * p.y), c.y - (o.x * p.y + o.y * p.x));
+    }
+}
+
 __global__ __launch_bounds__(256) void k_colnorms(int n, const zd* Y, int ldy, double* r)
 {
     __shared__ double sm[4];
@@ -501,6 +525,22 @@ int launch_residual_norms(hipStream_t s, int n, int m, const zd* HY, int ldhy, c
 {
     if (m <= 0) return 0;
     hipLaunchKernelGGL(k_residual_norms, dim3(m), dim3(256), 0, s, n, HY, ldhy, Y, ldy, theta, r);
+    return (int)hipGetLastError();
+}
+
+int launch_pair_dots(hipStream_t s, int n, int m, const zd* A, int lda, const zd* B, int ldb, double* d)
+{
+    if (m <= 0) return 0;
+    hipLaunchKernelGGL(k_pair_dots, dim3(m), dim3(256), 0, s, n, A, lda, B, ldb, d);
+    return (int)hipGetLastError();
+}
+
+int launch_sub_diag_scaled(hipStream_t s, int n, int m, const zd* Xc, int ldc, const zd* Xp, int ldp, const zd* O,
+                           int ldo, zd* D, int ldd)
+{
+    if (n <= 0 || m <= 0) return 0;
+    hipLaunchKernelGGL(k_sub_diag_scaled, dim3(grid_for((size_t)n * m)), dim3(256), 0, s, n, m, Xc, ldc, Xp, ldp, O,
+                       ldo, D, ldd);
     return (int)hipGetLastError();
 }
 

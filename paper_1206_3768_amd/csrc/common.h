@@ -113,6 +113,11 @@ int launch_gemv_n(hipStream_t s, int n, int ncols, const zd* V, int ldv, const z
 int launch_residual_norms(hipStream_t s, int n, int m, const zd* HY, int ldhy, const zd* Y, int ldy,
                           const double* theta, double* r);
 int launch_colnorms(hipStream_t s, int n, int m, const zd* Y, int ldy, double* r);
+// d[j] = Re(A[:, j]^H B[:, j])  (d device, m doubles)
+int launch_pair_dots(hipStream_t s, int n, int m, const zd* A, int lda, const zd* B, int ldb, double* d);
+// D[:, j] = Xc[:, j] - O_jj Xp[:, j]
+int launch_sub_diag_scaled(hipStream_t s, int n, int m, const zd* Xc, int ldc, const zd* Xp, int ldp, const zd* O,
+                           int ldo, zd* D, int ldd);
 int launch_scale_cols_inv(hipStream_t s, int n, int m, zd* Y, int ldy, const double* nrm);   // Y[:, j] /= nrm[j]
 int launch_max_colnorm(hipStream_t s, int n, const zd* A, int lda, double* out);            // max_j ||A[:, j]||
 int launch_max_rowsum_abs(hipStream_t s, int n, const zd* A, int lda, double* out);         // ||A||_inf
