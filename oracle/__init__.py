@@ -10,6 +10,7 @@ order).  It shares no code with the GPU library.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -18,7 +19,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "chfsi_oracle.c"), os.path.join(_HERE, "mlp_oracle.c")]
+_SRCS = [os.path.join(_HERE, "chfsi_oracle.c"), os.path.join(_HERE, "mlp_oracle.c"),
+         os.path.join(_HERE, "lobpcg_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -334,6 +336,40 @@ def solve(A, S=None, nev=32, nex=16, deg=10, tol=1e-10, X0=None, max_loops=50, l
     status = _load().orc_solve(n, _p(A), n, None if Sm is None else _p(Sm), n, _p(X), n,
                                0 if X0 is None else 1, _p(lam), _p(res), C.byref(p), C.byref(st))
     stats = {f: getattr(st, f) for f, _ in _Stats._fields_}
+    return SolveResult(status=int(status), lam=lam, resid=res, X=X, stats=stats)
+
+
+# ---- LOBPCG (the paper's second solver; GEN on the pencil, STD after the reduction) -------------
+
+class _LobpcgParams(C.Structure):
+    _fields_ = [("nev", C.c_int), ("bs", C.c_int), ("maxiter", C.c_int), ("gen", C.c_int), ("tol", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class _LobpcgStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("nconv", C.c_int), ("matvecs", C.c_longlong), ("bmatvecs", C.c_longlong),
+                ("dropped", C.c_int)]
+
+
+def lobpcg_block_size(nev: int) -> int:
+    """Table 3: the LOBPCG block is 1.05 nev."""
+    return int(math.ceil(1.05 * nev))
+
+
+def lobpcg(A, S=None, nev=16, bs=None, tol=1e-10, X0=None, maxiter=1000, gen=False, seed=0) -> SolveResult:
+    """Block LOBPCG without preconditioner; ``gen`` iterates on the pencil (A, S) directly,
+    otherwise on H = L^{-1} A L^{-H} (S given) and back-transforms."""
+    A = _zmat(A)
+    n = A.shape[0]
+    bs = lobpcg_block_size(nev) if bs is None else bs
+    Sm = None if S is None else _zmat(S)
+    X = np.zeros((n, bs), dtype=np.complex128, order="F") if X0 is None else _zmat(X0).copy(order="F")
+    lam = np.zeros(bs); res = np.zeros(bs)
+    p = _LobpcgParams(nev, bs, maxiter, 1 if gen else 0, tol, seed)
+    st = _LobpcgStats()
+    status = _load().orc_lobpcg(n, _p(A), n, None if Sm is None else _p(Sm), n, _p(X), n, 0 if X0 is None else 1,
+                                _p(lam), _p(res), C.byref(p), C.byref(st))
+    stats = {f: getattr(st, f) for f, _ in _LobpcgStats._fields_}
     return SolveResult(status=int(status), lam=lam, resid=res, X=X, stats=stats)
 
 
