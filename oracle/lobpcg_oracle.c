@@ -16,7 +16,13 @@
  *    X, then P against X and W, each projection done twice), so the projected problem is a
  *    standard Hermitian one; a block is orthonormalised through the eigen-decomposition of its
  *    B-Gram matrix after scaling its columns to unit B-norm, and directions whose Gram eigenvalue
- *    is below 1e-12 of the largest are dropped (a nearly dependent residual or direction);
+ *    is below 1e-8 of the largest are dropped (a nearly dependent residual or direction: with an
+ *    ill-conditioned B the rounding of the Gram matrix grows with kappa(B), and the direction of a
+ *    smaller eigenvalue would come out of the scaling far from B-orthonormal);
+ *  - A-images are updated with the same linear combinations as the blocks (one product with A per
+ *    new residual), B-images are formed again with B after every change of a block: with an
+ *    ill-conditioned B an updated image drifts from B Y, the basis stops being B-orthonormal and
+ *    the Rayleigh-Ritz step returns spurious Ritz values;
  *  - soft locking: a column whose residual meets the threshold leaves W and P but stays in X;
  *  - the iteration stops when the nev lowest Ritz pairs (a leading prefix) all meet the threshold,
  *    or after maxiter iterations;
@@ -81,24 +87,28 @@ static void apply_b(const pencil_t* P, int k, const zc* Y, zc* BY, long long* bm
     }
 }
 
-/* Y <- Y - Q (BQ^H Y) for the triple (Y, AY, BY) with (Q, AQ, BQ): the B-projection of Y off
- * span(Q), applied alike to A Y and B Y. */
-static void project_out(int n, int q, const zc* Q, const zc* AQ, const zc* BQ, int k, zc* Y, zc* AY, zc* BY)
+/* Y <- Y - Q (BQ^H Y): the B-projection of Y off span(Q), applied alike to A Y; B Y is formed
+ * again from the new Y (an image updated by the same combination drifts from B Y when B is
+ * ill-conditioned, and the Rayleigh-Ritz step relies on Z^H B Z = I). */
+static void project_out(const pencil_t* P, int q, const zc* Q, const zc* AQ, const zc* BQ, int k, zc* Y, zc* AY,
+                        zc* BY, long long* bmv)
 {
+    const int n = P->n;
     if (q == 0 || k == 0) return;
     zc* c = (zc*)malloc(sizeof(zc) * (size_t)q * k);
     orc_zgemm('C', 'N', q, k, n, 1.0, BQ, n, Y, n, 0.0, c, q);
     orc_zgemm('N', 'N', n, k, q, -1.0, Q, n, c, q, 1.0, Y, n);
     if (AY) orc_zgemm('N', 'N', n, k, q, -1.0, AQ, n, c, q, 1.0, AY, n);
-    orc_zgemm('N', 'N', n, k, q, -1.0, BQ, n, c, q, 1.0, BY, n);
+    apply_b(P, k, Y, BY, bmv);
     free(c);
 }
 
 /* Makes the k columns of (Y, AY, BY) B-orthonormal: columns scaled to unit B-norm, then
  * Y <- Y U diag(g)^{-1/2} over the eigenpairs (g, U) of the B-Gram matrix Y^H B Y whose g exceeds
- * 1e-12 max(g).  Returns the number of columns kept (the leading ones of Y, AY, BY). */
-static int b_orthonormalize(int n, int k, zc* Y, zc* AY, zc* BY, int* dropped)
+ * 1e-8 max(g), and BY = B Y again.  Returns the number of columns kept (the leading ones). */
+static int b_orthonormalize(const pencil_t* P, int k, zc* Y, zc* AY, zc* BY, int* dropped, long long* bmv)
 {
+    const int n = P->n;
     if (k == 0) return 0;
     for (int j = 0; j < k; ++j) {
         double s = 0;
@@ -120,19 +130,20 @@ static int b_orthonormalize(int n, int k, zc* Y, zc* AY, zc* BY, int* dropped)
     /* keep the largest eigenvalues; T = U(:, keep) diag(g)^{-1/2}, in descending order of g */
     zc* T = (zc*)calloc((size_t)k * k, sizeof(zc));
     for (int c = k - 1; c >= 0; --c) {
-        if (!(g[c] > 1e-12 * gmax)) break;
+        if (!(g[c] > 1e-8 * gmax)) break;
         const double s = 1.0 / sqrt(g[c]);
         for (int i = 0; i < k; ++i) T[IDX(i, kept, k)] = U[IDX(i, c, k)] * s;
         ++kept;
     }
     *dropped += k - kept;
     zc* tmp = (zc*)malloc(sizeof(zc) * (size_t)n * (kept > 0 ? kept : 1));
-    zc* mats[3] = {Y, AY, BY};
-    for (int t = 0; t < 3; ++t) {
+    zc* mats[2] = {Y, AY};
+    for (int t = 0; t < 2; ++t) {
         if (!mats[t] || kept == 0) continue;
         orc_zgemm('N', 'N', n, kept, k, 1.0, mats[t], n, T, k, 0.0, tmp, n);
         memcpy(mats[t], tmp, sizeof(zc) * (size_t)n * kept);
     }
+    apply_b(P, kept, Y, BY, bmv);   /* B Y of the new block, formed again */
     free(G); free(U); free(g); free(T); free(tmp);
     return kept;
 }
@@ -161,7 +172,7 @@ static int lobpcg_core(const pencil_t* P, int bs, int nev, double thr, int maxit
     /* X B-orthonormal (two passes), then A X */
     for (int pass = 0; pass < 2; ++pass) {
         apply_b(P, bs, Z, BZ, &st->bmatvecs);
-        if (b_orthonormalize(n, bs, Z, NULL, BZ, &st->dropped) < bs) { status = 4; goto done; }
+        if (b_orthonormalize(P, bs, Z, NULL, BZ, &st->dropped, &st->bmatvecs) < bs) { status = 4; goto done; }
     }
     apply(P, P->Aop, P->lda, bs, Z, n, AZ, n);
     st->matvecs += bs;
@@ -169,11 +180,12 @@ static int lobpcg_core(const pencil_t* P, int bs, int nev, double thr, int maxit
     orc_zgemm('C', 'N', bs, bs, n, 1.0, Z, n, AZ, n, 0.0, G, bs);
     orc_jacobi(bs, G, bs, w, V, bs);
     {
-        zc* mats[3] = {Z, AZ, BZ};
-        for (int t = 0; t < 3; ++t) {
+        zc* mats[2] = {Z, AZ};
+        for (int t = 0; t < 2; ++t) {
             orc_zgemm('N', 'N', n, bs, bs, 1.0, mats[t], n, V, bs, 0.0, T, n);
             memcpy(mats[t], T, sizeof(zc) * nb);
         }
+        apply_b(P, bs, Z, BZ, &st->bmatvecs);
     }
     for (int j = 0; j < bs; ++j) theta[j] = w[j];
 
@@ -207,8 +219,8 @@ static int lobpcg_core(const pencil_t* P, int bs, int nev, double thr, int maxit
         /* W: B-orthogonal to X (twice), B-orthonormal; then its images */
         apply_b(P, na, W, BW, &st->bmatvecs);
         for (int pass = 0; pass < 2; ++pass) {
-            project_out(n, bs, Z, NULL, BZ, na, W, NULL, BW);
-            na = b_orthonormalize(n, na, W, NULL, BW, &st->dropped);
+            project_out(P, bs, Z, NULL, BZ, na, W, NULL, BW, &st->bmatvecs);
+            na = b_orthonormalize(P, na, W, NULL, BW, &st->dropped, &st->bmatvecs);
         }
         apply(P, P->Aop, P->lda, na, W, n, AW, n);
         st->matvecs += na;
@@ -218,9 +230,9 @@ static int lobpcg_core(const pencil_t* P, int bs, int nev, double thr, int maxit
         zc* BP = BZ + 2 * nb;
         if (np > 0) {
             for (int pass = 0; pass < 2; ++pass) {
-                project_out(n, bs, Z, AZ, BZ, np, Pp, AP, BP);
-                project_out(n, na, W, AW, BW, np, Pp, AP, BP);
-                np = b_orthonormalize(n, np, Pp, AP, BP, &st->dropped);
+                project_out(P, bs, Z, AZ, BZ, np, Pp, AP, BP, &st->bmatvecs);
+                project_out(P, na, W, AW, BW, np, Pp, AP, BP, &st->bmatvecs);
+                np = b_orthonormalize(P, np, Pp, AP, BP, &st->dropped, &st->bmatvecs);
             }
         }
         /* compact basis [X | W(:, 0:na) | P(:, 0:np)]: move P right after W */
@@ -242,25 +254,27 @@ static int lobpcg_core(const pencil_t* P, int bs, int nev, double thr, int maxit
         if (na + np > 0) {
             for (int c = 0; c < nact; ++c)
                 for (int i = 0; i < na + np; ++i) C[IDX(i, c, na + np)] = V[IDX(bs + i, act[c], k)];
-            zc* mats[3] = {Z, AZ, BZ};
-            for (int t = 0; t < 3; ++t)
+            zc* mats[2] = {Z, AZ};
+            for (int t = 0; t < 2; ++t)
                 orc_zgemm('N', 'N', n, nact, na + np, 1.0, mats[t] + IDX(0, bs, n), n, C, na + np, 0.0,
                           T + IDX(0, t * bs, n), n);
         }
         {
-            zc* mats[3] = {Z, AZ, BZ};
+            zc* mats[2] = {Z, AZ};
             zc* Xn = (zc*)malloc(sizeof(zc) * nb);
-            for (int t = 0; t < 3; ++t) {
+            for (int t = 0; t < 2; ++t) {
                 orc_zgemm('N', 'N', n, bs, k, 1.0, mats[t], n, V, k, 0.0, Xn, n);
                 memcpy(mats[t], Xn, sizeof(zc) * nb);
             }
             free(Xn);
+            apply_b(P, bs, Z, BZ, &st->bmatvecs);
         }
         np = (na + np > 0) ? nact : 0;
-        for (int t = 0; t < 3 && np > 0; ++t) {
-            zc* dst = (t == 0 ? Z : t == 1 ? AZ : BZ) + 2 * nb;
+        for (int t = 0; t < 2 && np > 0; ++t) {
+            zc* dst = (t == 0 ? Z : AZ) + 2 * nb;
             memcpy(dst, T + IDX(0, t * bs, n), sizeof(zc) * (size_t)n * np);
         }
+        if (np > 0) apply_b(P, np, Z + 2 * nb, BZ + 2 * nb, &st->bmatvecs);
     }
 done:
     for (int j = 0; j < bs; ++j) memcpy(X + IDX(0, j, ldx), Z + IDX(0, j, n), sizeof(zc) * n);
