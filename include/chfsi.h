@@ -258,6 +258,45 @@ chfsi_status chfsi_rayleigh_ritz(chfsi_handle h, int n, const void* H, int ldh, 
 chfsi_status chfsi_correlation(chfsi_handle h, int n, int m, const void* S, int lds, const void* Xp, int ldxp,
                                const void* Xc, int ldxc, void* O, int ldo, double* sin_pair, double* sin_sub);
 
+/* Block LOBPCG without preconditioner (Knyazev 2001), the paper's second solver (Section 3.1),
+ * on the library's kernels.  gen = 1 iterates on the pencil A x = lambda S x directly; gen = 0
+ * first reduces it to H = L^{-1} A L^{-H} (Section 3.2) and iterates on H (Table 2 compares the
+ * two).  Each iteration is a Rayleigh-Ritz step on [X, W, P] (Ritz block, residuals of its
+ * unconverged columns, previous directions), the basis made S-orthonormal block by block; soft
+ * locking; the iteration stops when the nev lowest pairs all meet ||A x - lambda S x|| <=
+ * tol ||A||_lo (on H: ||H y - lambda y|| <= tol ||A||_lo / sqrt(||S||_inf)), ||A||_lo the largest
+ * column norm of A.  Block size bs (0: ceil(1.05 nev), Table 3), at most maxiter iterations
+ * (Table 3: 1000).  Random start: the library's Philox block, stream 1 (in the coordinates the
+ * iteration runs in). */
+typedef struct {
+    int nev;                      /* wanted eigenpairs (lowest)                                  */
+    int bs;                       /* block size, nev <= bs <= n; 0 = ceil(1.05 nev)              */
+    int maxiter;                  /* iteration limit                                             */
+    double tol;                   /* target of ||A x - lambda S x|| / ||A||_lo                    */
+    int gen;                      /* 1: iterate on (A, S); 0: reduce to standard form first       */
+    unsigned long long seed;      /* random start block                                          */
+} chfsi_lobpcg_params;
+
+typedef struct {
+    int iters, nconv;             /* iterations taken; leading pairs converged at the end        */
+    long long matvecs, bmatvecs;  /* columns multiplied by A (or H) and by S                     */
+    int dropped;                  /* basis directions dropped as dependent                       */
+    double t_reduce, t_iterate, t_total;   /* ms: reduction, iteration, whole call             */
+} chfsi_lobpcg_stats;
+
+/* Defaults: nev 32, bs 0, maxiter 1000, tol 1e-10, gen 0, seed 0. */
+void chfsi_lobpcg_default_params(chfsi_lobpcg_params* p);
+
+/* A (n x n Hermitian), S (n x n HPD, or NULL for a standard problem; gen is then ignored), X
+ * (n x bs, ldx >= n): in = start block when x_is_guess (generalized coordinates), out = Ritz
+ * vectors with unit S-norm, ascending.  lambda, resid: host [bs], Ritz values and
+ * ||A x - lambda S x|| / ||A||_lo of the returned vectors.  CHFSI_ERR_NO_CONVERGENCE after maxiter
+ * iterations (outputs valid, stats->nconv pairs converged); CHFSI_ERR_NOT_HPD, CHFSI_ERR_NUMERIC
+ * (non-finite values, or the start block is rank deficient) as for chfsi_solve.  Synchronous. */
+chfsi_status chfsi_lobpcg(chfsi_handle h, int n, const void* A, int lda, const void* S, int lds, void* X, int ldx,
+                          int x_is_guess, double* lambda, double* resid, const chfsi_lobpcg_params* p,
+                          chfsi_lobpcg_stats* stats);
+
 /* Fills Y (n x m, device) with the library's random block: element e = i + j n of stream `stream`
  * is Philox4x64-10 (Salmon et al., SC'11) of counter (e/2, stream, 0, 0) and key (seed, 0); the
  * parity of e selects words (0,1) or (2,3); each word w gives a part 2 (w >> 11) 2^-53 - 1 in

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchfsi.so")
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "blas1.hip", "mlp.hip", "solver.hip", "api.hip", "tune.hip", "batched.hip", "eig.hip", "chol.hip", "trsm.hip", "hegst.hip", "noalloc.hip"]
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "blas1.hip", "mlp.hip", "solver.hip", "api.hip", "tune.hip", "batched.hip", "eig.hip", "chol.hip", "trsm.hip", "hegst.hip", "noalloc.hip", "lobpcg.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # packed FP32 ops are disabled: hipcc must not form v_pk_{add,mul,fma}_f32 from scalar code

@@ -59,6 +59,16 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class LobpcgParams(C.Structure):
+    _fields_ = [("nev", C.c_int), ("bs", C.c_int), ("maxiter", C.c_int), ("tol", C.c_double), ("gen", C.c_int),
+                ("seed", C.c_ulonglong)]
+
+
+class LobpcgStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("nconv", C.c_int), ("matvecs", C.c_longlong), ("bmatvecs", C.c_longlong),
+                ("dropped", C.c_int), ("t_reduce", C.c_double), ("t_iterate", C.c_double), ("t_total", C.c_double)]
+
+
 class TilePlan(C.Structure):
     _fields_ = [("bm", C.c_int), ("bn", C.c_int), ("ksplit", C.c_int), ("fused", C.c_int)]
 
@@ -78,7 +88,8 @@ EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solv
             "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string",
             "chfsi_filter_kernel_time", "chfsi_autotune_filter", "chfsi_set_filter_plan",
             "chfsi_filter_launch_log", "chfsi_set_batched_plan", "chfsi_autotune_batched",
-            "chfsi_batched_info", "chfsi_filter_noalloc", "chfsi_correlation"]
+            "chfsi_batched_info", "chfsi_filter_noalloc", "chfsi_correlation", "chfsi_lobpcg",
+            "chfsi_lobpcg_default_params"]
 
 
 def load():
@@ -99,6 +110,9 @@ def load():
     lib.chfsi_filter.argtypes = [vp, i, vp, i, vp, i, i, vp, i, d, d, d, i]
     lib.chfsi_filter_noalloc.argtypes = [vp, i, vp, i, vp, i, i, i, d, d, d]
     lib.chfsi_correlation.argtypes = [vp, i, i, vp, i, vp, i, vp, i, vp, i, vp, vp]
+    lib.chfsi_lobpcg_default_params.argtypes = [C.POINTER(LobpcgParams)]
+    lib.chfsi_lobpcg_default_params.restype = None
+    lib.chfsi_lobpcg.argtypes = [vp, i, vp, i, vp, i, vp, i, i, vp, vp, C.POINTER(LobpcgParams), C.POINTER(LobpcgStats)]
     lib.chfsi_reduce.argtypes = [vp, i, vp, i, vp, i, vp, vp]
     lib.chfsi_lanczos.argtypes = [vp, i, vp, i, i, u, vp, vp, vp, vp]
     lib.chfsi_orthonormalize.argtypes = [vp, i, i, vp, i, i, vp, i]
@@ -360,6 +374,23 @@ class Handle:
                                                Xp.shape[-1], _ptr(Xc), Xc.shape[-1], _ptr(O), m, sp.ctypes.data,
                                                ss.ctypes.data), "chfsi_correlation")
         return O, sp, ss
+
+    def lobpcg(self, A, S, X, x_is_guess: bool, nev: int, bs: int = 0, tol: float = 1e-10, maxiter: int = 1000,
+               gen: bool = False, seed: int = 0, n: Optional[int] = None, raise_on_error: bool = True) -> "SolveResult":
+        """chfsi_lobpcg: X (torch, bs columns) in/out; returns the Ritz values, residuals and stats."""
+        n = A.shape[-1] if n is None else n
+        p = LobpcgParams()
+        self.lib.chfsi_lobpcg_default_params(C.byref(p))
+        p.nev, p.bs, p.tol, p.maxiter, p.gen, p.seed = nev, bs, tol, maxiter, 1 if gen else 0, seed
+        m = X.shape[0]
+        lam, res = np.zeros(m), np.zeros(m)
+        st = LobpcgStats()
+        s = self.lib.chfsi_lobpcg(self.h, n, _ptr(A), A.shape[-1], _ptr(S), 0 if S is None else S.shape[-1], _ptr(X),
+                                  X.shape[-1], 1 if x_is_guess else 0, lam.ctypes.data, res.ctypes.data, C.byref(p),
+                                  C.byref(st))
+        if raise_on_error and s not in (SUCCESS, ERR_NO_CONVERGENCE):
+            raise ChfsiError(s, "chfsi_lobpcg")
+        return SolveResult(int(s), lam, res, {f: getattr(st, f) for f, _ in LobpcgStats._fields_})
 
     def random_block(self, seed: int, stream: int, n: int, m: int):
         import torch

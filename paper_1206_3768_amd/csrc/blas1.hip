@@ -320,6 +320,46 @@ __global__ void k_scale_cols_inv(int n, int m, zd* Y, int ldy, const double* nrm
     }
 }
 
+// Y[:, j] *= 1/sqrt(d[j]) (0 when d[j] <= 0): columns scaled to unit norm from their squared norms
+__global__ void k_scale_cols_rsqrt(int n, int m, zd* Y, int ldy, const double* d)
+{
+    const size_t total = (size_t)n * m;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        const double s = d[j] > 0 ? 1.0 / sqrt(d[j]) : 0.0;
+        zd v = Y[(size_t)i + (size_t)j * ldy];
+        Y[(size_t)i + (size_t)j * ldy] = make_double2(v.x * s, v.y * s);
+    }
+}
+
+// W[:, c] = AX[:, idx[c]] - theta[idx[c]] BX[:, idx[c]]: the residuals of the selected columns
+__global__ void k_residual_gather(int n, int na, const zd* AX, int lda, const zd* BX, int ldb, const double* theta,
+                                  const int* idx, zd* W, int ldw)
+{
+    const size_t total = (size_t)n * na;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), c = (int)(e / n);
+        const int j = idx[c];
+        const double t = theta[j];
+        const zd a = AX[(size_t)i + (size_t)j * lda], b = BX[(size_t)i + (size_t)j * ldb];
+        W[(size_t)i + (size_t)c * ldw] = make_double2(a.x - t * b.x, a.y - t * b.y);
+    }
+}
+
+// T[:, c] = U[:, k-1-c] / sqrt(g[k-1-c]) for c < kept (g ascending): the kept eigenvectors of a
+// Gram matrix, largest first, scaled so that Y T has orthonormal columns
+__global__ void k_orth_factor(int k, int kept, const zd* U, int ldu, const double* g, zd* T, int ldt)
+{
+    const size_t total = (size_t)k * kept;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % k), c = (int)(e / k);
+        const int src = k - 1 - c;
+        const double s = 1.0 / sqrt(g[src]);
+        const zd u = U[(size_t)i + (size_t)src * ldu];
+        T[(size_t)i + (size_t)c * ldt] = make_double2(u.x * s, u.y * s);
+    }
+}
+
 __global__ void k_add_diag(int m, zd* G, int ldg, const double* shift, double factor)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,6 +565,29 @@ int launch_residual_norms(hipStream_t s, int n, int m, const zd* HY, int ldhy, c
 {
     if (m <= 0) return 0;
     hipLaunchKernelGGL(k_residual_norms, dim3(m), dim3(256), 0, s, n, HY, ldhy, Y, ldy, theta, r);
+    return (int)hipGetLastError();
+}
+
+int launch_scale_cols_rsqrt(hipStream_t s, int n, int m, zd* Y, int ldy, const double* d)
+{
+    if (n <= 0 || m <= 0) return 0;
+    hipLaunchKernelGGL(k_scale_cols_rsqrt, dim3(grid_for((size_t)n * m)), dim3(256), 0, s, n, m, Y, ldy, d);
+    return (int)hipGetLastError();
+}
+
+int launch_residual_gather(hipStream_t s, int n, int na, const zd* AX, int lda, const zd* BX, int ldb,
+                           const double* theta, const int* idx, zd* W, int ldw)
+{
+    if (n <= 0 || na <= 0) return 0;
+    hipLaunchKernelGGL(k_residual_gather, dim3(grid_for((size_t)n * na)), dim3(256), 0, s, n, na, AX, lda, BX, ldb,
+                       theta, idx, W, ldw);
+    return (int)hipGetLastError();
+}
+
+int launch_orth_factor(hipStream_t s, int k, int kept, const zd* U, int ldu, const double* g, zd* T, int ldt)
+{
+    if (k <= 0 || kept <= 0) return 0;
+    hipLaunchKernelGGL(k_orth_factor, dim3(grid_for((size_t)k * kept)), dim3(256), 0, s, k, kept, U, ldu, g, T, ldt);
     return (int)hipGetLastError();
 }
 

@@ -115,6 +115,13 @@ int launch_residual_norms(hipStream_t s, int n, int m, const zd* HY, int ldhy, c
 int launch_colnorms(hipStream_t s, int n, int m, const zd* Y, int ldy, double* r);
 // d[j] = Re(A[:, j]^H B[:, j])  (d device, m doubles)
 int launch_pair_dots(hipStream_t s, int n, int m, const zd* A, int lda, const zd* B, int ldb, double* d);
+// Y[:, j] *= 1/sqrt(d[j]) (0 when d[j] <= 0), d device
+int launch_scale_cols_rsqrt(hipStream_t s, int n, int m, zd* Y, int ldy, const double* d);
+// W[:, c] = AX[:, idx[c]] - theta[idx[c]] BX[:, idx[c]] for c < na (theta, idx device)
+int launch_residual_gather(hipStream_t s, int n, int na, const zd* AX, int lda, const zd* BX, int ldb,
+                           const double* theta, const int* idx, zd* W, int ldw);
+// T[:, c] = U[:, k-1-c] / sqrt(g[k-1-c]) for c < kept (g ascending, device)
+int launch_orth_factor(hipStream_t s, int k, int kept, const zd* U, int ldu, const double* g, zd* T, int ldt);
 // D[:, j] = Xc[:, j] - O_jj Xp[:, j]
 int launch_sub_diag_scaled(hipStream_t s, int n, int m, const zd* Xc, int ldc, const zd* Xp, int ldp, const zd* O,
                            int ldo, zd* D, int ldd);

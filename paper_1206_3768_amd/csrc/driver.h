@@ -85,6 +85,7 @@ struct chfsi_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
     Arena ws;
+    Arena lob;                     // LOBPCG blocks beyond the solver workspace
     PhaseTimer timer;
     std::vector<double> trace;
     float* model = nullptr;        // device: MLP parameters followed by 10 normalisation constants

@@ -95,8 +95,15 @@ __global__ __launch_bounds__(256) void k_eig_compress(int k, int M, const zd* __
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % M), j = (int)(e / M);
         zd g = make_double2(0.0, 0.0);
-        if (i < k && j < k) g = G[(size_t)act[i] + (size_t)act[j] * ldg];
-        else if (i == j) g.x = PAD;
+        if (i < k && j < k) {
+            // the Hermitian part (G + G^H) / 2: a Gram or Rayleigh quotient whose factors were
+            // updated rather than recomputed is Hermitian only up to their drift, and an
+            // anti-Hermitian remainder above the stopping level would never be rotated away
+            const zd a = G[(size_t)act[i] + (size_t)act[j] * ldg], b = G[(size_t)act[j] + (size_t)act[i] * ldg];
+            g = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+        } else if (i == j) {
+            g.x = PAD;
+        }
         if (i == j) g.y = 0.0;
         Gp[e] = g;
         Wp[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
@@ -350,8 +357,8 @@ size_t eig_work_bytes(int m)
 }
 
 // Eigen-decomposition G = W diag(theta) W^H of the Hermitian m x m matrix G (device, leading
-// dimension ldg): on return G holds W (columns ascending in theta), theta[m] (device) the
-// eigenvalues.  Indices whose whole off-diagonal row is below the stopping threshold are already
+// dimension ldg; its Hermitian part (G + G^H) / 2 is decomposed): on return G holds W (columns
+// ascending in theta), theta[m] (device) the eigenvalues.  Indices whose whole off-diagonal row is below the stopping threshold are already
 // eigenpairs of G to that accuracy (deflated): block Jacobi runs on the remaining k x k part only,
 // which in the late loops of a solve is a small fraction of m.  work: eig_work_bytes(m) bytes of
 // device memory; host: eig_host_doubles(m) doubles of host memory (pinned for speed).

@@ -210,6 +210,7 @@ chfsi_status chfsi_destroy(chfsi_handle h)
     (void)hipStreamSynchronize(h->stream);
     for (auto& l : h->lanes) (void)hipStreamSynchronize(l.st);
     if (h->ws.base) (void)hipFree(h->ws.base);
+    if (h->lob.base) (void)hipFree(h->lob.base);
     for (auto& a : h->barena)
         if (a.base) (void)hipFree(a.base);
     h->pin.release();
