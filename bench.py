@@ -315,6 +315,57 @@ def bench_seq2048(h, steps: int = 9) -> dict:
     return out
 
 
+def bench_lobpcg(h, kappa: float = 1e6, maxiter_gen: int = 300) -> dict:
+    """Table 2's comparison on a synthetic pencil: block LOBPCG iterating on the pencil (GEN) and on
+    the reduced problem (STD, reduction included in its time), tolerances 1e-6, 1e-8, 1e-10, from a
+    random block and from the previous cycle's eigenvectors; ChFSI on the same problem beside it.
+    Cycle 1 of the n = 2048 sequence with an overlap of condition number `kappa`, nev 128, block
+    1.05 nev (Table 3).  GEN runs are capped at `maxiter_gen` iterations (status 3 when they stop)."""
+    import torch
+    from paper_1206_3768_amd import chfsi, synth
+    spec = synth.config_ill_conditioned(kappa=kappa, cycles=2)
+    pens = list(synth.sequence(spec))
+    nev = spec.nev
+    bs = int(np.ceil(1.05 * nev))
+    dA0, dA1 = chfsi.to_device(pens[0].A), chfsi.to_device(pens[1].A)
+    dS = chfsi.to_device(pens[0].S)
+    # the approximate start: cycle 0's eigenvectors (STD LOBPCG at 1e-10)
+    X0 = torch.zeros((bs, spec.n), dtype=torch.complex128, device="cuda")
+    r0 = h.lobpcg(dA0, dS, X0, False, nev=nev, tol=1e-10, seed=1)
+    out = {"workload": f"n={spec.n} generalized, kappa(S)={kappa:g}, cycle 1 of the sequence, nev {nev}, block {bs}",
+           "cycle0_status": r0.status}
+    work = X0.clone()
+    for tol in (1e-6, 1e-8, 1e-10):
+        for start in ("random", "approx"):
+            for gen in (False, True):
+                work.copy_(X0)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = h.lobpcg(dA1, dS, work, start == "approx", nev=nev, tol=tol, gen=gen, seed=2,
+                             maxiter=maxiter_gen if gen else 1000, raise_on_error=False)
+                ms = (time.perf_counter() - t) * 1e3
+                key = f"tol{tol:g}_{start}_{'gen' if gen else 'std'}"
+                out[key] = {"status": r.status, "ms": round(ms, 1), "iters": r.stats["iters"],
+                            "matvecs": r.stats["matvecs"], "bmatvecs": r.stats["bmatvecs"],
+                            "nconv": r.stats["nconv"], "restarts": r.stats["restarts"],
+                            "max_resid": float(np.max(r.resid[:nev]))}
+                log(f"LOBPCG {key}: status {r.status}, {ms:.0f} ms, {r.stats['iters']} iterations")
+    # ChFSI on the same cycle, same starts, tolerance 1e-10
+    m = spec.nev + spec.nex
+    for start in ("random", "approx"):
+        Xc = torch.zeros((m, spec.n), dtype=torch.complex128, device="cuda")
+        if start == "approx":
+            Xc[:bs].copy_(X0)
+            Xc[bs:].copy_(h.random_block(3, 1, spec.n, m - bs))
+        prm = chfsi.default_params(nev=nev, nex=spec.nex, deg=spec.deg, tol=1e-10, seed=2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = h.solve(dA1, dS, Xc, start == "approx", prm, raise_on_error=False)
+        out[f"chfsi_tol1e-10_{start}"] = {"status": r.status, "ms": round((time.perf_counter() - t) * 1e3, 1),
+                                         "loops": r.stats["loops"], "matvecs": r.stats["matvecs"]}
+    return out
+
+
 def bench_kpoints(h, count: int = 32) -> dict:
     """Batched SCF cycle: `count` k-point problems (n uniform in [1500, 6000], nev = ceil(0.06 n),
     nex = ceil(0.2 nev), warm start from the unperturbed eigenvectors, perturbation 1e-3), solved
@@ -527,6 +578,8 @@ def main() -> int:
         if args.workload != "seq2048":
             log("n=2048 sequence ...")
             out["seq2048"] = bench_seq2048(seq.h)
+        log("LOBPCG GEN vs STD (n=2048, kappa 1e6) ...")
+        out["lobpcg_gen_vs_std"] = bench_lobpcg(seq.h)
         log("k-point batch ...")
         out["batched_kpoints"] = bench_kpoints(seq.h)
         log("learned degree (n=4096, 20 cycles) ...")

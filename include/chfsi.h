@@ -282,6 +282,8 @@ typedef struct {
     long long matvecs, bmatvecs;  /* columns multiplied by A (or H) and by S                     */
     int dropped;                  /* basis directions dropped as dependent                       */
     double t_reduce, t_iterate, t_total;   /* ms: reduction, iteration, whole call             */
+    int restarts;                 /* steps taken without the previous directions P, because the  */
+                                  /* eigensolver of their Gram matrix did not converge          */
 } chfsi_lobpcg_stats;
 
 /* Defaults: nev 32, bs 0, maxiter 1000, tol 1e-10, gen 0, seed 0. */

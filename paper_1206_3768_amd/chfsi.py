@@ -66,7 +66,8 @@ class LobpcgParams(C.Structure):
 
 class LobpcgStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("nconv", C.c_int), ("matvecs", C.c_longlong), ("bmatvecs", C.c_longlong),
-                ("dropped", C.c_int), ("t_reduce", C.c_double), ("t_iterate", C.c_double), ("t_total", C.c_double)]
+                ("dropped", C.c_int), ("t_reduce", C.c_double), ("t_iterate", C.c_double), ("t_total", C.c_double),
+                ("restarts", C.c_int)]
 
 
 class TilePlan(C.Structure):

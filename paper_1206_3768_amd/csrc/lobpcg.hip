@@ -62,7 +62,7 @@ struct Lob {
     std::vector<double> ehost;
     GemmWs gw;
     long long matvecs = 0, bmatvecs = 0;
-    int dropped = 0;
+    int dropped = 0, restarts = 0;
 
     int gemm(int opa, int opb, int m, int ncol, int k, double al, const zd* X, int ldx, const zd* Y, int ldy, double be,
              zd* Cc, int ldc)
@@ -104,6 +104,7 @@ struct Lob {
 
     // Makes the k columns of (Y, AY) B-orthonormal (AY may be null; BY == Y when B = I) and forms
     // BY = B Y again; *kept receives the number of columns kept, which are the leading ones.
+    // CHFSI_ERR_NO_CONVERGENCE when the eigensolver of the Gram matrix does not converge.
     chfsi_status b_orthonormalize(int k, zd* Y, zd* AY, zd* BY, int* kept)
     {
         *kept = 0;
@@ -134,9 +135,11 @@ struct Lob {
             *kept = k;
             return apply_b(k, Y, BY);
         }
+        // the columns have unit B-norm, so the Gram matrix has a unit diagonal: an off-diagonal
+        // level of 1e-12 resolves every direction kept (eigenvalue above 1e-8 of the largest)
         int sweeps = 0;
-        const int rc = eig_jacobi(st, k, G, k, g, eigw, ehost.data(), &sweeps);
-        if (rc == -1) return CHFSI_ERR_NUMERIC;
+        const int rc = eig_jacobi(st, k, G, k, g, eigw, ehost.data(), &sweeps, 1e-12);
+        if (rc == -1) return CHFSI_ERR_NO_CONVERGENCE;   // the caller decides (P: restart without it)
         TRY(rc);
         std::vector<double> gh(k);
         TRY(hipMemcpyAsync(gh.data(), g, sizeof(double) * k, hipMemcpyDeviceToHost, st));
@@ -196,8 +199,9 @@ chfsi_status lobpcg_core(Lob& L, int nev, double thr, int maxiter, std::vector<d
     // X B-orthonormal (two passes), then A X, then Rayleigh-Ritz on X alone
     TRYS(L.apply_b(bs, L.Z, L.BZ));
     for (int pass = 0; pass < 2; ++pass) {
-        TRYS(L.b_orthonormalize(bs, L.Z, nullptr, L.bz(L.Z), &kept));
-        if (kept < bs) return CHFSI_ERR_NUMERIC;
+        const chfsi_status s = L.b_orthonormalize(bs, L.Z, nullptr, L.bz(L.Z), &kept);
+        if (s == CHFSI_ERR_NO_CONVERGENCE || (s == CHFSI_SUCCESS && kept < bs)) return CHFSI_ERR_NUMERIC;
+        TRYS(s);
     }
     TRYS(L.apply_a(bs, L.Z, L.AZ));
     TRYS(L.rayleigh_ritz(bs));
@@ -235,7 +239,9 @@ chfsi_status lobpcg_core(Lob& L, int nev, double thr, int maxiter, std::vector<d
         TRYS(L.apply_b(na, W, L.bz(W)));
         for (int pass = 0; pass < 2 && na > 0; ++pass) {
             TRYS(L.project_out(bs, L.Z, nullptr, L.bz(L.Z), na, W, nullptr, L.bz(W)));
-            TRYS(L.b_orthonormalize(na, W, nullptr, L.bz(W), &na));
+            const chfsi_status s = L.b_orthonormalize(na, W, nullptr, L.bz(W), &na);
+            if (s == CHFSI_ERR_NO_CONVERGENCE) return CHFSI_ERR_NUMERIC;
+            TRYS(s);
         }
         TRYS(L.apply_a(na, W, AW));
         // P (the previous directions, kept in Tp) right after W, off X and W, B-orthonormal
@@ -248,7 +254,13 @@ chfsi_status lobpcg_core(Lob& L, int nev, double thr, int maxiter, std::vector<d
             for (int pass = 0; pass < 2 && np > 0; ++pass) {
                 TRYS(L.project_out(bs, L.Z, L.AZ, L.bz(L.Z), np, P, AP, L.bz(P)));
                 TRYS(L.project_out(na, W, AW, L.bz(W), np, P, AP, L.bz(P)));
-                TRYS(L.b_orthonormalize(np, P, AP, L.bz(P), &np));
+                const chfsi_status s = L.b_orthonormalize(np, P, AP, L.bz(P), &np);
+                if (s == CHFSI_ERR_NO_CONVERGENCE) {   // restart: this step without the directions
+                    np = 0;
+                    ++L.restarts;
+                    break;
+                }
+                TRYS(s);
             }
         }
         const int k = bs + na + np;
@@ -380,6 +392,7 @@ extern "C" chfsi_status chfsi_lobpcg(chfsi_handle h, int n, const void* Av, int 
     stt.matvecs = L.matvecs;
     stt.bmatvecs = L.bmatvecs;
     stt.dropped = L.dropped;
+    stt.restarts = L.restarts;
     if (status != CHFSI_SUCCESS && status != CHFSI_ERR_NO_CONVERGENCE) {
         stt.t_total = now_ms() - t0;
         if (stats) *stats = stt;
