@@ -444,46 +444,52 @@ def bench_kpoints(h, count: int = 32) -> dict:
 
 
 def bench_learned_degree(h, cycles: int = 20) -> dict:
-    """Learned per-vector degree against every fixed degree and the analytic rule (same margin) on
-    the held-out seed 0 of the n = 4096 standard sequence (warm cycles 1 .. cycles-1), FP64 and FP32
+    """Learned per-vector degree on the held-out seed 0 of the n = 4096 standard sequence (warm
+    cycles 1 .. cycles-1), against the analytic rule it falls back to (with the same margin and
+    without one) and every fixed degree; the margin and the best fixed degree come from the
+    network's selection seed (degree_model_meta.json), never from this sequence.  FP64 and FP32
     filters."""
     from paper_1206_3768_amd import chfsi, degree_model, sequence, synth
     blob = degree_model.load()
     if blob is None:
         return {"skipped": "no trained network"}
+    info = degree_model.meta()
+    margin = int(info.get("margin", degree_model.LEARNED_MARGIN))
+    margin_an = int(info.get("analytic_margin", margin))
+    best = int(info.get("best_fixed_degree", 20))
     h.set_degree_model(blob)
-    seq = sequence.Sequence(synth.config_learned_degree(seed=0, n=4096, cycles=cycles), handle=h)
-    margin = degree_model.LEARNED_MARGIN
+    seq = sequence.Sequence(synth.config_learned_degree(seed=degree_model.EVAL_SEED, n=4096, cycles=cycles), handle=h)
     res = {}
-    for d in (8, 12, 16, 20, 25):
+    for d in degree_model.FIXED_DEGREES:
         res[f"fixed{d}"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=d)
-    res["analytic"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=0)
-    res[f"analytic+{margin}"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=margin)
-    res["learned"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED)
-    for d in (16, 20, 25):
-        res[f"fixed{d}_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=d, precision=chfsi.FP32)
+    for mg in sorted({0, margin, margin_an}):
+        res[f"analytic+{mg}"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=mg)
+    res["learned"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED, margin=margin)
+    res[f"fixed{best}_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_FIXED, deg=best, precision=chfsi.FP32)
     res[f"analytic+{margin}_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_ANALYTIC, margin=margin,
                                                              precision=chfsi.FP32)
-    res["learned_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED, precision=chfsi.FP32)
+    res["learned_fp32"] = degree_model.run_policy(h, seq, chfsi.DEG_LEARNED, margin=margin, precision=chfsi.FP32)
     h.set_degree_model(None)
     out = {k: {"time_to_solution_ms": round(v["ms"], 1), "matvecs": v["matvecs"], "loops": v["loops"],
                "filter_ms": round(v["filter_ms"], 1), "all_converged": v["ok"], "max_resid": v["max_resid"]}
            for k, v in res.items()}
-    fixed64 = [k for k in res if k.startswith("fixed") and not k.endswith("fp32")]
-    best = min(fixed64, key=lambda k: res[k]["ms"])
-    best32 = min((k for k in res if k.startswith("fixed") and k.endswith("fp32")), key=lambda k: res[k]["ms"])
     an = f"analytic+{margin}"
+    ans = f"analytic+{margin_an}"
+    post = min((f"fixed{d}" for d in degree_model.FIXED_DEGREES), key=lambda k: res[k]["ms"])
     out["margin"] = margin
-    out["best_fixed"] = best
-    out["learned_vs_best_fixed_time"] = round(res[best]["ms"] / res["learned"]["ms"], 3)
-    out["learned_vs_best_fixed_matvecs"] = round(res[best]["matvecs"] / res["learned"]["matvecs"], 3)
-    out["learned_vs_analytic_time"] = round(res[an]["ms"] / res["learned"]["ms"], 3)
-    out["learned_vs_analytic_matvecs"] = round(res[an]["matvecs"] / res["learned"]["matvecs"], 3)
-    out["best_fixed_fp32"] = best32
-    out["learned_fp32_vs_best_fixed_fp64_time"] = round(res[best]["ms"] / res["learned_fp32"]["ms"], 3)
-    out["learned_fp32_vs_best_fixed_fp32_time"] = round(res[best32]["ms"] / res["learned_fp32"]["ms"], 3)
+    out["selection"] = {"seed": info.get("selection_seed"), "best_fixed": f"fixed{best}",
+                        "analytic_margin": margin_an, "train_seeds": info.get("train_seeds"),
+                        "train_cycles": info.get("cycles")}
+    out["learned_vs_analytic_selected_margin_time"] = round(res[ans]["ms"] / res["learned"]["ms"], 3)
+    out["learned_vs_analytic_selected_margin_matvecs"] = round(res[ans]["matvecs"] / res["learned"]["matvecs"], 3)
+    out["best_fixed_on_this_sequence"] = post
+    out["learned_vs_selected_fixed_time"] = round(res[f"fixed{best}"]["ms"] / res["learned"]["ms"], 3)
+    out["learned_vs_selected_fixed_matvecs"] = round(res[f"fixed{best}"]["matvecs"] / res["learned"]["matvecs"], 3)
+    out["learned_vs_analytic_same_margin_time"] = round(res[an]["ms"] / res["learned"]["ms"], 3)
+    out["learned_vs_analytic_same_margin_matvecs"] = round(res[an]["matvecs"] / res["learned"]["matvecs"], 3)
+    out["learned_fp32_vs_selected_fixed_fp64_time"] = round(res[f"fixed{best}"]["ms"] / res["learned_fp32"]["ms"], 3)
     out["learned_fp32_vs_analytic_fp32_time"] = round(res[an + "_fp32"]["ms"] / res["learned_fp32"]["ms"], 3)
-    out["workload"] = f"n=4096 standard sequence, seed 0, warm cycles 1..{cycles - 1}, nev 256, nex 64"
+    out["workload"] = f"n=4096 standard sequence, seed 0 (held out), warm cycles 1..{cycles - 1}, nev 256, nex 64"
     return out
 
 
