@@ -95,6 +95,7 @@ typedef struct {
     double t_filter_kernels;      /* ms: hipEvent-timed main filter kernel launches (summed)    */
     double t_filter_steps;        /* ms: the same launches plus their split-K reduce kernels    */
     int status;                   /* chfsi_status of this solve                                 */
+    int factor_reused;            /* 1: S equal to the last factored overlap, its factor reused  */
 } chfsi_stats;
 
 /* One problem of a batch (chfsi_solve_batched); same meaning as chfsi_solve's arguments. */
@@ -131,6 +132,10 @@ chfsi_status chfsi_destroy(chfsi_handle h);
  *   lambda   host [m]: ascending Ritz values; the first nev converged.
  *   resid    host [m]: ||A x_i - lambda_i S x_i||_2 / ||A||_lo.
  *   p        parameters (NULL = defaults); stats (nullable) receives counters and phase times.
+ * The handle keeps the Cholesky factor of the last overlap it factored, with a copy of that S
+ * (2 n^2 complex elements of device memory): a solve whose S equals it bit for bit (the overlap of
+ * a sequence whose basis does not change) reuses the factor and only forms H; any other S is
+ * factored again (stats->factor_reused says which).
  * Returns CHFSI_ERR_NOT_HPD if S is not positive definite, CHFSI_ERR_NO_CONVERGENCE when
  * max_loops is reached (stats->nlocked pairs at the front of X, lambda, resid are valid),
  * CHFSI_ERR_NUMERIC on NaN/Inf or QR breakdown. */

@@ -53,7 +53,7 @@ class Stats(C.Structure):
                 ("t_back", C.c_double), ("t_total", C.c_double), ("mu1", C.c_double), ("a", C.c_double),
                 ("b", C.c_double), ("norm_a", C.c_double), ("lanczos_steps", C.c_int),
                 ("precision_switches", C.c_int), ("filter_launches", C.c_int), ("t_filter_kernels", C.c_double),
-                ("t_filter_steps", C.c_double), ("status", C.c_int)]
+                ("t_filter_steps", C.c_double), ("status", C.c_int), ("factor_reused", C.c_int)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

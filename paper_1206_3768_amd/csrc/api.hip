@@ -241,6 +241,60 @@ static inline void mark(SolveState& s, int phase, hipStream_t st, bool begin)
     if (s.tm) s.tm->mark(phase, st, begin);
 }
 
+// The handle's cache of the last overlap's Cholesky factor: [copy of S | L | inverses of L's
+// 64 x 64 diagonal blocks], all for order fc_n.
+struct FactorCache { zd *S, *L, *dinv; };
+size_t factor_cache_bytes(int n) { return (2 * (size_t)n * n + tri_dinv_elems(n)) * sizeof(zd); }
+FactorCache factor_cache(chfsi_handle h, int n)
+{
+    zd* base = (zd*)h->fc.base;
+    const size_t nn = (size_t)n * n;
+    return {base, base + nn, base + 2 * nn};
+}
+
+// Reduction to standard form with the handle's factor cache: when S equals (bit for bit) the
+// overlap of the cached factor, the Cholesky factorisation is skipped and only H = L^{-1} A L^{-H}
+// is formed; otherwise S is factored as usual and the cache takes S, L and the block inverses
+// (valid once the factorisation is known to have succeeded, see st_init_complete).
+chfsi_status reduce_with_cache(chfsi_handle h, SolveState& s)
+{
+    hipStream_t st = h->stream;
+    SolveBufs& b = s.b;
+    const int n = s.n;
+    if (h->fc_enabled && h->fc_n == n && h->fc.base) {
+        const FactorCache fc = factor_cache(h, n);
+        int* dflag = b.info + 12;
+        TRY(hipMemsetAsync(dflag, 0, sizeof(int), st));
+        TRY(launch_any_diff(st, n, s.S, s.lds, fc.S, n, dflag));
+        TRY(hipMemcpyAsync(&s.hi[1], dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+        TRY(hipStreamSynchronize(st));
+        if (s.hi[1] == 0) {
+            TRY(launch_zlacpy(st, n, n, fc.L, n, b.L, n));
+            TRY(hipMemcpyAsync(b.dinvL, fc.dinv, sizeof(zd) * tri_dinv_elems(n), hipMemcpyDeviceToDevice, st));
+            TRY(launch_zlacpy(st, n, n, s.A, s.lda, b.H, n));
+            TRY(hegst_lower(st, n, b.H, n, b.L, n, b.dinvL, b.hwork, b.gw));
+            s.hi[0] = 0;
+            s.fc_reused = true;
+            return CHFSI_SUCCESS;
+        }
+    }
+    TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw));
+    if (!h->fc_enabled) return CHFSI_SUCCESS;
+    h->fc_n = 0;
+    const size_t need = factor_cache_bytes(n);
+    if (h->fc.cap < need) {
+        TRY(hipStreamSynchronize(st));
+        h->fc.grow(need);
+        if (h->fc.cap < need) return CHFSI_SUCCESS;   // no room: solve without the cache
+    }
+    const FactorCache fc = factor_cache(h, n);
+    TRY(launch_zlacpy(st, n, n, s.S, s.lds, fc.S, n));
+    TRY(launch_zlacpy(st, n, n, b.L, n, fc.L, n));
+    TRY(hipMemcpyAsync(fc.dinv, b.dinvL, sizeof(zd) * tri_dinv_elems(n), hipMemcpyDeviceToDevice, st));
+    s.fc_store = true;
+    return CHFSI_SUCCESS;
+}
+
 chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
 {
     hipStream_t st = h->stream;
@@ -253,7 +307,7 @@ chfsi_status st_init_enqueue(chfsi_handle h, SolveState& s)
     s.ldh = s.lda;
     s.hi[0] = 0;
     if (s.S) {
-        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw));
+        TRYS(reduce_with_cache(h, s));
         s.H = b.H;
         s.ldh = n;
     }
@@ -288,6 +342,7 @@ chfsi_status st_init_complete(chfsi_handle h, SolveState& s)
 {
     TRY(hipStreamSynchronize(h->stream));
     if (s.S && s.hi[0] != 0) return CHFSI_ERR_NOT_HPD;
+    if (s.fc_store) h->fc_n = s.n;   // the factorisation succeeded: the cache is valid
     const chfsi_params& p = s.p;
     const int m = s.m;
     const double norm_a = s.h_norms()[0], s_inf = s.h_norms()[1];
@@ -607,6 +662,7 @@ chfsi_status solve_impl(chfsi_handle h, int n, const zd* A, int lda, const zd* S
     double ph[NPHASE];
     tm.collect(ph);
     stt.t_reduce = ph[PH_REDUCE]; stt.t_lanczos = ph[PH_LANCZOS]; stt.t_filter = ph[PH_FILTER];
+    stt.factor_reused = s.fc_reused ? 1 : 0;
     stt.t_qr = ph[PH_QR]; stt.t_rr = ph[PH_RR]; stt.t_resid = ph[PH_RESID]; stt.t_lock = ph[PH_LOCK];
     stt.t_back = ph[PH_BACK];
     stt.t_filter_kernels = h->ktimer.collect(&stt.filter_launches, &stt.t_filter_steps);

@@ -163,6 +163,7 @@ chfsi_status ensure_lanes(chfsi_handle h)
         if (ok) {
             l.sub->device = h->device;
             l.sub->stream = l.st;
+            l.sub->fc_enabled = false;   // each problem of a batch has its own overlap
             l.sub->tile_cnt_len = 1 << 16;
             ok = hipMalloc((void**)&l.sub->tile_cnt, sizeof(int) * l.sub->tile_cnt_len) == hipSuccess;
             if (!ok) l.sub->tile_cnt = nullptr;

@@ -218,6 +218,20 @@ __global__ __launch_bounds__(256) void k_residual_norms(int n, const zd* HY, int
     if (threadIdx.x == 0) r[j] = sqrt(s);
 }
 
+// *flag |= 1 if A and B (n x n) differ in any bit
+__global__ void k_any_diff(int n, const zd* __restrict__ A, int lda, const zd* __restrict__ B, int ldb, int* flag)
+{
+    const size_t total = (size_t)n * n;
+    int diff = 0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        const zd a = A[(size_t)i + (size_t)j * lda], b = B[(size_t)i + (size_t)j * ldb];
+        diff |= (__double_as_longlong(a.x) != __double_as_longlong(b.x)) |
+                (__double_as_longlong(a.y) != __double_as_longlong(b.y));
+    }
+    if (__any(diff) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 // d[j] = Re(A[:, j]^H B[:, j]), one 256-thread block per column
 __global__ __launch_bounds__(256) void k_pair_dots(int n, const zd* A, int lda, const zd* B, int ldb, double* d)
 {
@@ -565,6 +579,13 @@ int launch_residual_norms(hipStream_t s, int n, int m, const zd* HY, int ldhy, c
 {
     if (m <= 0) return 0;
     hipLaunchKernelGGL(k_residual_norms, dim3(m), dim3(256), 0, s, n, HY, ldhy, Y, ldy, theta, r);
+    return (int)hipGetLastError();
+}
+
+int launch_any_diff(hipStream_t s, int n, const zd* A, int lda, const zd* B, int ldb, int* flag)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_any_diff, dim3(grid_for((size_t)n * n)), dim3(256), 0, s, n, A, lda, B, ldb, flag);
     return (int)hipGetLastError();
 }
 

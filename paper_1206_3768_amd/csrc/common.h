@@ -115,6 +115,8 @@ int launch_residual_norms(hipStream_t s, int n, int m, const zd* HY, int ldhy, c
 int launch_colnorms(hipStream_t s, int n, int m, const zd* Y, int ldy, double* r);
 // d[j] = Re(A[:, j]^H B[:, j])  (d device, m doubles)
 int launch_pair_dots(hipStream_t s, int n, int m, const zd* A, int lda, const zd* B, int ldb, double* d);
+// *flag |= 1 (device) when A and B (n x n) differ in any bit; flag is not cleared
+int launch_any_diff(hipStream_t s, int n, const zd* A, int lda, const zd* B, int ldb, int* flag);
 // Y[:, j] *= 1/sqrt(d[j]) (0 when d[j] <= 0), d device
 int launch_scale_cols_rsqrt(hipStream_t s, int n, int m, zd* Y, int ldy, const double* d);
 // W[:, c] = AX[:, idx[c]] - theta[idx[c]] BX[:, idx[c]] for c < na (theta, idx device)

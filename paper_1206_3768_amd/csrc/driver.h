@@ -86,6 +86,11 @@ struct chfsi_handle_s {
     hipStream_t stream = nullptr;
     Arena ws;
     Arena lob;                     // LOBPCG blocks beyond the solver workspace
+    // Cholesky factor of the last overlap chfsi_solve factored: a copy of that S (n^2), its L (n^2)
+    // and the inverses of L's diagonal blocks; reused when the next S is equal element for element
+    Arena fc;
+    int fc_n = 0;                  // order of the cached factor (0: none)
+    bool fc_enabled = true;        // off for the lane handles of the batched solver
     PhaseTimer timer;
     std::vector<double> trace;
     float* model = nullptr;        // device: MLP parameters followed by 10 normalisation constants

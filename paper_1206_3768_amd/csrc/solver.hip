@@ -211,6 +211,7 @@ chfsi_status chfsi_destroy(chfsi_handle h)
     for (auto& l : h->lanes) (void)hipStreamSynchronize(l.st);
     if (h->ws.base) (void)hipFree(h->ws.base);
     if (h->lob.base) (void)hipFree(h->lob.base);
+    if (h->fc.base) (void)hipFree(h->fc.base);
     for (auto& a : h->barena)
         if (a.base) (void)hipFree(a.base);
     h->pin.release();

@@ -58,6 +58,8 @@ struct SolveState {
     double* hd = nullptr;              // pinned host doubles, see the accessors below
     int* hi = nullptr;                 // pinned host ints, see h_perm / h_flags
     bool permuted = false;             // the active columns are in the filter's degree order
+    bool fc_store = false;             // the factor of this solve's S goes to the handle's cache
+    bool fc_reused = false;            // the cached factor was reused
     // algorithm state
     const zd* H = nullptr;
     int ldh = 0;
