@@ -12,9 +12,13 @@
 //   W   = Y - 1/2 L21 H11                      (= A21 L11^{-H} - L21 H11)
 //   H21 = L22^{-1} W,   H22 = L22^{-1} A22 L22^{-H}  (the same reduction of the trailing pencil)
 // (the ordering of LAPACK's blocked xHEGST).  Phase 1 runs the panels left to right, each a few
-// small products with the stored inverse D11 = L11^{-1} and one Hermitian rank-128 update of the
-// lower triangle of the trailing matrix (one product [Y L21] [L21 Y]^H on the tiles on or below
-// the diagonal).  The solves H21 = L22^{-1} W of all panels are deferred: the block-strictly-lower
+// small products with the stored inverse D11 = L11^{-1}.  The trailing update of a panel is split:
+// the columns of the rest of its group of four panels (GW = 256 columns) are updated at once (a
+// rectangular product with K = 128), the lower triangle beyond the group only once per group, with
+// the Y blocks of its four panels: one product [Y L21] [L21 Y]^H with K = 512 on the tiles on or
+// below the diagonal.  The panels of a group read nothing beyond it, so the delayed update gives
+// the same H; it streams the trailing matrix once per 256 columns instead of once per 64, with
+// products four times as deep.  The solves H21 = L22^{-1} W of all panels are deferred: the block-strictly-lower
 // part of H is L^{-1} W with W the block-strictly-lower matrix of the panels' W (column block c of W
 // is zero in block rows <= c, and L^{-1} keeps that), which phase 2 solves recursively on halves in
 // products with a long inner dimension.  The diagonal blocks H11 of every panel are final after
@@ -28,6 +32,7 @@
 namespace {
 
 constexpr int TB = 64;   // panel width = the diagonal blocks whose inverses the Cholesky factor stores
+constexpr int GW = 4 * TB;   // panels per delayed trailing update
 
 // work (ldw x 192) <- [Y | L21 | Y] for the rank-2k update of a panel (rows rows, 64 columns each)
 __global__ void k_pack_her2k(int rows, int nb, const zd* __restrict__ Y, int ldy, const zd* __restrict__ L21, int ldl,
@@ -65,7 +70,9 @@ int solve_block_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv
 
 }  // namespace
 
-size_t hegst_work_elems(int n) { return (size_t)n * 3 * TB; }
+// work: [Y | L21 | Y] of one panel (n x 3 TB), the Y blocks of a group below it (n x GW), and
+// [Yg | Lg | Yg] of the group's delayed update (n x 3 GW)
+size_t hegst_work_elems(int n) { return (size_t)n * (3 * TB + GW + 3 * GW); }
 
 // A (n x n, lower triangle read, Hermitian) <- H = L^{-1} A L^{-H} in full (exactly Hermitian, real
 // diagonal); L lower with the inverses of its 64 x 64 diagonal blocks in dinv (chol_lower); work:
@@ -75,30 +82,54 @@ int hegst_lower(hipStream_t s, int n, zd* A, int lda, const zd* L, int ldl, cons
 {
     if (n <= 0) return 0;
     int rc = 0;
-    for (int k0 = 0; k0 < n && rc == 0; k0 += TB) {
-        const int nb = std::min(TB, n - k0), rest = n - k0 - nb;
-        zd* A11 = A + k0 + (size_t)k0 * lda;
-        const zd* D = dinv + (size_t)(k0 / TB) * TB * TB;
-        // H11 = D A11 D^H from the lower triangle of A11 (the updates leave its upper part stale)
-        if ((rc = launch_mirror_lower(s, nb, A11, lda)) != 0) break;
-        if ((rc = tri_apply(s, TA_LEFT_N, nb, nb, D, A11, lda)) != 0) break;
-        if ((rc = tri_apply(s, TA_RIGHT_C, nb, nb, D, A11, lda)) != 0) break;
-        if (rest == 0) break;
-        zd* A21 = A11 + nb;
-        zd* A22 = A21 + (size_t)nb * lda;
-        const zd* L21 = L + (k0 + nb) + (size_t)k0 * ldl;
-        if ((rc = tri_apply(s, TA_RIGHT_C, nb, rest, D, A21, lda)) != 0) break;                 // A21 L11^{-H}
-        if ((rc = launch_zgemm(s, OP_N, OP_N, rest, nb, nb, -0.5, L21, ldl, A11, lda, 1.0, A21, lda, gw)) != 0)
-            break;                                                                               // Y
-        hipLaunchKernelGGL(k_pack_her2k, dim3((unsigned)std::min<size_t>(((size_t)rest * nb + 255) / 256, 2048)),
-                           dim3(256), 0, s, rest, nb, A21, lda, L21, ldl, work, n);
+    zd* pw = work;                           // [Y | L21 | Y] of the current panel, leading dimension n
+    zd* yg = work + (size_t)n * 3 * TB;      // Y of the group's panels below the group (n x GW)
+    zd* gwk = yg + (size_t)n * GW;           // [Yg | Lg | Yg] of the group update (n x 3 GW)
+    for (int g0 = 0; g0 < n && rc == 0; g0 += GW) {
+        const int gend = std::min(n, g0 + GW);   // columns of this group: [g0, gend)
+        const int below = n - gend;               // rows beyond the group
+        for (int k0 = g0; k0 < gend && rc == 0; k0 += TB) {
+            const int nb = std::min(TB, n - k0), rest = n - k0 - nb;
+            zd* A11 = A + k0 + (size_t)k0 * lda;
+            const zd* D = dinv + (size_t)(k0 / TB) * TB * TB;
+            // H11 = D A11 D^H from the lower triangle of A11 (the updates leave its upper part stale)
+            if ((rc = launch_mirror_lower(s, nb, A11, lda)) != 0) break;
+            if ((rc = tri_apply(s, TA_LEFT_N, nb, nb, D, A11, lda)) != 0) break;
+            if ((rc = tri_apply(s, TA_RIGHT_C, nb, nb, D, A11, lda)) != 0) break;
+            if (rest == 0) break;
+            zd* A21 = A11 + nb;
+            zd* A22 = A21 + (size_t)nb * lda;
+            const zd* L21 = L + (k0 + nb) + (size_t)k0 * ldl;
+            if ((rc = tri_apply(s, TA_RIGHT_C, nb, rest, D, A21, lda)) != 0) break;                 // A21 L11^{-H}
+            if ((rc = launch_zgemm(s, OP_N, OP_N, rest, nb, nb, -0.5, L21, ldl, A11, lda, 1.0, A21, lda, gw)) != 0)
+                break;                                                                               // Y
+            const int cr = gend - (k0 + nb);   // columns of the group after this panel
+            if (cr > 0) {
+                hipLaunchKernelGGL(k_pack_her2k, dim3((unsigned)std::min<size_t>(((size_t)rest * nb + 255) / 256, 2048)),
+                                   dim3(256), 0, s, rest, nb, A21, lda, L21, ldl, pw, n);
+                if ((rc = (int)hipGetLastError()) != 0) break;
+                // A22[:, group columns] -= [Y L21] [L21 Y]_(group rows)^H  (rows below the diagonal of
+                // the group's block are not read by the later panels: written, never used)
+                if ((rc = launch_zgemm(s, OP_N, OP_C, rest, cr, 2 * nb, -1.0, pw, n, pw + (size_t)nb * n, n, 1.0, A22,
+                                       lda, gw)) != 0)
+                    break;
+            }
+            if (below > 0) {   // this panel's Y below the group, for the group's delayed update
+                if ((rc = launch_zlacpy(s, below, nb, A21 + cr, lda, yg + (size_t)(k0 - g0) * n, n)) != 0) break;
+            }
+            if ((rc = launch_zgemm(s, OP_N, OP_N, rest, nb, nb, -0.5, L21, ldl, A11, lda, 1.0, A21, lda, gw)) != 0)
+                break;                                                                               // W
+        }
+        if (rc != 0 || below <= 0) continue;
+        // delayed update of the lower triangle beyond the group: A_bb -= [Yg Lg] [Lg Yg]^H, K = 2 GW
+        const int gwid = gend - g0;
+        const zd* Lg = L + gend + (size_t)g0 * ldl;
+        hipLaunchKernelGGL(k_pack_her2k, dim3((unsigned)std::min<size_t>(((size_t)below * gwid + 255) / 256, 4096)),
+                           dim3(256), 0, s, below, gwid, yg, n, Lg, ldl, gwk, n);
         if ((rc = (int)hipGetLastError()) != 0) break;
-        // A22 -= [Y L21] [L21 Y]^H on the tiles on or below the diagonal
-        if ((rc = launch_zgemm_tri(s, TRI_C_LOWER, OP_N, OP_C, rest, rest, 2 * nb, -1.0, work, n, work + (size_t)nb * n,
-                                   n, 1.0, A22, lda)) != 0)
-            break;
-        if ((rc = launch_zgemm(s, OP_N, OP_N, rest, nb, nb, -0.5, L21, ldl, A11, lda, 1.0, A21, lda, gw)) != 0)
-            break;                                                                               // W
+        zd* Abb = A + gend + (size_t)gend * lda;
+        rc = launch_zgemm_tri(s, TRI_C_LOWER, OP_N, OP_C, below, below, 2 * gwid, -1.0, gwk, n, gwk + (size_t)gwid * n,
+                              n, 1.0, Abb, lda);
     }
     if (rc != 0) return rc;
     if ((rc = solve_block_lower(s, n, L, ldl, dinv, A, lda, gw)) != 0) return rc;              // H21 of every panel
