@@ -126,12 +126,17 @@ struct BArgs {
     int kchunk, tiles_m, tiles_n, ksplit;
 };
 
-template <int NT, bool SPLIT>
+// One filter step on a BM x BN tile (BM = BN = 32 WT), 4 waves of (16 WT) x (16 WT) outputs, each
+// a WT x WT array of 16 x 16 MFMA blocks.  WT = 2: 64 x 64 tiles (two workgroups per CU); WT = 4:
+// 128 x 128 tiles (one workgroup per CU, the whole LDS), whose waves read half the LDS bytes per
+// MFMA and whose workgroups fetch half the L2 bytes per MFMA.
+template <int NT, bool SPLIT, int WT>
 __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
 {
-    constexpr int BM = 64, BN = 64, BK = 32;
+    constexpr int BM = 32 * WT, BN = 32 * WT, BK = 32;
     constexpr int NPL = 2 * NT;                  // planes per operand
     constexpr int RS = BK + 8;                   // LDS row stride in bf16 (80 bytes)
+    constexpr int RL = BM / 64;                  // 64-row slabs a thread loads per plane
     __shared__ __attribute__((aligned(16))) uint16_t Hs[2][NPL][BM * RS];
     __shared__ __attribute__((aligned(16))) uint16_t Ys[2][NPL][BN * RS];
 
@@ -146,42 +151,54 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
     const int kb = ks * g.kchunk;
     const int ke = min(g.np, kb + g.kchunk);
     const int nstages = ke > kb ? (ke - kb) / BK : 0;
-    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int wr = (wave & 1) * (16 * WT), wc = (wave >> 1) * (16 * WT);
 
-    f4 accr[2][2], acci[2][2];
+    f4 accr[WT][WT], acci[WT][WT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < WT; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { accr[a][b][r] = 0.f; acci[a][b][r] = 0.f; }
 
-    // global -> register: thread t moves 16 bytes (8 k) of row/col t/4, chunk t%4, per plane
+    // global -> register: thread t moves 16 bytes (8 k) of row/col t/4 (+ 64 q), chunk t%4, per plane.
+    // Rows of H beyond the padded order and columns of Y beyond the padded width are clamped to the
+    // last one instead of masked: they only reach output rows / columns that are never stored, and
+    // the loads stay branch-free
     const int lrow = tid >> 2, lch = tid & 3;
-    u4v rh[NPL], ry[NPL];
+    u4v rh[RL][NPL], ry[RL][NPL];
     const size_t hps = (size_t)g.np * g.np, yps = (size_t)g.np * g.ncp;
-    auto gload = [&](int k0) {
-        const int gi = i0 + lrow, gj = j0 + lrow;
+    const uint16_t* hbase[RL];
+    const uint16_t* ybase[RL];
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) {
-            const uint16_t* hsrc = g.Hp + (size_t)p * hps + (size_t)gi * g.np + k0 + lch * 8;
-            rh[p] = gi < g.np ? *(const u4v*)hsrc : u4v{0, 0, 0, 0};
-            const uint16_t* ysrc = g.Ys + (size_t)p * yps + (size_t)gj * g.np + k0 + lch * 8;
-            ry[p] = gj < g.ncp ? *(const u4v*)ysrc : u4v{0, 0, 0, 0};
-        }
+    for (int q = 0; q < RL; ++q) {
+        const int gi = min(i0 + lrow + 64 * q, g.np - 1), gj = min(j0 + lrow + 64 * q, g.ncp - 1);
+        hbase[q] = g.Hp + (size_t)gi * g.np + lch * 8;
+        ybase[q] = g.Ys + (size_t)gj * g.np + lch * 8;
+    }
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < RL; ++q)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) {
+                rh[q][p] = *(const u4v*)(hbase[q] + (size_t)p * hps + k0);
+                ry[q][p] = *(const u4v*)(ybase[q] + (size_t)p * yps + k0);
+            }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < NPL; ++p) {
-            *(u4v*)&Hs[buf][p][lrow * RS + lch * 8] = rh[p];
-            *(u4v*)&Ys[buf][p][lrow * RS + lch * 8] = ry[p];
-        }
+        for (int q = 0; q < RL; ++q)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) {
+                *(u4v*)&Hs[buf][p][(lrow + 64 * q) * RS + lch * 8] = rh[q][p];
+                *(u4v*)&Ys[buf][p][(lrow + 64 * q) * RS + lch * 8] = ry[q][p];
+            }
     };
     auto compute = [&](int buf) {
         const int fr = lane & 15, fk = (lane >> 4) * 8;
-        u4v hf[2][NPL], yf[2][NPL];
+        u4v hf[WT][NPL], yf[WT][NPL];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < WT; ++b)
 #pragma unroll
             for (int p = 0; p < NPL; ++p) {
                 hf[b][p] = *(const u4v*)&Hs[buf][p][(wr + b * 16 + fr) * RS + fk];
@@ -193,9 +210,9 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
             for (int t = 0; t < NT; ++t) {
                 if (s + t >= NT) continue;
 #pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
+                for (int bi = 0; bi < WT; ++bi)
 #pragma unroll
-                    for (int bj = 0; bj < 2; ++bj) {
+                    for (int bj = 0; bj < WT; ++bj) {
                         const bf8 hre = __builtin_bit_cast(bf8, hf[bi][2 * s]);
                         const bf8 him = __builtin_bit_cast(bf8, hf[bi][2 * s + 1]);
                         const bf8 yre = __builtin_bit_cast(bf8, yf[bj][2 * t]);
@@ -226,9 +243,9 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
     const size_t slab = (size_t)g.n * g.ncols;
     if (SPLIT) {
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < WT; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+            for (int bj = 0; bj < WT; ++bj)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + wr + bi * 16 + (lane & 15);
@@ -238,17 +255,17 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
                             make_float2(accr[bi][bj][r], acci[bi][bj][r]);
                 }
         __threadfence();
-        __shared__ int s_last;
+        // the arrival flag lives in the (no longer read) LDS of the operands: the loop ended with a barrier
+        int* s_last = (int*)&Hs[0][0][0];
+        if (tid == 0) s_last[0] = (atomicAdd(&g.cnt[it * g.tiles_n + jt], 1) == g.ksplit - 1);
         __syncthreads();
-        if (tid == 0) s_last = (atomicAdd(&g.cnt[it * g.tiles_n + jt], 1) == g.ksplit - 1);
-        __syncthreads();
-        if (!s_last) return;
+        if (!s_last[0]) return;
         __threadfence();
     }
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < WT; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < WT; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr + bi * 16 + (lane & 15);
@@ -315,11 +332,17 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
     g.alpha = (float)fs.alpha; g.beta = (float)fs.beta; g.shift = (float)fs.shift;
     g.P = (zf*)gw.ws;
     g.cnt = gw.cnt;
-    g.tiles_m = (n + 63) / 64;
-    g.tiles_n = (ncols + 63) / 64;
+    // 128 x 128 tiles (one workgroup per CU) for the two-term split when they still give a
+    // workgroup per CU, else 64 x 64 tiles (two per CU); the three-term split's planes do not fit
+    // the LDS at 128 x 128
+    const long t128 = (long)((n + 127) / 128) * ((ncols + 127) / 128);
+    const int tile = (nterms == 2 && t128 >= 192) ? 128 : 64;
+    const long per_cu = tile == 128 ? 256 : 512;
+    g.tiles_m = (n + tile - 1) / tile;
+    g.tiles_n = (ncols + tile - 1) / tile;
     const long tiles = (long)g.tiles_m * g.tiles_n;
     int ksp = 1;
-    while (tiles * ksp < 512 && np / (2 * ksp) >= 512) ksp *= 2;
+    while (tiles * ksp < per_cu && np / (2 * ksp) >= 512) ksp *= 2;
     if (!gw.ws || !gw.cnt || tiles > gw.ncnt) ksp = 1;
     while (ksp > 1 && (size_t)ksp * n * ncols * sizeof(zf) > gw.bytes) ksp /= 2;
     int kc = (np + ksp - 1) / ksp;
@@ -329,15 +352,18 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
     const int nt = g.tiles_m * g.tiles_n * g.ksplit;
     const bool split = g.ksplit > 1;
     const hipEvent_t e1 = timed ? gw.ev_main : nullptr;
-    if (nterms == 2) {
-        if (split) launch_timed(k_filter_bf16<2, true>, dim3(nt), dim3(256), s, nullptr, e1, g);
-        else launch_timed(k_filter_bf16<2, false>, dim3(nt), dim3(256), s, nullptr, e1, g);
+    if (nterms == 2 && tile == 128) {
+        if (split) launch_timed(k_filter_bf16<2, true, 4>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        else launch_timed(k_filter_bf16<2, false, 4>, dim3(nt), dim3(256), s, nullptr, e1, g);
+    } else if (nterms == 2) {
+        if (split) launch_timed(k_filter_bf16<2, true, 2>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        else launch_timed(k_filter_bf16<2, false, 2>, dim3(nt), dim3(256), s, nullptr, e1, g);
     } else {
-        if (split) launch_timed(k_filter_bf16<3, true>, dim3(nt), dim3(256), s, nullptr, e1, g);
-        else launch_timed(k_filter_bf16<3, false>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        if (split) launch_timed(k_filter_bf16<3, true, 2>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        else launch_timed(k_filter_bf16<3, false, 2>, dim3(nt), dim3(256), s, nullptr, e1, g);
     }
     if (gw.plan_used) {
-        gw.plan_used[0] = 64; gw.plan_used[1] = 64; gw.plan_used[2] = g.ksplit; gw.plan_used[3] = split ? 2 : 0;
+        gw.plan_used[0] = tile; gw.plan_used[1] = tile; gw.plan_used[2] = g.ksplit; gw.plan_used[3] = split ? 2 : 0;
     }
     if (timed) (void)hipEventRecord(gw.ev_end, s);
     return (int)hipGetLastError();

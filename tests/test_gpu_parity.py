@@ -142,6 +142,26 @@ def test_filter_low_precision_against_fp64_oracle(hd, orc, prec, tol):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("n,m", [(4096, 768), (8192, 480)])
+def test_filter_bf16x3_wide_tiles_against_fp64_filter(hd, torch_dev, n, m):
+    """The BF16x3 filter on 128 x 128 tiles (taken when they still give a workgroup per CU: with a
+    K split at n = 4096, w = 768, without one at the n = 8192 block of the sequence) against the FP64
+    filter of the same library (itself checked against the oracle above), the two-term split's
+    tolerance 4e-3 of the largest entry."""
+    from paper_1206_3768_amd import chfsi
+    g = torch_dev.Generator(device="cuda").manual_seed(5)
+    A = torch_dev.randn((n, n), dtype=torch_dev.complex128, device="cuda", generator=g) * (1.0 / math.sqrt(2 * n))
+    A = (0.5 * (A + A.conj().T)).contiguous()
+    Y0 = torch_dev.randn((m, n), dtype=torch_dev.complex128, device="cuda", generator=g)
+    Y1, Y2 = Y0.clone(), Y0.clone()
+    hd.filter(A, Y1, -0.3, 1.2, -1.0, deg=3, prec=chfsi.FP64)
+    hd.filter(A, Y2, -0.3, 1.2, -1.0, deg=3, prec=chfsi.BF16X3)
+    log = hd.filter_launch_log()
+    assert np.all(log[:, 3] == 128)   # the wide-tile kernel ran every step
+    ref = host(Y1)
+    assert relerr(host(Y2), ref) <= 4e-3
+
+
 def test_filter_closed_form_diagonal(hd, orc):
     # diagonal H: (Y_d)_j = T_d((h_j - c)/e) / T_d((mu1 - c)/e) (Y_0)_j
     n, d = 200, 9
