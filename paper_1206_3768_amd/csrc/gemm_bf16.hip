@@ -289,6 +289,232 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
     if (SPLIT && tid == 0) g.cnt[it * g.tiles_n + jt] = 0;
 }
 
+// LDS row swizzle of the pipelined kernel: the 16-byte chunk c of tile row r (32 bf16 of k per row,
+// 64 bytes, no padding) sits at chunk position c ^ swz(r).  The 16 (or 8) rows that one MFMA
+// fragment read serves in one LDS cycle then fall on disjoint banks for 64 (or 32) banks of 4 bytes.
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// Two-term split, 128 x 128 tiles, software-pipelined.  Each of the 4 waves owns a 64 x 64 block of
+// outputs (4 x 4 MFMA blocks of 16 x 16) and moves one bf16 plane of each operand per k-stage
+// straight from global memory into LDS (global_load_lds_dwordx4: no staging registers, no LDS
+// store instructions).  Per k-stage of 32:
+//   row blocks 0..2: read the H fragment of the next row block, then the 48 products of this one;
+//   barrier (the next stage's tiles have landed, every wave is done with this stage's buffer);
+//   start the stage after next into the buffer just released, read the next stage's Y fragments
+//   and first H fragment, and run the 48 products of row block 3 meanwhile.
+// So the matrix cores always have independent products queued while LDS and memory traffic for
+// the next stage is in flight; one barrier per stage.
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_filter_bf16_p(BArgs g)
+{
+    constexpr int NPL = 4, BM = 128, BK = 32;
+    // one array per buffer: the compiler then knows which buffer a load into LDS targets and waits
+    // for it only before reads of that buffer
+    __shared__ __attribute__((aligned(1024))) uint16_t Hs0[NPL][BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint16_t Hs1[NPL][BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint16_t Ys0[NPL][BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint16_t Ys1[NPL][BM * BK];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nt = g.tiles_m * g.tiles_n * g.ksplit;
+    const int tile = xcd_remap(blockIdx.x, nt);
+    const int jt = tile % g.tiles_n;
+    const int r1 = tile / g.tiles_n;
+    const int ks = r1 % g.ksplit;
+    const int it = r1 / g.ksplit;
+    const int i0 = it * BM, j0 = jt * BM;
+    const int kb = ks * g.kchunk;
+    const int ke = min(g.np, kb + g.kchunk);
+    const int nst = ke > kb ? (ke - kb) / BK : 0;
+    const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+
+    f4 accr[4][4], acci[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { accr[a][b][r] = 0.f; acci[a][b][r] = 0.f; }
+
+    // global -> LDS: wave w moves plane w of H and of Y, 8 instructions of 16 rows x 64 bytes each;
+    // lane l serves row 16 i + l/4 at chunk position l%4.  Rows beyond the padded order / width are
+    // clamped to the last one (they reach only outputs that are never stored)
+    const int q = lane >> 2, pos = lane & 3;
+    uint32_t ho[8], yo[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = 16 * i + q, c = pos ^ swz(r);
+        ho[i] = (uint32_t)((min(i0 + r, g.np - 1) - i0) * g.np + c * 8) * 2u;
+        yo[i] = (uint32_t)((min(j0 + r, g.ncp - 1) - j0) * g.np + c * 8) * 2u;
+    }
+    const char* hplane = (const char*)(g.Hp + (size_t)wave * g.np * g.np + (size_t)i0 * g.np);
+    const char* yplane = (const char*)(g.Ys + (size_t)wave * g.np * g.ncp + (size_t)j0 * g.np);
+    auto dma = [&](uint16_t (&hs)[NPL][BM * BK], uint16_t (&ys)[NPL][BM * BK], int k0) {
+        const char* hb = hplane + 2 * (size_t)k0;
+        const char* yb = yplane + 2 * (size_t)k0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            __builtin_amdgcn_global_load_lds((const void*)(hb + ho[i]), &hs[wave][16 * i * BK], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(yb + yo[i]), &ys[wave][16 * i * BK], 16, 0, 0);
+        }
+    };
+
+    // fragment offsets (elements) of the four 16-row blocks of this wave, lane row l%16, chunk l/16
+    const int fr = lane & 15, fc = lane >> 4;
+    int hoff[4], yoff[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int rh = wr + 16 * b + fr, ry = wc + 16 * b + fr;
+        hoff[b] = rh * BK + ((fc ^ swz(rh)) << 3);
+        yoff[b] = ry * BK + ((fc ^ swz(ry)) << 3);
+    }
+    auto hread = [&](const uint16_t (&hs)[NPL][BM * BK], int b, u4v (&h)[NPL]) {
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) h[p] = *(const u4v*)&hs[p][hoff[b]];
+    };
+    auto yread = [&](const uint16_t (&ys)[NPL][BM * BK], u4v (&y)[4][NPL]) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) y[b][p] = *(const u4v*)&ys[p][yoff[b]];
+    };
+    // the 48 products of one 16-row block: term pairs (0,0), (0,1), (1,0), four real products each
+    auto mblock = [&](int bi, const u4v (&h)[NPL], const u4v (&y)[4][NPL]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (s + t >= 2) continue;
+                const bf8 hre = __builtin_bit_cast(bf8, h[2 * s]);
+                const bf8 him = __builtin_bit_cast(bf8, h[2 * s + 1]);
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) {
+                    const bf8 yre = __builtin_bit_cast(bf8, y[bj][2 * t]);
+                    const u4v ymi = y[bj][2 * t + 1];
+                    const bf8 yim = __builtin_bit_cast(bf8, ymi);
+                    const bf8 nyim = __builtin_bit_cast(bf8, ymi ^ u4v{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u});
+                    accr[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yre, hre, accr[bi][bj], 0, 0, 0);
+                    acci[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yim, hre, acci[bi][bj], 0, 0, 0);
+                    accr[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nyim, him, accr[bi][bj], 0, 0, 0);
+                    acci[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yre, him, acci[bi][bj], 0, 0, 0);
+                }
+            }
+    };
+
+    // Stage s lives in buffer s % 2.  A stage is split at its barrier into a front (row blocks 0..2)
+    // and a back (loads two stages ahead, next stage's fragments, row block 3); the loop runs
+    // back(s), front(s+1), back(s+1), front(s+2), so its trips start right after a barrier, when no
+    // load into LDS is in flight, and every buffer is static.  Scheduling barriers keep each
+    // fragment read one row block ahead of its products; the next stage's fragments are always read
+    // (on the last stage from the idle buffer, unused) so that no branch joins in-flight reads.
+    u4v yf[4][NPL], h0[NPL], h1[NPL], h2[NPL], h3[NPL];
+    // products of one row block with the next block's H fragment read after its first four
+    auto phase = [&](const uint16_t (&hs)[NPL][BM * BK], int b, const u4v (&h)[NPL], u4v (&hnext)[NPL]) {
+        mblock(b, h, yf);
+        hread(hs, b + 1, hnext);
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 44, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto front = [&](const uint16_t (&hs)[NPL][BM * BK]) {
+        phase(hs, 0, h0, h1);
+        phase(hs, 1, h1, h2);
+        phase(hs, 2, h2, h3);
+        // this thread's loads of the next stage have landed and its reads of this one are done;
+        // then every wave's
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+    auto back = [&](int s, uint16_t (&hs)[NPL][BM * BK], uint16_t (&ys)[NPL][BM * BK],
+                    const uint16_t (&hs_next)[NPL][BM * BK], const uint16_t (&ys_next)[NPL][BM * BK]) {
+        if (s + 2 < nst) dma(hs, ys, kb + (s + 2) * BK);
+        __builtin_amdgcn_sched_barrier(0);
+        u4v yn[4][NPL];
+        yread(ys_next, yn);
+        hread(hs_next, 0, h0);
+        mblock(3, h3, yf);
+        // one fragment read per two products of row block 3
+#pragma unroll
+        for (int r = 0; r < 20; ++r) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) yf[b][p] = yn[b][p];
+    };
+    if (nst > 0) {
+        dma(Hs0, Ys0, kb);
+        if (nst > 1) dma(Hs1, Ys1, kb + BK);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        yread(Ys0, yf);
+        hread(Hs0, 0, h0);
+        front(Hs0);
+        for (int s = 0; s < nst; s += 2) {
+            back(s, Hs0, Ys0, Hs1, Ys1);
+            if (s + 1 < nst) {
+                front(Hs1);
+                back(s + 1, Hs1, Ys1, Hs0, Ys0);
+                if (s + 2 < nst) front(Hs0);
+            }
+        }
+    }
+
+    const size_t slab = (size_t)g.n * g.ncols;
+    if (SPLIT) {
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + wr + bi * 16 + fr;
+                    const int j = j0 + wc + bj * 16 + fc * 4 + r;
+                    if (i < g.n && j < g.ncols)
+                        g.P[(size_t)ks * slab + (size_t)i + (size_t)j * g.n] =
+                            make_float2(accr[bi][bj][r], acci[bi][bj][r]);
+                }
+        __threadfence();
+        // arrival flag in the operands' LDS: no wave touches it after the last stage's barrier
+        int* s_last = (int*)&Hs0[0][0];
+        __syncthreads();
+        if (tid == 0) s_last[0] = (atomicAdd(&g.cnt[it * g.tiles_n + jt], 1) == g.ksplit - 1);
+        __syncthreads();
+        if (!s_last[0]) return;
+        __threadfence();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr + bi * 16 + fr;
+                const int j = j0 + wc + bj * 16 + fc * 4 + r;
+                if (i >= g.n || j >= g.ncols) continue;
+                float vr = accr[bi][bj][r], vi = acci[bi][bj][r];
+                if (SPLIT) {
+                    vr = 0.f;
+                    vi = 0.f;
+                    for (int s2 = 0; s2 < g.ksplit; ++s2) {
+                        const zf p = g.P[(size_t)s2 * slab + (size_t)i + (size_t)j * g.n];
+                        vr += p.x;
+                        vi += p.y;
+                    }
+                }
+                const zf yk = g.Yk[(size_t)i + (size_t)j * g.ldyk];
+                const zf yp = g.Yp[(size_t)i + (size_t)j * g.ldyp];
+                g.Yo[(size_t)i + (size_t)j * g.ldyo] = make_float2(g.alpha * (vr - g.shift * yk.x) + g.beta * yp.x,
+                                                                 g.alpha * (vi - g.shift * yk.y) + g.beta * yp.y);
+            }
+    if (SPLIT && tid == 0) g.cnt[it * g.tiles_n + jt] = 0;
+}
+
 inline int grid_for(size_t total)
 {
     size_t b = (total + 255) / 256;
@@ -353,8 +579,8 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
     const bool split = g.ksplit > 1;
     const hipEvent_t e1 = timed ? gw.ev_main : nullptr;
     if (nterms == 2 && tile == 128) {
-        if (split) launch_timed(k_filter_bf16<2, true, 4>, dim3(nt), dim3(256), s, nullptr, e1, g);
-        else launch_timed(k_filter_bf16<2, false, 4>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        if (split) launch_timed(k_filter_bf16_p<true>, dim3(nt), dim3(256), s, nullptr, e1, g);
+        else launch_timed(k_filter_bf16_p<false>, dim3(nt), dim3(256), s, nullptr, e1, g);
     } else if (nterms == 2) {
         if (split) launch_timed(k_filter_bf16<2, true, 2>, dim3(nt), dim3(256), s, nullptr, e1, g);
         else launch_timed(k_filter_bf16<2, false, 2>, dim3(nt), dim3(256), s, nullptr, e1, g);
