@@ -126,6 +126,16 @@ struct BArgs {
     int kchunk, tiles_m, tiles_n, ksplit;
 };
 
+// LDS row swizzle of the filter kernels: the 16-byte chunk c of tile row r (32 bf16 of k per row,
+// 64 bytes, no padding) sits at chunk position c ^ swz(r).  A 16-byte fragment read (lane l: row
+// l%16 of a 16-row block, chunk l/16) is served 32 lanes = 512 bytes per LDS cycle on gfx950
+// (measured: a plain, padded or 8-row-swizzled 64-byte row layout costs 4 extra cycles per read, a
+// linear one none).  The 32 lanes then cover rows r and r+8 with two chunks each, and the four
+// (row, chunk) pairs that share a 64-byte bank window must take four different positions: bit 1 of
+// swz flips between r and r+8, and swz takes four values on r, r+4, r+8, r+12 and on r, r+2, r+4,
+// r+6 (also conflict-free when 16 or 8 lanes are served per cycle).
+__device__ __forceinline__ int swz(int r) { return (((r >> 1) ^ (r >> 3)) & 1) | ((((r >> 2) ^ (r >> 3)) & 1) << 1); }
+
 // One filter step on a BM x BN tile (BM = BN = 32 WT), 4 waves of (16 WT) x (16 WT) outputs, each
 // a WT x WT array of 16 x 16 MFMA blocks.  WT = 2: 64 x 64 tiles (two workgroups per CU); WT = 4:
 // 128 x 128 tiles (one workgroup per CU, the whole LDS), whose waves read half the LDS bytes per
@@ -135,7 +145,7 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
 {
     constexpr int BM = 32 * WT, BN = 32 * WT, BK = 32;
     constexpr int NPL = 2 * NT;                  // planes per operand
-    constexpr int RS = BK + 8;                   // LDS row stride in bf16 (80 bytes)
+    constexpr int RS = BK;                       // LDS row stride in bf16 (64 bytes, chunks swizzled)
     constexpr int RL = BM / 64;                  // 64-row slabs a thread loads per plane
     __shared__ __attribute__((aligned(16))) uint16_t Hs[2][NPL][BM * RS];
     __shared__ __attribute__((aligned(16))) uint16_t Ys[2][NPL][BN * RS];
@@ -190,20 +200,24 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
         for (int q = 0; q < RL; ++q)
 #pragma unroll
             for (int p = 0; p < NPL; ++p) {
-                *(u4v*)&Hs[buf][p][(lrow + 64 * q) * RS + lch * 8] = rh[q][p];
-                *(u4v*)&Ys[buf][p][(lrow + 64 * q) * RS + lch * 8] = ry[q][p];
+                const int r = lrow + 64 * q, c = (lch ^ swz(r)) * 8;
+                *(u4v*)&Hs[buf][p][r * RS + c] = rh[q][p];
+                *(u4v*)&Ys[buf][p][r * RS + c] = ry[q][p];
             }
     };
     auto compute = [&](int buf) {
-        const int fr = lane & 15, fk = (lane >> 4) * 8;
+        const int fr = lane & 15, fc = lane >> 4;
         u4v hf[WT][NPL], yf[WT][NPL];
 #pragma unroll
-        for (int b = 0; b < WT; ++b)
+        for (int b = 0; b < WT; ++b) {
+            const int rh = wr + b * 16 + fr, ry = wc + b * 16 + fr;
+            const int oh = rh * RS + ((fc ^ swz(rh)) << 3), oy = ry * RS + ((fc ^ swz(ry)) << 3);
 #pragma unroll
             for (int p = 0; p < NPL; ++p) {
-                hf[b][p] = *(const u4v*)&Hs[buf][p][(wr + b * 16 + fr) * RS + fk];
-                yf[b][p] = *(const u4v*)&Ys[buf][p][(wc + b * 16 + fr) * RS + fk];
+                hf[b][p] = *(const u4v*)&Hs[buf][p][oh];
+                yf[b][p] = *(const u4v*)&Ys[buf][p][oy];
             }
+        }
 #pragma unroll
         for (int s = 0; s < NT; ++s)
 #pragma unroll
@@ -289,10 +303,6 @@ __global__ __launch_bounds__(256) void k_filter_bf16(BArgs g)
     if (SPLIT && tid == 0) g.cnt[it * g.tiles_n + jt] = 0;
 }
 
-// LDS row swizzle of the pipelined kernel: the 16-byte chunk c of tile row r (32 bf16 of k per row,
-// 64 bytes, no padding) sits at chunk position c ^ swz(r).  The 16 (or 8) rows that one MFMA
-// fragment read serves in one LDS cycle then fall on disjoint banks for 64 (or 32) banks of 4 bytes.
-__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
 // Two-term split, 128 x 128 tiles, software-pipelined.  Each of the 4 waves owns a 64 x 64 block of
 // outputs (4 x 4 MFMA blocks of 16 x 16) and moves one bf16 plane of each operand per k-stage
