@@ -81,7 +81,10 @@ def kernel_symbol(prec: int, bm: int, bn: int, mode: int) -> str:
         return f"k_zgemm<double, 0, 0, 1, {bm}, {bn}, {mode}>"
     if prec == 1:
         return f"k_zgemm<float, 0, 0, 1, {bm}, {bn}, {mode}>"
-    return f"k_filter_bf16<{2 if prec == 2 else 3}, {'true' if mode else 'false'}>"
+    split = 'true' if mode else 'false'
+    if prec == 2 and bm == 128:
+        return f"k_filter_bf16_p<{split}>"
+    return f"k_filter_bf16<{2 if prec == 2 else 3}, {split}, {bm // 32}>"
 
 
 def peak_and_products(prec: int):
