@@ -241,21 +241,36 @@ static inline void mark(SolveState& s, int phase, hipStream_t st, bool begin)
     if (s.tm) s.tm->mark(phase, st, begin);
 }
 
+// Orders up to which H = L^{-1} A L^{-H} is formed from the explicit inverse L^{-1} (two products,
+// 12 n^3 flops in three launches) rather than by the panel algorithm (4 n^3 flops in about ten
+// launches per 64 columns): below it the launches dominate.
+constexpr int EXPLICIT_REDUCTION_MAX_N = 3072;
+inline bool explicit_reduction(int n) { return n <= EXPLICIT_REDUCTION_MAX_N; }
+
 // The handle's cache of the last overlap's Cholesky factor: [copy of S | L | inverses of L's
-// 64 x 64 diagonal blocks], all for order fc_n.
-struct FactorCache { zd *S, *L, *dinv; };
-size_t factor_cache_bytes(int n) { return (2 * (size_t)n * n + tri_dinv_elems(n)) * sizeof(zd); }
+// 64 x 64 diagonal blocks], all for order fc_n, and for the orders reduced with the explicit
+// inverse also [L^{-1} | n x n product buffer].
+struct FactorCache { zd *S, *L, *dinv, *Linv, *T; };
+size_t factor_cache_bytes(int n)
+{
+    const size_t nn = (size_t)n * n;
+    return ((explicit_reduction(n) ? 4 : 2) * nn + tri_dinv_elems(n)) * sizeof(zd);
+}
 FactorCache factor_cache(chfsi_handle h, int n)
 {
     zd* base = (zd*)h->fc.base;
     const size_t nn = (size_t)n * n;
-    return {base, base + nn, base + 2 * nn};
+    zd* dinv = base + 2 * nn;
+    zd* Linv = dinv + tri_dinv_elems(n);
+    return {base, base + nn, dinv, explicit_reduction(n) ? Linv : nullptr, explicit_reduction(n) ? Linv + nn : nullptr};
 }
 
 // Reduction to standard form with the handle's factor cache: when S equals (bit for bit) the
 // overlap of the cached factor, the Cholesky factorisation is skipped and only H = L^{-1} A L^{-H}
 // is formed; otherwise S is factored as usual and the cache takes S, L and the block inverses
-// (valid once the factorisation is known to have succeeded, see st_init_complete).
+// (valid once the factorisation is known to have succeeded, see st_init_complete).  Small orders
+// form H from the cached L^{-1}, computed once per factorisation; a fresh factorisation forms H
+// the same way, so a solve that reuses the factor gives the same bits as one that does not.
 chfsi_status reduce_with_cache(chfsi_handle h, SolveState& s)
 {
     hipStream_t st = h->stream;
@@ -271,23 +286,35 @@ chfsi_status reduce_with_cache(chfsi_handle h, SolveState& s)
         if (s.hi[1] == 0) {
             TRY(launch_zlacpy(st, n, n, fc.L, n, b.L, n));
             TRY(hipMemcpyAsync(b.dinvL, fc.dinv, sizeof(zd) * tri_dinv_elems(n), hipMemcpyDeviceToDevice, st));
-            TRY(launch_zlacpy(st, n, n, s.A, s.lda, b.H, n));
-            TRY(hegst_lower(st, n, b.H, n, b.L, n, b.dinvL, b.hwork, b.gw));
+            if (fc.Linv) {
+                TRY(hegst_explicit(st, n, s.A, s.lda, fc.Linv, fc.T, b.H, b.gw));
+            } else {
+                TRY(launch_zlacpy(st, n, n, s.A, s.lda, b.H, n));
+                TRY(hegst_lower(st, n, b.H, n, b.L, n, b.dinvL, b.hwork, b.gw));
+            }
             s.hi[0] = 0;
             s.fc_reused = true;
             return CHFSI_SUCCESS;
         }
     }
-    TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw));
-    if (!h->fc_enabled) return CHFSI_SUCCESS;
+    if (!h->fc_enabled)
+        return step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw);
     h->fc_n = 0;
     const size_t need = factor_cache_bytes(n);
     if (h->fc.cap < need) {
         TRY(hipStreamSynchronize(st));
         h->fc.grow(need);
-        if (h->fc.cap < need) return CHFSI_SUCCESS;   // no room: solve without the cache
     }
+    if (h->fc.cap < need)   // no room: solve without the cache
+        return step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw);
     const FactorCache fc = factor_cache(h, n);
+    if (fc.Linv) {
+        TRYS(step_factor_enqueue(h, n, s.S, s.lds, b.L, b.dinvL, b.info, s.hi, b.gw));
+        TRY(tri_inverse_lower(st, n, b.L, n, b.dinvL, fc.Linv, n, b.gw));
+        TRY(hegst_explicit(st, n, s.A, s.lda, fc.Linv, fc.T, b.H, b.gw));
+    } else {
+        TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw));
+    }
     TRY(launch_zlacpy(st, n, n, s.S, s.lds, fc.S, n));
     TRY(launch_zlacpy(st, n, n, b.L, n, fc.L, n));
     TRY(hipMemcpyAsync(fc.dinv, b.dinvL, sizeof(zd) * tri_dinv_elems(n), hipMemcpyDeviceToDevice, st));

@@ -182,6 +182,11 @@ size_t hegst_work_elems(int n);
 // inverses dinv; work: hegst_work_elems(n) elements
 int hegst_lower(hipStream_t s, int n, zd* A, int lda, const zd* L, int ldl, const zd* dinv, zd* work,
                 const GemmWs& gw);
+// X <- L^{-1} (n x n, zero above the diagonal) from L and its diagonal-block inverses dinv
+int tri_inverse_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* X, int ldx, const GemmWs& gw);
+// H (ld n) <- Linv A Linv^H (exactly Hermitian) from the explicit inverse Linv = L^{-1} (ld n) and the
+// full Hermitian A; T: n x n elements of scratch
+int hegst_explicit(hipStream_t s, int n, const zd* A, int lda, const zd* Linv, zd* T, zd* H, const GemmWs& gw);
 
 // ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
 int eig_padded_order(int m);

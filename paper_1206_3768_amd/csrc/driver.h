@@ -122,6 +122,10 @@ struct chfsi_handle_s {
 // steps (solver.hip)
 chfsi_status step_reduce(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L, zd* dinv,
                          zd* hwork, int* info_dev, const GemmWs& gw);
+// L L^H = S (L lower, zero above the diagonal, dinv the inverses of its 64 x 64 diagonal blocks);
+// the factorisation's info is copied to info_host (valid after a synchronisation)
+chfsi_status step_factor_enqueue(chfsi_handle h, int n, const zd* S, int lds, zd* L, zd* dinv, int* info_dev,
+                                 int* info_host, const GemmWs& gw);
 chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
                                  zd* dinv, zd* hwork, int* info_dev, int* info_host, const GemmWs& gw);
 chfsi_status step_lanczos_enqueue(chfsi_handle h, int n, const zd* H, int ldh, int k, unsigned long long seed,

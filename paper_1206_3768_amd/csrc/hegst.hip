@@ -68,7 +68,65 @@ int solve_block_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv
     return solve_block_lower(s, n - h, L22, ldl, D22, B + h + (size_t)h * ldb, ldb, gw);   // X22
 }
 
+// X (n x n) <- [D_1 0 ...; 0 D_2 ...; ...]: the stored inverses of L's 64 x 64 diagonal blocks on the
+// block diagonal (the last block may be smaller: its inverse sits in the leading part of a
+// 64 x 64 slot), zero elsewhere
+__global__ __launch_bounds__(256) void k_blockdiag_init(int n, const zd* __restrict__ dinv, zd* __restrict__ X, int ldx)
+{
+    const size_t total = (size_t)n * n;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        const int bi = i / TB, bj = j / TB;
+        zd v = make_double2(0.0, 0.0);
+        if (bi == bj) v = dinv[(size_t)bi * TB * TB + (i - bi * TB) + (size_t)(j - bj * TB) * TB];
+        X[(size_t)i + (size_t)j * ldx] = v;
+    }
+}
+
+// Strictly lower blocks of X = L^{-1} on halves, X holding the diagonal-block inverses and zero
+// below them: X11 = L11^{-1}, X21 = -L22^{-1} (L21 X11), X22 = L22^{-1}.  (The product with X11
+// includes its diagonal blocks, unlike the deferred solves of the reduction above.)
+int tri_inverse_rec(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* X, int ldx, const GemmWs& gw)
+{
+    if (n <= TB) return 0;
+    const int h = split_point(n);
+    int rc = tri_inverse_rec(s, h, L, ldl, dinv, X, ldx, gw);
+    if (rc == 0) rc = launch_zgemm(s, OP_N, OP_N, n - h, h, h, -1.0, L + h, ldl, X, ldx, 0.0, X + h, ldx, gw);
+    const zd* L22 = L + h + (size_t)h * ldl;
+    const zd* D22 = dinv + (size_t)(h / TB) * TB * TB;
+    if (rc == 0) rc = trsm_left_lower(s, n - h, h, L22, ldl, D22, X + h, ldx, gw);
+    if (rc == 0) rc = tri_inverse_rec(s, n - h, L22, ldl, D22, X + h + (size_t)h * ldx, ldx, gw);
+    return rc;
+}
+
 }  // namespace
+
+// X (n x n, leading dimension ldx) <- L^{-1} for the lower-triangular L whose diagonal-block
+// inverses are dinv (chol_lower): X starts as the block diagonal of the inverses, zero elsewhere,
+// and a recursion on halves fills the strictly lower blocks.
+int tri_inverse_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* X, int ldx, const GemmWs& gw)
+{
+    if (n <= 0) return 0;
+    const size_t blocks = std::min<size_t>(((size_t)n * n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_blockdiag_init, dim3((unsigned)blocks), dim3(256), 0, s, n, dinv, X, ldx);
+    const int rc = (int)hipGetLastError();
+    if (rc != 0) return rc;
+    return tri_inverse_rec(s, n, L, ldl, dinv, X, ldx, gw);
+}
+
+// H (n x n, leading dimension n) <- Linv A Linv^H with the explicit inverse Linv = L^{-1} (n x n,
+// zero above the diagonal) and A (n x n Hermitian, full storage): T = Linv A, the tiles of H on
+// or below the diagonal as T Linv^H, then the upper triangle mirrored (exactly Hermitian, real
+// diagonal).  12 n^3 real flops in three launches, against the panel algorithm's 4 n^3 in a few
+// hundred small ones: for orders where those launches dominate.  T: n x n elements.
+int hegst_explicit(hipStream_t s, int n, const zd* A, int lda, const zd* Linv, zd* T, zd* H, const GemmWs& gw)
+{
+    if (n <= 0) return 0;
+    int rc = launch_zgemm(s, OP_N, OP_N, n, n, n, 1.0, Linv, n, A, lda, 0.0, T, n, gw);
+    if (rc == 0) rc = launch_zgemm_tri(s, TRI_C_LOWER, OP_N, OP_C, n, n, n, 1.0, T, n, Linv, n, 0.0, H, n);
+    if (rc == 0) rc = launch_mirror_lower(s, n, H, n);
+    return rc;
+}
 
 // work: [Y | L21 | Y] of one panel (n x 3 TB), the Y blocks of a group below it (n x GW), and
 // [Yg | Lg | Yg] of the group's delayed update (n x 3 GW)

@@ -308,11 +308,10 @@ void host_tridiag_eig(int k, const double* al, const double* be, std::vector<dou
         if (rc_ != 0) return CHFSI_ERR_DEVICE;              \
     } while (0)
 
-// S = L L^H (L lower, strict upper part zeroed), H = L^{-1} A L^{-H}, Hermitized.  Enqueues the
-// whole reduction; the Cholesky info word is copied to *info_host (host memory, valid after the
-// stream has been synchronised; nonzero = S not positive definite, H then meaningless).
-chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
-                                 zd* dinv, zd* hwork, int* info_dev, int* info_host, const GemmWs& gw)
+// S = L L^H (L lower, strict upper part zeroed, dinv the inverses of its 64 x 64 diagonal blocks);
+// the Cholesky info word is copied to *info_host (valid after the stream has been synchronised).
+chfsi_status step_factor_enqueue(chfsi_handle h, int n, const zd* S, int lds, zd* L, zd* dinv, int* info_dev,
+                                 int* info_host, const GemmWs& gw)
 {
     hipStream_t st = h->stream;
     TRY(launch_zlacpy(st, n, n, S, lds, L, n));
@@ -320,6 +319,18 @@ chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, co
     TRY(chol_lower(st, n, L, n, info_dev, dinv, gw));
     TRY(hipMemcpyAsync(info_host, info_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     TRY(launch_zero_upper(st, n, L, n));
+    return CHFSI_SUCCESS;
+}
+
+// S = L L^H (L lower, strict upper part zeroed), H = L^{-1} A L^{-H}, Hermitized.  Enqueues the
+// whole reduction; the Cholesky info word is copied to *info_host (host memory, valid after the
+// stream has been synchronised; nonzero = S not positive definite, H then meaningless).
+chfsi_status step_reduce_enqueue(chfsi_handle h, int n, const zd* A, int lda, const zd* S, int lds, zd* H, zd* L,
+                                 zd* dinv, zd* hwork, int* info_dev, int* info_host, const GemmWs& gw)
+{
+    hipStream_t st = h->stream;
+    const chfsi_status fs = step_factor_enqueue(h, n, S, lds, L, dinv, info_dev, info_host, gw);
+    if (fs != CHFSI_SUCCESS) return fs;
     TRY(launch_zlacpy(st, n, n, A, lda, H, n));
     TRY(hegst_lower(st, n, H, n, L, n, dinv, hwork, gw));        // H = L^{-1} A L^{-H}, lower triangles only
     return CHFSI_SUCCESS;
