@@ -576,9 +576,12 @@ chfsi_status st_final_enqueue(chfsi_handle h, SolveState& s)
     SolveBufs& b = s.b;
     const int n = s.n, m = s.m;
     mark(s, PH_BACK, st, true);
-    TRY(launch_zlacpy(st, n, m, b.V, n, s.X, s.ldx));
-    if (s.S) {
-        TRY(trsm_left_lower_h(st, n, m, b.L, n, b.dinvL, s.X, s.ldx, b.gw));   // X = L^{-H} V
+    if (s.S && h->fc_enabled && h->fc_n == n && explicit_reduction(n)) {
+        // the cache holds this overlap's L^{-1}: X = L^{-H} V is one product
+        TRY(launch_zgemm(st, OP_C, OP_N, n, m, n, 1.0, factor_cache(h, n).Linv, n, b.V, n, 0.0, s.X, s.ldx, b.gw));
+    } else {
+        TRY(launch_zlacpy(st, n, m, b.V, n, s.X, s.ldx));
+        if (s.S) TRY(trsm_left_lower_h(st, n, m, b.L, n, b.dinvL, s.X, s.ldx, b.gw));   // X = L^{-H} V
     }
     TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.A, s.lda, s.X, s.ldx, 0.0, b.HY, n, b.gw));
     const zd* SX = s.X;
