@@ -222,12 +222,15 @@ chfsi_status chfsi_filter_launch_log(chfsi_handle h, double* rows, int cap, int*
 
 
 /* Project autotuner of the filter-step kernel: times every candidate plan for the n x m filter
- * step in precision prec (CHFSI_FP64 or CHFSI_FP32) on scratch buffers with hipEvents, stores the
- * fastest in the handle's plan table (used by every later filter step of that precision and n
- * whose width is at most m and above the next smaller tuned width) and returns it with its time
- * per step in ms (both outputs nullable).  Allocates and frees its own scratch. */
+ * step in precision prec on scratch buffers with hipEvents, stores the fastest in the handle's
+ * plan table (used by every later filter step of that precision and n whose width is at most m
+ * and above the next smaller tuned width) and returns it with its time per step in ms (both
+ * outputs nullable).  Allocates and frees its own scratch.  CHFSI_FP64 / CHFSI_FP32: tiles
+ * bm, bn in {32, 64}, K split 1..16, either summation.  CHFSI_BF16X3 / CHFSI_BF16X6: square tiles
+ * of 64, or 128 for CHFSI_BF16X3, K split 1..16, always summed in the kernel (fused = 1 for a split). */
 chfsi_status chfsi_autotune_filter(chfsi_handle h, int n, int m, int prec, chfsi_tile_plan* best, double* best_ms);
-/* Sets (plan != NULL) or removes (plan == NULL) the table entry for (n, m, prec) by hand. */
+/* Sets (plan != NULL) or removes (plan == NULL) the table entry for (n, m, prec) by hand; a plan
+ * outside the candidates listed above is rejected with CHFSI_ERR_ARG. */
 chfsi_status chfsi_set_filter_plan(chfsi_handle h, int n, int m, int prec, const chfsi_tile_plan* plan);
 
 /* Step-level entry points (the pieces chfsi_solve is made of), for parity tests.

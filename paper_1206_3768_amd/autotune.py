@@ -36,7 +36,7 @@ def main() -> int:
     out = []
     for n, widths in SHAPES:
         for w in widths:
-            for prec in (chfsi.FP64, chfsi.FP32):
+            for prec in (chfsi.FP64, chfsi.FP32, chfsi.BF16X3, chfsi.BF16X6):
                 plan, ms = h.autotune_filter(n, w, prec)
                 tf = 8.0 * n * n * w / (ms * 1e-3) / 1e12
                 out.append({"n": n, "m": w, "prec": prec, "plan": plan, "ms": round(ms, 5), "tflops": round(tf, 2)})

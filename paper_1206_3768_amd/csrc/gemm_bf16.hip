@@ -16,6 +16,7 @@
 #include "common.h"
 #include "driver.h"
 
+#include <algorithm>
 #include <vector>
 
 namespace {
@@ -568,17 +569,23 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
     g.alpha = (float)fs.alpha; g.beta = (float)fs.beta; g.shift = (float)fs.shift;
     g.P = (zf*)gw.ws;
     g.cnt = gw.cnt;
-    // 128 x 128 tiles (one workgroup per CU) for the two-term split when they still give a
-    // workgroup per CU, else 64 x 64 tiles (two per CU); the three-term split's planes do not fit
-    // the LDS at 128 x 128
+    // A forced plan (tuned table or caller): tile plan_bm (64, or 128 for the two-term split) and
+    // K split plan_ksplit.  Otherwise 128 x 128 tiles (one workgroup per CU) for the two-term split
+    // when they still give a workgroup per CU, else 64 x 64 tiles (two per CU; the three-term
+    // split's planes do not fit the LDS at 128 x 128), and the K split that fills the CUs.
+    const bool forced = gw.plan_bm == 64 || (gw.plan_bm == 128 && nterms == 2);
     const long t128 = (long)((n + 127) / 128) * ((ncols + 127) / 128);
-    const int tile = (nterms == 2 && t128 >= 192) ? 128 : 64;
+    const int tile = forced ? gw.plan_bm : ((nterms == 2 && t128 >= 192) ? 128 : 64);
     const long per_cu = tile == 128 ? 256 : 512;
     g.tiles_m = (n + tile - 1) / tile;
     g.tiles_n = (ncols + tile - 1) / tile;
     const long tiles = (long)g.tiles_m * g.tiles_n;
     int ksp = 1;
-    while (tiles * ksp < per_cu && np / (2 * ksp) >= 512) ksp *= 2;
+    if (forced) {
+        ksp = std::max(1, std::min(gw.plan_ksplit, np / 32));
+    } else {
+        while (tiles * ksp < per_cu && np / (2 * ksp) >= 512) ksp *= 2;
+    }
     if (!gw.ws || !gw.cnt || tiles > gw.ncnt) ksp = 1;
     while (ksp > 1 && (size_t)ksp * n * ncols * sizeof(zf) > gw.bytes) ksp /= 2;
     int kc = (np + ksp - 1) / ksp;
@@ -626,7 +633,9 @@ chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int
         const zf* yp = (k == 1) ? yk : yo;
         const int ldp = (k == 1) ? ldk : ldo;
         GemmWs gs = gw;
-        h->ktimer.begin(n, w, nterms == 2 ? CHFSI_BF16X3 : CHFSI_BF16X6, gs);
+        const int pr = nterms == 2 ? CHFSI_BF16X3 : CHFSI_BF16X6;
+        apply_tuned_plan(h, pr, n, w, gs);
+        h->ktimer.begin(n, w, pr, gs);
         if (launch_filter_step_bf16(st, n, w, Hb, ldh, nterms, yk, ldk, yp, ldp, yo, ldo, steps[k - 1], ysplit, gs))
             return CHFSI_ERR_DEVICE;
         h->ktimer.end(gs);

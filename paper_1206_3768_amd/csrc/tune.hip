@@ -1,6 +1,8 @@
 // Project autotuner of the filter-step kernel: per (precision, n, block width) the fastest tile
-// plan among the 32/64 output tiles, K splits of 1..16 and the two split-K summation modes, timed
-// with hipEvents on scratch buffers.  The table lives in the handle.
+// plan, timed with hipEvents on scratch buffers: FP64 / FP32 among the 32/64 output tiles, K splits
+// of 1..16 and the two split-K summation modes; the BF16-split filters among 64 x 64 (and, for the
+// two-term split, the pipelined 128 x 128) tiles and K splits of 1..16 (their K split always sums
+// in the kernel).  The table lives in the handle.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,30 +50,106 @@ void set_entry(chfsi_handle h, int prec, int n, int m, int bm, int bn, int ks, i
     h->plans.push_back({prec, n, m, bm, bn, ks, mode});
 }
 
+inline bool is_bf16(int prec) { return prec == CHFSI_BF16X3 || prec == CHFSI_BF16X6; }
+
+// a BF16-split plan: square tiles of 64, or 128 for the two-term split
+inline bool bf16_tile_ok(int prec, int bm, int bn) { return bm == bn && (bm == 64 || (bm == 128 && prec == CHFSI_BF16X3)); }
+
+// BF16-split tuning: H = 0 split into planes, Y blocks zero, every candidate timed over 5 steps
+chfsi_status autotune_bf16(chfsi_handle h, int n, int m, int prec, chfsi_tile_plan* best_out, double* best_ms)
+{
+    hipStream_t st = h->stream;
+    const int nterms = prec == CHFSI_BF16X3 ? 2 : 3;
+    const int ksmax = 16;
+    void *H = nullptr, *P = nullptr, *Ys = nullptr, *Y0 = nullptr, *Y1 = nullptr, *ws = nullptr;
+    const size_t wsb = (size_t)ksmax * n * m * sizeof(zf);
+    chfsi_status rc = CHFSI_SUCCESS;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(&H, (size_t)n * n * sizeof(zd)) != hipSuccess ||
+        hipMalloc(&P, bf16_hplanes_elems(n, nterms) * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&Ys, bf16_ysplit_bytes(n, m, nterms)) != hipSuccess ||
+        hipMalloc(&Y0, (size_t)n * m * sizeof(zf)) != hipSuccess || hipMalloc(&Y1, (size_t)n * m * sizeof(zf)) != hipSuccess ||
+        hipMalloc(&ws, wsb) != hipSuccess)
+        rc = CHFSI_ERR_ALLOC;
+    if (rc == CHFSI_SUCCESS &&
+        (hipMemsetAsync(H, 0, (size_t)n * n * sizeof(zd), st) != hipSuccess ||
+         hipMemsetAsync(Y0, 0, (size_t)n * m * sizeof(zf), st) != hipSuccess ||
+         hipMemsetAsync(Y1, 0, (size_t)n * m * sizeof(zf), st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+         hipEventCreate(&e1) != hipSuccess ||
+         launch_split_h_bf16(st, n, (const zd*)H, n, (uint16_t*)P, 0, nterms) != 0))
+        rc = CHFSI_ERR_DEVICE;
+    FilterStep fs = {0.5, -0.25, 0.1};
+    float best = 1e30f;
+    int btile = 64, bks = 1;
+    const int np = (n + 31) / 32 * 32;
+    for (int tile : {128, 64})
+        for (int ks : {1, 2, 4, 8, 16}) {
+            if (rc != CHFSI_SUCCESS) break;
+            if (!bf16_tile_ok(prec, tile, tile)) continue;
+            if (ks > 1 && np / ks < 64) continue;
+            const long tiles = (long)((n + tile - 1) / tile) * ((m + tile - 1) / tile);
+            if (ks > 1 && tiles > h->tile_cnt_len) continue;
+            GemmWs gw;
+            gw.ws = ws; gw.bytes = wsb; gw.cnt = h->tile_cnt; gw.ncnt = h->tile_cnt_len;
+            gw.plan_bm = tile; gw.plan_bn = tile; gw.plan_ksplit = ks; gw.plan_mode = 2;
+            auto step = [&]() {
+                return launch_filter_step_bf16(st, n, m, (const uint16_t*)P, 0, nterms, (const zf*)Y0, n, (const zf*)Y1,
+                                               n, (zf*)Y1, n, fs, (uint16_t*)Ys, gw);
+            };
+            if (step() || step()) { rc = CHFSI_ERR_DEVICE; break; }
+            const int reps = 5;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps; ++r)
+                if (step()) rc = CHFSI_ERR_DEVICE;
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = CHFSI_ERR_DEVICE; break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (ms < best) { best = ms; btile = tile; bks = ks; }
+        }
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (void* p : {H, P, Ys, Y0, Y1, ws})
+        if (p) (void)hipFree(p);
+    if (rc != CHFSI_SUCCESS) return rc;
+    set_entry(h, prec, n, m, btile, btile, bks, 2);
+    if (best_out) { best_out->bm = btile; best_out->bn = btile; best_out->ksplit = bks; best_out->fused = bks > 1; }
+    if (best_ms) *best_ms = best;
+    return CHFSI_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" {
 
 chfsi_status chfsi_set_filter_plan(chfsi_handle h, int n, int m, int prec, const chfsi_tile_plan* plan)
 {
-    if (!h || n <= 0 || m <= 0 || (prec != CHFSI_FP64 && prec != CHFSI_FP32)) return CHFSI_ERR_ARG;
+    if (!h || n <= 0 || m <= 0 || (prec != CHFSI_FP64 && prec != CHFSI_FP32 && !is_bf16(prec))) return CHFSI_ERR_ARG;
     if (!plan) {
         h->plans.erase(std::remove_if(h->plans.begin(), h->plans.end(),
                                       [&](const TuneEntry& e) { return e.prec == prec && e.n == n && e.m == m; }),
                        h->plans.end());
         return CHFSI_SUCCESS;
     }
-    if ((plan->bm != 32 && plan->bm != 64) || (plan->bn != 32 && plan->bn != 64) || plan->ksplit < 1 ||
-        plan->ksplit > 64)
-        return CHFSI_ERR_ARG;
+    if (plan->ksplit < 1 || plan->ksplit > 64) return CHFSI_ERR_ARG;
+    if (is_bf16(prec)) {
+        if (!bf16_tile_ok(prec, plan->bm, plan->bn)) return CHFSI_ERR_ARG;
+        set_entry(h, prec, n, m, plan->bm, plan->bn, plan->ksplit, 2);
+        return CHFSI_SUCCESS;
+    }
+    if ((plan->bm != 32 && plan->bm != 64) || (plan->bn != 32 && plan->bn != 64)) return CHFSI_ERR_ARG;
     set_entry(h, prec, n, m, plan->bm, plan->bn, plan->ksplit, plan->fused ? 2 : 1);
     return CHFSI_SUCCESS;
 }
 
 chfsi_status chfsi_autotune_filter(chfsi_handle h, int n, int m, int prec, chfsi_tile_plan* best_out, double* best_ms)
 {
-    if (!h || n <= 0 || m <= 0 || m > n || (prec != CHFSI_FP64 && prec != CHFSI_FP32)) return CHFSI_ERR_ARG;
+    if (!h || n <= 0 || m <= 0 || m > n || (prec != CHFSI_FP64 && prec != CHFSI_FP32 && !is_bf16(prec)))
+        return CHFSI_ERR_ARG;
     if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
+    if (is_bf16(prec)) return autotune_bf16(h, n, m, prec, best_out, best_ms);
     hipStream_t st = h->stream;
     const size_t eb = prec == CHFSI_FP64 ? 16 : 8;
     const int ksmax = 16;

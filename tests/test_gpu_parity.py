@@ -561,6 +561,46 @@ def test_filter_every_tile_plan(hd, orc, plan, prec, tol):
     assert relerr(host(dY), ref) <= tol
 
 
+@pytest.mark.parametrize("plan", [dict(bm=64, bn=64, ksplit=1, fused=0), dict(bm=64, bn=64, ksplit=4, fused=1),
+                                  dict(bm=128, bn=128, ksplit=1, fused=0), dict(bm=128, bn=128, ksplit=2, fused=1),
+                                  dict(bm=128, bn=128, ksplit=8, fused=1)])
+@pytest.mark.parametrize("prec,tol", [(2, 4e-3), (3, 2e-4)])
+def test_filter_every_bf16_plan(hd, orc, plan, prec, tol):
+    """The BF16-split kernels under every plan the tuner may pick (64 x 64 tiles, the pipelined
+    128 x 128 kernel for the two-term split, K split in the kernel) against the FP64 oracle filter;
+    128 x 128 tiles are refused for the three-term split, whose planes do not fit the LDS."""
+    from paper_1206_3768_amd import chfsi
+    n, m = 520, 70
+    if prec == 3 and plan["bm"] == 128:
+        with pytest.raises(chfsi.ChfsiError):
+            hd.set_filter_plan(n, m, prec, plan)
+        return
+    H, Y0, a, b, mu1 = _filter_case(n, m)
+    ref = orc.cheb_filter(H, Y0, a, b, mu1, deg=6)
+    hd.set_filter_plan(n, m, prec, plan)
+    try:
+        dY = dev(Y0)
+        hd.filter(dev(H), dY, a, b, mu1, deg=6, prec=prec)
+        used = hd.filter_launch_log()[-1]
+    finally:
+        hd.set_filter_plan(n, m, prec, None)
+    assert relerr(host(dY), ref) <= tol
+    # the tile as asked; the K split as asked up to the rounding of its slices to 32 rows of K
+    assert used[3] == plan["bm"] and (used[5] > 1) == (plan["ksplit"] > 1) and used[5] <= plan["ksplit"]
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_autotune_filter_bf16_returns_a_valid_plan(hd, orc, prec):
+    plan, ms = hd.autotune_filter(320, 48, prec)
+    assert plan["bm"] == plan["bn"] and plan["bm"] in ((64, 128) if prec == 2 else (64,)) and ms > 0
+    H, Y0, a, b, mu1 = _filter_case(320, 48)
+    ref = orc.cheb_filter(H, Y0, a, b, mu1, deg=5)
+    dY = dev(Y0)
+    hd.filter(dev(H), dY, a, b, mu1, deg=5, prec=prec)
+    hd.set_filter_plan(320, 48, prec, None)
+    assert relerr(host(dY), ref) <= (4e-3 if prec == 2 else 2e-4)
+
+
 def test_autotune_filter_returns_a_valid_plan(hd, orc):
     plan, ms = hd.autotune_filter(256, 40, 0)
     assert plan["bm"] in (32, 64) and plan["bn"] in (32, 64) and plan["ksplit"] >= 1 and ms > 0
