@@ -176,6 +176,21 @@ chfsi_status chfsi_set_batched_plan(chfsi_handle h, const chfsi_tile_plan* plan,
 chfsi_status chfsi_autotune_batched(chfsi_handle h, int count, const chfsi_problem* probs,
                                     chfsi_tile_plan* best, double* best_ms);
 
+/* Project autotuner of a tile per problem (a tile per order n and block width m = nev + nex), timed
+ * on one filter step of the whole batch of `count` (<= 64) problems: first every one-tile kernel
+ * (64x64, 64x32, 32x64, 32x32), then the persistent kernel that takes a tile per problem, starting
+ * from the best one tile, the problems ordered by n in four groups, each group trying every shape
+ * with the others fixed.  The faster of the two kernels serves later chfsi_solve_batched calls; its
+ * tile per problem is kept per (n, m) and returned in tiles[count] (nullable; ksplit 1, fused 0),
+ * the step time in *batch_ms (nullable).  A, X read as in chfsi_autotune_batched. */
+chfsi_status chfsi_autotune_batched_tiles(chfsi_handle h, int count, const chfsi_problem* probs,
+                                          chfsi_tile_plan* tiles, double* batch_ms);
+/* Sets the tile of each problem's (n, nev + nex) by hand (bm, bn in {32, 64}; only n, nev, nex of
+ * probs are read) and selects the kernel with a tile per problem; tiles == NULL clears the table and
+ * returns to the one tile of chfsi_set_batched_plan, which (with a plan) also selects that kernel. */
+chfsi_status chfsi_set_batched_tiles(chfsi_handle h, int count, const chfsi_problem* probs,
+                                     const chfsi_tile_plan* tiles);
+
 /* Counters of the last chfsi_solve_batched (host pointers, each nullable): filter time in ms
  * (hipEvents around each loop's filter launches, summed), filter flops (8 n^2 per column and
  * step), graph replays and persistent kernel launches. */

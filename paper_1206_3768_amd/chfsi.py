@@ -90,7 +90,7 @@ EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solv
             "chfsi_filter_kernel_time", "chfsi_autotune_filter", "chfsi_set_filter_plan",
             "chfsi_filter_launch_log", "chfsi_set_batched_plan", "chfsi_autotune_batched",
             "chfsi_batched_info", "chfsi_filter_noalloc", "chfsi_correlation", "chfsi_lobpcg",
-            "chfsi_lobpcg_default_params"]
+            "chfsi_lobpcg_default_params", "chfsi_autotune_batched_tiles", "chfsi_set_batched_tiles"]
 
 
 def load():
@@ -132,6 +132,8 @@ def load():
     lib.chfsi_set_filter_plan.argtypes = [vp, i, i, i, C.POINTER(TilePlan)]
     lib.chfsi_set_batched_plan.argtypes = [vp, C.POINTER(TilePlan), i, i]
     lib.chfsi_autotune_batched.argtypes = [vp, i, C.POINTER(Problem), C.POINTER(TilePlan), vp]
+    lib.chfsi_autotune_batched_tiles.argtypes = [vp, i, C.POINTER(Problem), C.POINTER(TilePlan), vp]
+    lib.chfsi_set_batched_tiles.argtypes = [vp, i, C.POINTER(Problem), C.POINTER(TilePlan)]
     lib.chfsi_batched_info.argtypes = [vp, vp, vp, vp, vp]
     lib.chfsi_status_string.argtypes = [i]
     lib.chfsi_status_string.restype = C.c_char_p
@@ -287,6 +289,25 @@ class Handle:
         self._check(self.lib.chfsi_autotune_batched(self.h, len(problems), arr, C.byref(plan), ms.ctypes.data),
                     "chfsi_autotune_batched")
         return (plan.bm, plan.bn), float(ms[0])
+
+    def autotune_batched_tiles(self, problems: Sequence[dict]):
+        """Tunes a tile per problem (per order and block width) and selects the kernel with a tile
+        per problem; returns ([(bm, bn)] per problem, ms of one filter step of the whole batch)."""
+        arr, _ = self._problems(problems)
+        tiles = (TilePlan * len(problems))()
+        ms = np.zeros(1)
+        self._check(self.lib.chfsi_autotune_batched_tiles(self.h, len(problems), arr, tiles, ms.ctypes.data),
+                    "chfsi_autotune_batched_tiles")
+        return [(t.bm, t.bn) for t in tiles], float(ms[0])
+
+    def set_batched_tiles(self, problems: Optional[Sequence[dict]], tiles: Optional[Sequence[tuple]]):
+        """Sets the tile (bm, bn) of each problem's order and width (tiles None: back to one tile)."""
+        if tiles is None:
+            self._check(self.lib.chfsi_set_batched_tiles(self.h, 0, None, None), "chfsi_set_batched_tiles")
+            return
+        arr, _ = self._problems(problems)
+        tp = (TilePlan * len(tiles))(*[TilePlan(bm, bn, 1, 0) for bm, bn in tiles])
+        self._check(self.lib.chfsi_set_batched_tiles(self.h, len(problems), arr, tp), "chfsi_set_batched_tiles")
 
     def batched_info(self) -> dict:
         """Filter ms, filter flops, graph replays and kernel launches of the last solve_batched."""

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <numeric>
 #include <thread>
@@ -30,13 +31,14 @@ constexpr int BATCH_MAXP = 64;   // problems per persistent launch (larger batch
 constexpr int NUM_XCD = 8;       // gfx950: workgroup w runs on XCD w % 8
 constexpr int MAX_LANES = 8;     // streams for the per-problem dense steps (default 3)
 
-// One problem of a filter step: Yo = alpha (H Yk - shift Yk) + beta Yp on columns [0, w).
+// One problem of a filter step: Yo = alpha (H Yk - shift Yk) + beta Yp on columns [0, w).  bm x bn
+// is its output tile in the per-problem kernel (ignored by the one-tile kernels).
 struct BatchProb {
     const zd* H;
     const zd* Yk;
     const zd* Yp;
     zd* Yo;
-    int n, ldh, ldk, ldp, ldo, w;
+    int n, ldh, ldk, ldp, ldo, w, bm, bn;
     double alpha, beta, shift;
 };
 
@@ -107,10 +109,84 @@ __global__ __launch_bounds__(256) void k_filter_batched(const BatchStep* __restr
     }
 }
 
+// One output tile of problem b with the BM x BN shape (As, Bs: LDS of at least that shape's size).
+template <int BM, int BN>
+__device__ inline void batched_tile(const BatchProb& b, int i0, int j0, zd* As, zd* Bs)
+{
+    typedef TileShape<double, BM, BN> S;
+    d4 accr[S::MI][S::NJ], acci[S::MI][S::NJ];
+    chfsi_tile::tile_mainloop<double, OP_N, OP_N, BM, BN>(b.H, b.ldh, b.n, b.Yk, b.ldk, b.w, i0, j0, 0, b.n, As, Bs,
+                                                          accr, acci);
+#pragma unroll
+    for (int bi = 0; bi < S::MI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < S::NJ; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = chfsi_tile::tile_row<double, BM, BN>(i0, bi);
+                const int j = chfsi_tile::tile_col<double, BM, BN>(j0, bj, r);
+                if (i < b.n && j < b.w) {
+                    const zd yk = b.Yk[(size_t)i + (size_t)j * b.ldk];
+                    const zd yp = b.Yp[(size_t)i + (size_t)j * b.ldp];
+                    zd o;
+                    o.x = b.alpha * (accr[bi][bj][r] - b.shift * yk.x) + b.beta * yp.x;
+                    o.y = b.alpha * (acci[bi][bj][r] - b.shift * yk.y) + b.beta * yp.y;
+                    b.Yo[(size_t)i + (size_t)j * b.ldo] = o;
+                }
+            }
+}
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int AS_MAX = cmax(cmax(TileShape<double, 64, 64>::AS_ELEMS, TileShape<double, 64, 32>::AS_ELEMS),
+                            cmax(TileShape<double, 32, 64>::AS_ELEMS, TileShape<double, 32, 32>::AS_ELEMS));
+constexpr int BS_MAX = cmax(cmax(TileShape<double, 64, 64>::BS_ELEMS, TileShape<double, 64, 32>::BS_ELEMS),
+                            cmax(TileShape<double, 32, 64>::BS_ELEMS, TileShape<double, 32, 32>::BS_ELEMS));
+
+// Persistent filter step with a tile shape per problem (b.bm x b.bn, each 32 or 64): the same work
+// list and XCD split as k_filter_batched, each problem cut into its own tiles; every work item
+// runs the tile loop of its problem's shape.  LDS and registers are those of the largest shape.
+__global__ __launch_bounds__(256) void k_filter_batched_mixed(const BatchStep* __restrict__ step)
+{
+    __shared__ zd As[2 * AS_MAX];
+    __shared__ zd Bs[2 * BS_MAX];
+    __shared__ int pre[BATCH_MAXP + 1], r0s[BATCH_MAXP], tns[BATCH_MAXP];
+    const int x = blockIdx.x % NUM_XCD, q = blockIdx.x / NUM_XCD, Q = gridDim.x / NUM_XCD;
+    const int np = min(step->nprob, BATCH_MAXP);
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int p = 0; p < np; ++p) {
+            const int n = step->p[p].n, w = step->p[p].w, bm = step->p[p].bm, bn = step->p[p].bn;
+            const int tm = (n + bm - 1) / bm, tn = (w + bn - 1) / bn;
+            const int r0 = (int)((long)x * tm / NUM_XCD), r1 = (int)((long)(x + 1) * tm / NUM_XCD);
+            pre[p] = acc;
+            r0s[p] = r0;
+            tns[p] = tn;
+            acc += (r1 - r0) * tn;
+        }
+        pre[np] = acc;
+    }
+    __syncthreads();
+    const int total = pre[np];
+    int p = 0;
+    for (int f = q; f < total; f += Q) {
+        while (pre[p + 1] <= f) ++p;
+        const BatchProb b = step->p[p];
+        const int loc = f - pre[p];
+        const int i0 = (r0s[p] + loc / tns[p]) * b.bm, j0 = (loc % tns[p]) * b.bn;
+        if (b.bm == 64 && b.bn == 64) batched_tile<64, 64>(b, i0, j0, As, Bs);
+        else if (b.bm == 64) batched_tile<64, 32>(b, i0, j0, As, Bs);
+        else if (b.bn == 64) batched_tile<32, 64>(b, i0, j0, As, Bs);
+        else batched_tile<32, 32>(b, i0, j0, As, Bs);
+        __syncthreads();   // the next tile refills As/Bs
+    }
+}
+
 template <int BM, int BN> const void* kernel_of() { return (const void*)k_filter_batched<BM, BN>; }
 
+// bm = bn = 0 selects the per-problem kernel
 const void* batched_kernel(int bm, int bn)
 {
+    if (bm == 0 && bn == 0) return (const void*)k_filter_batched_mixed;
     if (bm == 64 && bn == 64) return kernel_of<64, 64>();
     if (bm == 64 && bn == 32) return kernel_of<64, 32>();
     if (bm == 32 && bn == 64) return kernel_of<32, 64>();
@@ -131,7 +207,8 @@ int batched_grid(int device, int bm, int bn)
 
 int launch_batched(hipStream_t s, const BatchStep* step, int bm, int bn, int grid)
 {
-    if (bm == 64 && bn == 64) hipLaunchKernelGGL((k_filter_batched<64, 64>), dim3(grid), dim3(256), 0, s, step);
+    if (bm == 0 && bn == 0) hipLaunchKernelGGL(k_filter_batched_mixed, dim3(grid), dim3(256), 0, s, step);
+    else if (bm == 64 && bn == 64) hipLaunchKernelGGL((k_filter_batched<64, 64>), dim3(grid), dim3(256), 0, s, step);
     else if (bm == 64 && bn == 32) hipLaunchKernelGGL((k_filter_batched<64, 32>), dim3(grid), dim3(256), 0, s, step);
     else if (bm == 32 && bn == 64) hipLaunchKernelGGL((k_filter_batched<32, 64>), dim3(grid), dim3(256), 0, s, step);
     else hipLaunchKernelGGL((k_filter_batched<32, 32>), dim3(grid), dim3(256), 0, s, step);
@@ -189,6 +266,16 @@ chfsi_status ensure_lanes(chfsi_handle h)
 void sync_lanes(chfsi_handle h)
 {
     for (auto& l : h->lanes) (void)hipStreamSynchronize(l.st);
+}
+
+// Tile of a problem of order n and block width m in the per-problem kernel: its tuned (or set)
+// entry, else the batch's one tile.
+void batched_tile_of(chfsi_handle h, int n, int m, int& bm, int& bn)
+{
+    bm = h->batch_bm;
+    bn = h->batch_bn;
+    for (const auto& e : h->batch_tiles)
+        if (e[0] == n && e[1] == m) { bm = e[2]; bn = e[3]; return; }
 }
 
 // Makes the step tables hold `steps` steps; a reallocation invalidates the captured graphs.
@@ -283,6 +370,7 @@ chfsi_status batched_filter(chfsi_handle h, std::vector<Slot>& sl, const std::ve
             bp.ldh = s.ldh;
             bp.n = s.n;
             bp.w = w;
+            batched_tile_of(h, s.n, s.m, bp.bm, bp.bn);
             bp.Yk = (k % 2 == 1) ? Ya : T;
             bp.Yo = (k % 2 == 1) ? T : Ya;
             bp.Yp = (k == 1) ? bp.Yk : bp.Yo;   // beta = 0 on step 1: any finite input
@@ -296,7 +384,7 @@ chfsi_status batched_filter(chfsi_handle h, std::vector<Slot>& sl, const std::ve
             h->batch_flops += 8.0 * (double)s.n * (double)s.n * (double)w;
         }
     }
-    const int bm = h->batch_bm, bn = h->batch_bn;
+    const int bm = h->batch_mixed ? 0 : h->batch_bm, bn = h->batch_mixed ? 0 : h->batch_bn;
     const int grid = batched_grid(h->device, bm, bn);
     TRY(hipMemcpyAsync(h->btable, tab, sizeof(BatchStep) * dmax, hipMemcpyHostToDevice, st));
     TRY(hipEventRecord(h->bev[0], st));
@@ -530,14 +618,21 @@ chfsi_status chfsi_set_batched_plan(chfsi_handle h, const chfsi_tile_plan* plan,
         if ((plan->bm != 32 && plan->bm != 64) || (plan->bn != 32 && plan->bn != 64)) return CHFSI_ERR_ARG;
         h->batch_bm = plan->bm;
         h->batch_bn = plan->bn;
+        h->batch_mixed = false;
     }
     h->batch_use_graph = use_graph != 0;
     return CHFSI_SUCCESS;
 }
 
-chfsi_status chfsi_autotune_batched(chfsi_handle h, int count, const chfsi_problem* probs, chfsi_tile_plan* best,
-                                    double* best_ms)
+}  // extern "C"
+
+namespace {
+
+// Checks the problems of a tuning call and builds a one-step table over all of them (scratch
+// outputs in *out, one n x m block per problem, freed by the caller).
+chfsi_status tune_setup(chfsi_handle h, int count, const chfsi_problem* probs, BatchStep& tab, zd** out)
 {
+    *out = nullptr;
     if (!h || count <= 0 || count > BATCH_MAXP || !probs) return CHFSI_ERR_ARG;
     for (int i = 0; i < count; ++i) {
         const chfsi_problem& q = probs[i];
@@ -546,67 +641,179 @@ chfsi_status chfsi_autotune_batched(chfsi_handle h, int count, const chfsi_probl
             return CHFSI_ERR_ARG;
     }
     if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
-    hipStream_t st = h->stream;
     TRYS(ensure_lanes(h));
     TRYS(ensure_table(h, 1));
-    // scratch outputs, one n x m block per problem
     std::vector<size_t> off(count);
     size_t tot = 0;
     for (int i = 0; i < count; ++i) {
         off[i] = tot;
         tot += (size_t)probs[i].n * (probs[i].nev + probs[i].nex);
     }
-    zd* out = nullptr;
-    if (hipMalloc((void**)&out, sizeof(zd) * tot) != hipSuccess) return CHFSI_ERR_ALLOC;
-    BatchStep* tab = (BatchStep*)h->btable_host.p;
-    tab->nprob = count;
+    if (hipMalloc((void**)out, sizeof(zd) * tot) != hipSuccess) { *out = nullptr; return CHFSI_ERR_ALLOC; }
+    tab.nprob = count;
     for (int i = 0; i < count; ++i) {
         const chfsi_problem& q = probs[i];
-        BatchProb& bp = tab->p[i];
+        BatchProb& bp = tab.p[i];
         bp.H = (const zd*)q.A;
         bp.ldh = q.lda;
         bp.n = q.n;
         bp.w = q.nev + q.nex;
+        bp.bm = h->batch_bm;
+        bp.bn = h->batch_bn;
         bp.Yk = (const zd*)q.X;
         bp.ldk = q.ldx;
         bp.Yp = (const zd*)q.X;
         bp.ldp = q.ldx;
-        bp.Yo = out + off[i];
+        bp.Yo = *out + off[i];
         bp.ldo = q.n;
         bp.alpha = 1e-3;
         bp.beta = -0.5;
         bp.shift = 0.1;
     }
+    return CHFSI_SUCCESS;
+}
+
+// ms per launch of the step table in device slot 0 with tile bm x bn (0 x 0: per problem),
+// after two warm-up launches; negative on a device error
+double time_table(chfsi_handle h, int bm, int bn)
+{
+    hipStream_t st = h->stream;
+    const int grid = batched_grid(h->device, bm, bn);
+    for (int w = 0; w < 2; ++w)
+        if (launch_batched(st, (const BatchStep*)h->btable, bm, bn, grid) != 0) return -1.0;
+    (void)hipEventRecord(h->bev[0], st);
+    for (int r = 0; r < 5; ++r)
+        if (launch_batched(st, (const BatchStep*)h->btable, bm, bn, grid) != 0) return -1.0;
+    (void)hipEventRecord(h->bev[1], st);
+    if (hipEventSynchronize(h->bev[1]) != hipSuccess) return -1.0;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, h->bev[0], h->bev[1]) != hipSuccess) return -1.0;
+    return ms / 5;
+}
+
+void set_tile_entry(chfsi_handle h, int n, int m, int bm, int bn)
+{
+    for (auto& e : h->batch_tiles)
+        if (e[0] == n && e[1] == m) { e[2] = bm; e[3] = bn; return; }
+    h->batch_tiles.push_back({n, m, bm, bn});
+}
+
+const int TILE_CAND[4][2] = {{64, 64}, {64, 32}, {32, 64}, {32, 32}};
+
+}  // namespace
+
+extern "C" {
+
+chfsi_status chfsi_autotune_batched(chfsi_handle h, int count, const chfsi_problem* probs, chfsi_tile_plan* best,
+                                    double* best_ms)
+{
+    if (!h) return CHFSI_ERR_ARG;
+    std::unique_ptr<BatchStep> tab(new (std::nothrow) BatchStep());
+    if (!tab) return CHFSI_ERR_ALLOC;
+    zd* out = nullptr;
+    TRYS(tune_setup(h, count, probs, *tab, &out));
     chfsi_status rc = CHFSI_SUCCESS;
-    if (hipMemcpyAsync(h->btable, tab, sizeof(BatchStep), hipMemcpyHostToDevice, st) != hipSuccess)
-        rc = CHFSI_ERR_DEVICE;
-    static const int cand[4][2] = {{64, 64}, {64, 32}, {32, 64}, {32, 32}};
+    if (hipMemcpy(h->btable, tab.get(), sizeof(BatchStep), hipMemcpyHostToDevice) != hipSuccess) rc = CHFSI_ERR_DEVICE;
     double bms = 1e30;
     int bi = 0;
     for (int c = 0; c < 4 && rc == CHFSI_SUCCESS; ++c) {
-        const int bm = cand[c][0], bn = cand[c][1];
-        const int grid = batched_grid(h->device, bm, bn);
-        for (int w = 0; w < 2 && rc == CHFSI_SUCCESS; ++w)
-            if (launch_batched(st, (const BatchStep*)h->btable, bm, bn, grid) != 0) rc = CHFSI_ERR_DEVICE;
-        if (rc != CHFSI_SUCCESS) break;
-        (void)hipEventRecord(h->bev[0], st);
-        for (int r = 0; r < 5; ++r)
-            if (launch_batched(st, (const BatchStep*)h->btable, bm, bn, grid) != 0) rc = CHFSI_ERR_DEVICE;
-        (void)hipEventRecord(h->bev[1], st);
-        if (hipEventSynchronize(h->bev[1]) != hipSuccess) rc = CHFSI_ERR_DEVICE;
-        float ms = 0;
-        if (rc == CHFSI_SUCCESS && hipEventElapsedTime(&ms, h->bev[0], h->bev[1]) == hipSuccess && ms / 5 < bms) {
-            bms = ms / 5;
-            bi = c;
-        }
+        const double ms = time_table(h, TILE_CAND[c][0], TILE_CAND[c][1]);
+        if (ms < 0) rc = CHFSI_ERR_DEVICE;
+        else if (ms < bms) { bms = ms; bi = c; }
     }
-    (void)hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(h->stream);
     (void)hipFree(out);
     if (rc != CHFSI_SUCCESS) return rc;
-    h->batch_bm = cand[bi][0];
-    h->batch_bn = cand[bi][1];
+    h->batch_bm = TILE_CAND[bi][0];
+    h->batch_bn = TILE_CAND[bi][1];
+    h->batch_mixed = false;
     if (best) { best->bm = h->batch_bm; best->bn = h->batch_bn; best->ksplit = 1; best->fused = 0; }
     if (best_ms) *best_ms = bms;
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_autotune_batched_tiles(chfsi_handle h, int count, const chfsi_problem* probs,
+                                          chfsi_tile_plan* tiles, double* batch_ms)
+{
+    if (!h) return CHFSI_ERR_ARG;
+    std::unique_ptr<BatchStep> tab(new (std::nothrow) BatchStep());
+    if (!tab) return CHFSI_ERR_ALLOC;
+    zd* out = nullptr;
+    TRYS(tune_setup(h, count, probs, *tab, &out));
+    chfsi_status rc = CHFSI_SUCCESS;
+    auto upload = [&]() {
+        return hipMemcpy(h->btable, tab.get(), sizeof(BatchStep), hipMemcpyHostToDevice) == hipSuccess;
+    };
+    // 1. the whole batch with each one-tile kernel
+    double uni_ms = 1e30;
+    int ui = 0;
+    if (!upload()) rc = CHFSI_ERR_DEVICE;
+    for (int c = 0; c < 4 && rc == CHFSI_SUCCESS; ++c) {
+        const double ms = time_table(h, TILE_CAND[c][0], TILE_CAND[c][1]);
+        if (ms < 0) rc = CHFSI_ERR_DEVICE;
+        else if (ms < uni_ms) { uni_ms = ms; ui = c; }
+    }
+    // 2. the kernel with a tile per problem, from the best one tile: the problems ordered by n cut
+    //    into four groups, each group trying every shape with the others fixed, timed on the batch
+    std::vector<int> shape(count, ui), ord(count);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return probs[a].n < probs[b].n; });
+    auto apply = [&]() {
+        for (int i = 0; i < count; ++i) { tab->p[i].bm = TILE_CAND[shape[i]][0]; tab->p[i].bn = TILE_CAND[shape[i]][1]; }
+    };
+    double mix_ms = -1.0;
+    if (rc == CHFSI_SUCCESS) {
+        apply();
+        if (!upload() || (mix_ms = time_table(h, 0, 0)) < 0) rc = CHFSI_ERR_DEVICE;
+    }
+    const int groups = std::min(4, count);
+    for (int gi = 0; gi < groups && rc == CHFSI_SUCCESS; ++gi) {
+        const int lo = gi * count / groups, hi = (gi + 1) * count / groups;
+        const int keep = shape[ord[lo]];
+        int best_c = keep;
+        for (int c = 0; c < 4 && rc == CHFSI_SUCCESS; ++c) {
+            if (c == keep) continue;
+            for (int k = lo; k < hi; ++k) shape[ord[k]] = c;
+            apply();
+            double ms = -1.0;
+            if (!upload() || (ms = time_table(h, 0, 0)) < 0) { rc = CHFSI_ERR_DEVICE; break; }
+            if (ms < mix_ms) { mix_ms = ms; best_c = c; }
+        }
+        for (int k = lo; k < hi; ++k) shape[ord[k]] = best_c;
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(out);
+    if (rc != CHFSI_SUCCESS) return rc;
+    // 3. the faster of the two kernels serves later solves
+    const bool mixed = mix_ms < uni_ms;
+    h->batch_bm = TILE_CAND[ui][0];
+    h->batch_bn = TILE_CAND[ui][1];
+    for (int i = 0; i < count; ++i) {
+        const int c = mixed ? shape[i] : ui;
+        set_tile_entry(h, probs[i].n, probs[i].nev + probs[i].nex, TILE_CAND[c][0], TILE_CAND[c][1]);
+        if (tiles) { tiles[i].bm = TILE_CAND[c][0]; tiles[i].bn = TILE_CAND[c][1]; tiles[i].ksplit = 1; tiles[i].fused = 0; }
+    }
+    h->batch_mixed = mixed;
+    if (batch_ms) *batch_ms = mixed ? mix_ms : uni_ms;
+    return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_set_batched_tiles(chfsi_handle h, int count, const chfsi_problem* probs,
+                                     const chfsi_tile_plan* tiles)
+{
+    if (!h) return CHFSI_ERR_ARG;
+    if (!tiles) {
+        h->batch_tiles.clear();
+        h->batch_mixed = false;
+        return CHFSI_SUCCESS;
+    }
+    if (count <= 0 || !probs) return CHFSI_ERR_ARG;
+    for (int i = 0; i < count; ++i)
+        if ((tiles[i].bm != 32 && tiles[i].bm != 64) || (tiles[i].bn != 32 && tiles[i].bn != 64) || probs[i].n <= 0 ||
+            probs[i].nev <= 0 || probs[i].nex < 0)
+            return CHFSI_ERR_ARG;
+    for (int i = 0; i < count; ++i) set_tile_entry(h, probs[i].n, probs[i].nev + probs[i].nex, tiles[i].bm, tiles[i].bn);
+    h->batch_mixed = true;
     return CHFSI_SUCCESS;
 }
 

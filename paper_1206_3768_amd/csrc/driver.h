@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <functional>
 #include <vector>
 
@@ -112,6 +113,10 @@ struct chfsi_handle_s {
     size_t btable_cap = 0;
     PinBuf btable_host;
     int batch_bm = 64, batch_bn = 64;   // tile of the persistent filter kernel
+    // per-problem tiles: (n, m, bm, bn) entries; when batch_mixed, every problem of a step takes the
+    // tile of its (n, m) (else batch_bm x batch_bn) in the kernel with a tile per problem
+    bool batch_mixed = false;
+    std::vector<std::array<int, 4>> batch_tiles;
     double batch_filter_ms = 0, batch_flops = 0;
     int batch_graph_launches = 0, batch_kernel_launches = 0;
     bool batch_use_graph = true;   // replay each loop's filter steps as one captured graph

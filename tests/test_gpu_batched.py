@@ -116,6 +116,61 @@ def test_autotune_batched_picks_a_valid_plan(hd):
     hd.set_batched_plan(64, 64, use_graph=True)
 
 
+def test_batched_tile_per_problem_matches_one_tile_kernels(hd):
+    """The kernel that takes a tile per problem: with one shape for every problem it gives the
+    eigenvalues of the one-tile kernel of that shape on the same batch to 1e-12 (the same tile code
+    inlined into another kernel may round its epilogue differently); with the four shapes over four
+    problems (set by hand) every problem meets its pencil's spectrum and the 64 x 64 results."""
+    from paper_1206_3768_amd import chfsi
+    kps = _problems([256, 401, 333, 300], seed=6)
+    shapes = [(64, 64), (64, 32), (32, 64), (32, 32)]
+
+    def run(use_graph=True):
+        probs = _upload(kps)
+        st, res = hd.solve_batched(probs, _params())
+        assert st == 0 and (hd.batched_info()["graph_launches"] > 0) == use_graph
+        return [(r.lam.copy(), chfsi.to_numpy(pr["X"])) for r, pr in zip(res, probs)]
+
+    try:
+        ref = {}
+        for shape in shapes:
+            hd.set_batched_tiles(None, None)
+            hd.set_batched_plan(*shape, use_graph=True)
+            ref[shape] = run()
+            hd.set_batched_tiles(_upload(kps), [shape] * len(kps))
+            for kp, (la, _), (lb, _) in zip(kps, ref[shape], run()):
+                assert np.all(np.abs(la[:kp.nev] - lb[:kp.nev]) <= 1e-12 * np.maximum(np.abs(la[:kp.nev]), 1e-3))
+        hd.set_batched_tiles(_upload(kps), shapes)
+        for use_graph in (True, False):
+            hd.set_batched_plan(use_graph=use_graph)          # no plan: the tiles per problem stay
+            for kp, (lam, X), (l64, _) in zip(kps, run(use_graph), ref[(64, 64)]):
+                ev = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(kp.S), np.linalg.solve(
+                    np.linalg.cholesky(kp.S), kp.A).conj().T))
+                assert np.all(np.abs(lam[:kp.nev] - ev[:kp.nev]) <= 1e-10 * np.maximum(np.abs(ev[:kp.nev]), 1e-3))
+                assert np.all(np.abs(lam[:kp.nev] - l64[:kp.nev]) <= 1e-12 * np.maximum(np.abs(l64[:kp.nev]), 1e-3))
+    finally:
+        hd.set_batched_tiles(None, None)
+        hd.set_batched_plan(64, 64, use_graph=True)
+
+
+def test_autotune_batched_tiles_picks_valid_tiles(hd):
+    kps = _problems([512, 700, 640, 555], seed=7)
+    probs = _upload(kps)
+    try:
+        tiles, ms = hd.autotune_batched_tiles(probs)
+        assert len(tiles) == 4 and all(bm in (32, 64) and bn in (32, 64) for bm, bn in tiles) and ms > 0
+        st, res = hd.solve_batched(probs, _params())
+        assert st == 0
+        for kp, r in zip(kps, res):
+            ev = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(kp.S), np.linalg.solve(
+                np.linalg.cholesky(kp.S), kp.A).conj().T))
+            assert r.resid[:kp.nev].max() <= 1e-10
+            assert np.all(np.abs(r.lam[:kp.nev] - ev[:kp.nev]) <= 1e-10 * np.maximum(np.abs(ev[:kp.nev]), 1e-3))
+    finally:
+        hd.set_batched_tiles(None, None)
+        hd.set_batched_plan(64, 64, use_graph=True)
+
+
 def test_batched_analytic_degrees_and_cold_start(hd, orc):
     from paper_1206_3768_amd import chfsi
     kps = _problems([300, 360], seed=8)
