@@ -85,7 +85,10 @@ typedef struct {
     int nlocked;                  /* locked (converged) pairs                                   */
     long long filtered_vectors;   /* sum over loops of the active block width                   */
     long long matvecs;            /* sum over loops and vectors of the filter degree            */
-    double filter_flops;          /* 8 n^2 * matvecs (complex GEMM count)                       */
+    double filter_flops;          /* 8 n^2 per product the filter performed (complex GEMM
+                                     count): the first step of a loop after the first is formed
+                                     from the Rayleigh-Ritz step's H Y without a product, so this
+                                     is 8 n^2 (matvecs - vectors filtered in those loops)      */
     double t_reduce, t_lanczos, t_filter, t_qr, t_rr, t_resid, t_lock, t_back, t_total; /* ms */
     double mu1, a, b;             /* final filter bounds                                        */
     double norm_a;                /* largest column 2-norm of A (lower bound of ||A||_2)        */

@@ -124,10 +124,12 @@ chfsi_status restore_column_order(chfsi_handle h, SolveBufs& b, int n, int ma, z
 
 // Filters the active block Y (n x ma) with per-column degrees deg and precision flags lowp
 // (1 = low precision).  Columns are reordered for the filter (low-precision group first, each group
-// sorted by non-increasing degree) and put back into their order afterwards.
+// sorted by non-increasing degree) and put back into their order afterwards.  HY (nullable, ld n):
+// H Y for the block's columns, which turns every filter's first step into an elementwise update; it
+// is reordered with Y and not restored (it is consumed).
 chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ldh, int prec, int ma, zd* Y, int ldy,
                         std::vector<int>& deg, std::vector<int>& lowp, double a, double bb, double mu1,
-                        double& flops, long long& matvecs)
+                        double& flops, long long& matvecs, zd* HY = nullptr)
 {
     hipStream_t st = h->stream;
     std::vector<int> ord(ma);
@@ -144,6 +146,10 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
         TRY(hipMemcpyAsync(b.iperm, perm.data(), sizeof(int) * 2 * ma, hipMemcpyHostToDevice, st));
         TRY(launch_permute_cols(st, n, ma, Y, ldy, b.T, n, b.iperm));
         TRY(launch_zlacpy(st, n, ma, b.T, n, Y, ldy));
+        if (HY) {
+            TRY(launch_permute_cols(st, n, ma, HY, n, b.T, n, b.iperm));
+            TRY(launch_zlacpy(st, n, ma, b.T, n, HY, n));
+        }
         std::vector<int> d2(ma), l2(ma);
         for (int j = 0; j < ma; ++j) { d2[j] = deg[ord[j]]; l2[j] = lowp[ord[j]]; }
         deg.swap(d2);
@@ -157,11 +163,11 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
         TRY(launch_z2c(st, n, nlow, Y, ldy, b.Vf, n));
         if (prec == CHFSI_FP32) {
             TRYS(filter_f32(h, n, b.Hf, n, nlow, b.Vf, n, b.Tf, dl, a, bb, mu1, b.flag, b.gw,
-                            flops, matvecs));
+                            flops, matvecs, HY));
         } else {
             const int nterms = prec == CHFSI_BF16X3 ? 2 : 3;
             TRYS(filter_bf16(h, n, b.Hb, n, nterms, nlow, b.Vf, n, b.Tf, b.ysplit, dl, a, bb, mu1, b.flag,
-                             b.gw, flops, matvecs));
+                             b.gw, flops, matvecs, HY));
         }
         TRY(launch_c2z(st, n, nlow, b.Vf, n, Y, ldy));
     }
@@ -169,7 +175,8 @@ chfsi_status run_filter(chfsi_handle h, SolveBufs& b, int n, const zd* H, int ld
     const int off = ma - n64;
     if (n64 > 0) {
         std::vector<int> dh(deg.begin() + off, deg.end());
-        TRYS(filter_f64(h, n, H, ldh, n64, Y + (size_t)off * ldy, ldy, b.T, dh, a, bb, mu1, b.flag, b.gw, flops, matvecs));
+        TRYS(filter_f64(h, n, H, ldh, n64, Y + (size_t)off * ldy, ldy, b.T, dh, a, bb, mu1, b.flag, b.gw, flops, matvecs,
+                        HY ? HY + (size_t)off * n : nullptr));
     }
     if (!ident) TRYS(restore_column_order(h, b, n, ma, Y, ldy));
     return CHFSI_SUCCESS;
@@ -415,8 +422,10 @@ chfsi_status st_filter(chfsi_handle h, SolveState& s)
     const int ma = s.ma();
     mark(s, PH_FILTER, h->stream, true);
     std::vector<int> dact(s.deg.begin() + s.nlocked, s.deg.end()), lact(s.lowp.begin() + s.nlocked, s.lowp.end());
+    zd* hy = s.hy_off >= 0 ? s.b.HY + (size_t)s.hy_off * s.n : nullptr;
+    s.hy_off = -1;
     TRYS(run_filter(h, s.b, s.n, s.H, s.ldh, s.prec, ma, s.Ya(), s.n, dact, lact, s.a, s.bb, s.mu1, s.flops,
-                    s.matvecs));
+                    s.matvecs, hy));
     mark(s, PH_FILTER, h->stream, false);
     return CHFSI_SUCCESS;
 }
@@ -433,6 +442,7 @@ chfsi_status st_order_columns(chfsi_handle h, SolveState& s, std::vector<int>& d
     bool ident = true;
     for (int j = 0; j < ma; ++j) { dsorted[j] = d[ord[j]]; ident &= ord[j] == j; }
     s.permuted = !ident;
+    s.hy_off = -1;   // the batched filter computes every step
     if (!ident) {
         int* perm = s.h_perm();   // pinned staging [2 m]: order, inverse
         for (int j = 0; j < ma; ++j) { perm[j] = ord[j]; perm[ma + ord[j]] = j; }
@@ -564,6 +574,8 @@ chfsi_status st_loop_complete(chfsi_handle h, SolveState& s)
     }
     for (int j = 0; j < ma; ++j) s.rprev[nlocked + j] = hr[j];
     s.nlocked = nl2;
+    // HY = H Ya from this loop's Rayleigh-Ritz step: its columns from cnt on are the next block's
+    s.hy_off = cnt;
     mark(s, PH_LOCK, st, false);
     s.want_final = s.nlocked >= nev;
     return CHFSI_SUCCESS;
@@ -575,6 +587,7 @@ chfsi_status st_final_enqueue(chfsi_handle h, SolveState& s)
     hipStream_t st = h->stream;
     SolveBufs& b = s.b;
     const int n = s.n, m = s.m;
+    s.hy_off = -1;   // HY is overwritten below
     mark(s, PH_BACK, st, true);
     if (s.S && h->fc_enabled && h->fc_n == n && explicit_reduction(n)) {
         // the cache holds this overlap's L^{-1}: X = L^{-H} V is one product

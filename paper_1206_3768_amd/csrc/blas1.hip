@@ -507,6 +507,25 @@ __global__ void k_add_diag_const(int m, zd* G, int ldg, double shift)
     if (i < m) G[(size_t)i + (size_t)i * ldg].x += shift;
 }
 
+// Y1 = alpha (HY - shift Y0) on columns [0, w): the first step of the scaled recurrence
+// (beta = 0) when the block's image H Y0 is already known (the previous Rayleigh-Ritz step's)
+template <typename T2>
+__global__ __launch_bounds__(256) void k_first_step(int n, int w, double alpha, double shift, const zd* __restrict__ HY,
+                                                    int ldhy, const T2* __restrict__ Y0, int ldy0, T2* __restrict__ Y1,
+                                                    int ldy1)
+{
+    const size_t total = (size_t)n * w;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        const zd hy = HY[(size_t)i + (size_t)j * ldhy];
+        const T2 y = Y0[(size_t)i + (size_t)j * ldy0];
+        T2 o;
+        o.x = alpha * (hy.x - shift * (double)y.x);
+        o.y = alpha * (hy.y - shift * (double)y.y);
+        Y1[(size_t)i + (size_t)j * ldy1] = o;
+    }
+}
+
 inline int grid_for(size_t total)
 {
     size_t b = (total + 255) / 256;
@@ -749,5 +768,23 @@ int launch_add_diag_const(hipStream_t s, int m, zd* G, int ldg, double shift)
 {
     if (m <= 0) return 0;
     hipLaunchKernelGGL(k_add_diag_const, dim3((m + 255) / 256), dim3(256), 0, s, m, G, ldg, shift);
+    return (int)hipGetLastError();
+}
+
+int launch_first_step(hipStream_t s, int n, int w, double alpha, double shift, const zd* HY, int ldhy, const zd* Y0,
+                      int ldy0, zd* Y1, int ldy1)
+{
+    if (n <= 0 || w <= 0) return 0;
+    hipLaunchKernelGGL(k_first_step<zd>, dim3(grid_for((size_t)n * w)), dim3(256), 0, s, n, w, alpha, shift, HY, ldhy,
+                       Y0, ldy0, Y1, ldy1);
+    return (int)hipGetLastError();
+}
+
+int launch_first_step(hipStream_t s, int n, int w, double alpha, double shift, const zd* HY, int ldhy, const zf* Y0,
+                      int ldy0, zf* Y1, int ldy1)
+{
+    if (n <= 0 || w <= 0) return 0;
+    hipLaunchKernelGGL(k_first_step<zf>, dim3(grid_for((size_t)n * w)), dim3(256), 0, s, n, w, alpha, shift, HY, ldhy,
+                       Y0, ldy0, Y1, ldy1);
     return (int)hipGetLastError();
 }

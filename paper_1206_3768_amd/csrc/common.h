@@ -182,6 +182,12 @@ size_t hegst_work_elems(int n);
 // inverses dinv; work: hegst_work_elems(n) elements
 int hegst_lower(hipStream_t s, int n, zd* A, int lda, const zd* L, int ldl, const zd* dinv, zd* work,
                 const GemmWs& gw);
+// Y1 = alpha (HY - shift Y0) on columns [0, w) (HY complex128; Y0, Y1 complex128 or complex64): the
+// first filter step of a block whose image HY = H Y0 is known
+int launch_first_step(hipStream_t s, int n, int w, double alpha, double shift, const zd* HY, int ldhy, const zd* Y0,
+                      int ldy0, zd* Y1, int ldy1);
+int launch_first_step(hipStream_t s, int n, int w, double alpha, double shift, const zd* HY, int ldhy, const zf* Y0,
+                      int ldy0, zf* Y1, int ldy1);
 // X <- L^{-1} (n x n, zero above the diagonal) from L and its diagonal-block inverses dinv
 int tri_inverse_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* X, int ldx, const GemmWs& gw);
 // H (ld n) <- Linv A Linv^H (exactly Hermitian) from the explicit inverse Linv = L^{-1} (ld n) and the

@@ -148,16 +148,20 @@ chfsi_status step_rayleigh_ritz(chfsi_handle h, int n, const zd* H, int ldh, int
                                 const GemmWs& gw, PhaseTimer* tm, double eig_stop = 0.0);
 void filter_coefficients(int dmax, double a, double b, double mu1, std::vector<FilterStep>& steps);
 FilterStep filter_step_coefficients(int k, double a, double b, double mu1, double& sigma);
+// The filters: hy0 (nullable, complex128, ld n) = H times the block's columns in their order, which
+// makes step 1 an elementwise update instead of a product.
 chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs,
+                        const zd* hy0 = nullptr);
 chfsi_status filter_f32(chfsi_handle h, int n, const zf* Hf, int ldh, int ma, zf* Yf, int ldy, zf* Tf,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs,
+                        const zd* hy0 = nullptr);
 void host_tridiag_eig(int k, const double* al, const double* be, std::vector<double>& theta,
                       std::vector<double>& z1sq);
 
 chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int nterms, int ma, zf* Yf, int ldy,
                          zf* Tf, uint16_t* ysplit, const std::vector<int>& deg, double a, double b, double mu1,
-                         int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs);
+                         int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs, const zd* hy0 = nullptr);
 // degree network (mlp.hip)
 chfsi_status learned_degrees(chfsi_handle h, int ma, const double* theta_dev, const double* r_dev, double a,
                              double b, double mu1, double thr, const std::vector<int>& dprev, float* feat,

@@ -616,7 +616,7 @@ int launch_filter_step_bf16(hipStream_t s, int n, int ncols, const uint16_t* Hpl
 // non-increasing, columns finishing on odd steps copied back from T at the end).
 chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int nterms, int ma, zf* Yf, int ldy,
                          zf* Tf, uint16_t* ysplit, const std::vector<int>& deg, double a, double b, double mu1,
-                         int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs)
+                         int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs, const zd* hy0)
 {
     hipStream_t st = h->stream;
     if (ma <= 0 || deg[0] <= 0) return CHFSI_SUCCESS;
@@ -632,6 +632,12 @@ chfsi_status filter_bf16(chfsi_handle h, int n, const uint16_t* Hb, int ldh, int
         const int ldo = (k % 2 == 1) ? n : ldy;
         const zf* yp = (k == 1) ? yk : yo;
         const int ldp = (k == 1) ? ldk : ldo;
+        if (k == 1 && hy0) {   // H Y_0 known (hy0, ld n): step 1 without a product
+            if (launch_first_step(st, n, w, steps[0].alpha, steps[0].shift, hy0, n, yk, ldk, yo, ldo))
+                return CHFSI_ERR_DEVICE;
+            matvecs += w;        // the degree count; filter_flops counts the products performed
+            continue;
+        }
         GemmWs gs = gw;
         const int pr = nterms == 2 ? CHFSI_BF16X3 : CHFSI_BF16X6;
         apply_tuned_plan(h, pr, n, w, gs);

@@ -531,7 +531,7 @@ chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma,
                            const GemmWs& gw, double& flops, long long& matvecs,
                            int (*step_fn)(hipStream_t, int, int, const HT*, int, const C2*, int, const C2*, int,
                                           C2*, int, FilterStep, const GemmWs&),
-                           int (*copy_fn)(hipStream_t, int, int, const C2*, int, C2*, int, const int*))
+                           int (*copy_fn)(hipStream_t, int, int, const C2*, int, C2*, int, const int*), const zd* hy0)
 {
     hipStream_t st = h->stream;
     if (ma <= 0) return CHFSI_SUCCESS;
@@ -549,6 +549,11 @@ chfsi_status filter_sorted(chfsi_handle h, int n, const HT* Hm, int ldh, int ma,
         const int ldo = (k % 2 == 1) ? ldt : ldy;
         const C2* yp = (k == 1) ? yk : yo;          // beta == 0 on step 1: any finite input
         const int ldp = (k == 1) ? ldk : ldo;
+        if (k == 1 && hy0) {   // H Y_0 known (hy0, ld n): step 1 without a product
+            TRY(launch_first_step(st, n, w, steps[0].alpha, steps[0].shift, hy0, n, yk, ldk, yo, ldo));
+            matvecs += w;        // the degree count; filter_flops counts the products performed
+            continue;
+        }
         GemmWs gs = gw;
         const int pr = sizeof(C2) == 16 ? CHFSI_FP64 : CHFSI_FP32;
         apply_tuned_plan(h, pr, n, w, gs);
@@ -583,15 +588,17 @@ static int step_f32(hipStream_t s, int n, int w, const zf* H, int ldh, const zf*
 }
 
 chfsi_status filter_f64(chfsi_handle h, int n, const zd* H, int ldh, int ma, zd* Y, int ldy, zd* T,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs)
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw,
+                        double& flops, long long& matvecs, const zd* hy0)
 {
     return filter_sorted<zd, zd>(h, n, H, ldh, ma, Y, ldy, T, n, deg, a, b, mu1, flag_dev, gw, flops, matvecs,
-                                 step_f64, launch_copy_cols_flag);
+                                 step_f64, launch_copy_cols_flag, hy0);
 }
 
 chfsi_status filter_f32(chfsi_handle h, int n, const zf* Hf, int ldh, int ma, zf* Yf, int ldy, zf* Tf,
-                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw, double& flops, long long& matvecs)
+                        const std::vector<int>& deg, double a, double b, double mu1, int* flag_dev, const GemmWs& gw,
+                        double& flops, long long& matvecs, const zd* hy0)
 {
     return filter_sorted<zf, zf>(h, n, Hf, ldh, ma, Yf, ldy, Tf, n, deg, a, b, mu1, flag_dev, gw, flops,
-                                 matvecs, step_f32, launch_copy_cols_flag_c);
+                                 matvecs, step_f32, launch_copy_cols_flag_c, hy0);
 }

@@ -68,6 +68,7 @@ struct SolveState {
     std::vector<double> rprev;
     std::vector<TraceRow> trace;
     int nlocked = 0, loops = 0, switches = 0;
+    int hy_off = -1;                   // b.HY columns hy_off.. = H times the active block, or -1
     long long matvecs = 0, filtered = 0;
     double flops = 0;
     chfsi_status status = CHFSI_ERR_NO_CONVERGENCE;
