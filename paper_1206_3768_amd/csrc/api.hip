@@ -442,13 +442,17 @@ chfsi_status st_order_columns(chfsi_handle h, SolveState& s, std::vector<int>& d
     bool ident = true;
     for (int j = 0; j < ma; ++j) { dsorted[j] = d[ord[j]]; ident &= ord[j] == j; }
     s.permuted = !ident;
-    s.hy_off = -1;   // the batched filter computes every step
     if (!ident) {
         int* perm = s.h_perm();   // pinned staging [2 m]: order, inverse
         for (int j = 0; j < ma; ++j) { perm[j] = ord[j]; perm[ma + ord[j]] = j; }
         TRY(hipMemcpyAsync(s.b.iperm, perm, sizeof(int) * 2 * ma, hipMemcpyHostToDevice, st));
         TRY(launch_permute_cols(st, n, ma, s.Ya(), n, s.b.T, n, s.b.iperm));
         TRY(launch_zlacpy(st, n, ma, s.b.T, n, s.Ya(), n));
+        if (s.hy_off >= 0) {   // the image H Y of the block follows its columns
+            zd* hy = s.b.HY + (size_t)s.hy_off * n;
+            TRY(launch_permute_cols(st, n, ma, hy, n, s.b.T, n, s.b.iperm));
+            TRY(launch_zlacpy(st, n, ma, s.b.T, n, hy, n));
+        }
     }
     return CHFSI_SUCCESS;
 }
@@ -596,11 +600,14 @@ chfsi_status st_final_enqueue(chfsi_handle h, SolveState& s)
         TRY(launch_zlacpy(st, n, m, b.V, n, s.X, s.ldx));
         if (s.S) TRY(trsm_left_lower_h(st, n, m, b.L, n, b.dinvL, s.X, s.ldx, b.gw));   // X = L^{-H} V
     }
-    TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.A, s.lda, s.X, s.ldx, 0.0, b.HY, n, b.gw));
+    // the verification products have the shape of a filter step: the filter's tuned plan
+    GemmWs gv = b.gw;
+    apply_tuned_plan(h, CHFSI_FP64, n, m, gv);
+    TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.A, s.lda, s.X, s.ldx, 0.0, b.HY, n, gv));
     const zd* SX = s.X;
     int ldsx = s.ldx;
     if (s.S) {
-        TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.S, s.lds, s.X, s.ldx, 0.0, b.T, n, b.gw));
+        TRY(launch_zgemm(st, OP_N, OP_N, n, m, n, 1.0, s.S, s.lds, s.X, s.ldx, 0.0, b.T, n, gv));
         SX = b.T;
         ldsx = n;
     }

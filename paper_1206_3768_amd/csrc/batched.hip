@@ -352,6 +352,14 @@ chfsi_status batched_filter(chfsi_handle h, std::vector<Slot>& sl, const std::ve
         const SolveState& s = sl[act[u]].s;
         filter_coefficients(std::max(1, sl[act[u]].dsorted[0]), s.a, s.bb, s.mu1, coef[u]);
     }
+    // step 1 of a problem whose block image H Y_0 is known (after a Rayleigh-Ritz step) needs no
+    // product: it is formed elementwise before the persistent steps
+    struct First {
+        SolveState* s;
+        int w;
+        double alpha, shift;
+    };
+    std::vector<First> first;
     for (int k = 1; k <= dmax; ++k) {
         BatchStep& t = tab[k - 1];
         t.nprob = 0;
@@ -362,6 +370,11 @@ chfsi_status batched_filter(chfsi_handle h, std::vector<Slot>& sl, const std::ve
             int w = 0;
             while (w < ma && z.dsorted[w] >= k) ++w;
             if (w == 0) continue;
+            if (k == 1 && s.hy_off >= 0) {
+                first.push_back({&s, w, coef[u][0].alpha, coef[u][0].shift});
+                s.matvecs += w;   // the degree count; the flop counts hold the products performed
+                continue;
+            }
             // Y_k lives in Ya when k is even, in T when k is odd; Y_{k-1} in the other buffer
             zd* Ya = s.Ya();
             zd* T = s.b.T;
@@ -388,6 +401,12 @@ chfsi_status batched_filter(chfsi_handle h, std::vector<Slot>& sl, const std::ve
     const int grid = batched_grid(h->device, bm, bn);
     TRY(hipMemcpyAsync(h->btable, tab, sizeof(BatchStep) * dmax, hipMemcpyHostToDevice, st));
     TRY(hipEventRecord(h->bev[0], st));
+    for (const First& f : first) {
+        SolveState& s = *f.s;
+        TRY(launch_first_step(st, s.n, f.w, f.alpha, f.shift, s.b.HY + (size_t)s.hy_off * s.n, s.n, s.Ya(), s.n,
+                              s.b.T, s.n));
+    }
+    for (int i : act) sl[i].s.hy_off = -1;
     if (h->batch_use_graph) {
         hipGraphExec_t exec = nullptr;
         TRYS(get_graph(h, dmax, bm, bn, grid, exec));
