@@ -72,7 +72,7 @@ struct FilterStep {
 };
 
 // Restricted products of launch_zgemm_tri (gemm.hip)
-enum { TRI_C_LOWER = 1, TRI_B_BLOCK_LOWER = 2 };
+enum { TRI_C_LOWER = 1, TRI_B_BLOCK_LOWER = 2, TRI_A_LOWER = 4, TRI_B_UPPER = 8 };
 int launch_zgemm_tri(hipStream_t s, int tri, int opa, int opb, int M, int N, int K, double alpha, const zd* A,
                      int lda, const zd* B, int ldb, double beta, zd* C, int ldc);
 

@@ -88,7 +88,9 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
         // tiles on or below the diagonal only (BM == BN), row by row: tile t is (it, jt) with
         // t = it (it + 1) / 2 + jt, jt <= it
         const int nt = g.tiles_m * (g.tiles_m + 1) / 2;
-        const int tile = xcd_remap(blockIdx.x, nt);
+        int tile = xcd_remap(blockIdx.x, nt);
+        // op(B) upper triangular: the work grows with jt, the last rows' tiles go out first
+        if (g.tri & TRI_B_UPPER) tile = nt - 1 - tile;
         int r = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
         while (r * (r + 1) / 2 > tile) --r;
         while ((r + 1) * (r + 2) / 2 <= tile) ++r;
@@ -105,12 +107,18 @@ __global__ __launch_bounds__(256) void k_zgemm(GDims g, const typename CT<T>::c*
         const int r1 = tile / g.tiles_n;
         it = r1 % g.tiles_m;
         ks = r1 / g.tiles_m;
+        // op(A) lower triangular: the row tile's work grows with it, the longest go out first
+        if (g.tri & TRI_A_LOWER) it = g.tiles_m - 1 - it;
     }
     const int i0 = it * BM, j0 = jt * BN;
     int kb = ks * g.kchunk;
-    const int ke = min(g.K, kb + g.kchunk);
+    int ke = min(g.K, kb + g.kchunk);
     // op(B) zero in the rows above the 64-block after the output column's: the products start there
     if (g.tri & TRI_B_BLOCK_LOWER) kb = max(kb, ((j0 >> 6) + 1) << 6);
+    // op(A) zero right of the diagonal, op(B) zero below it: the products end at the tile's last
+    // row (column)
+    if (g.tri & TRI_A_LOWER) ke = min(ke, i0 + BM);
+    if (g.tri & TRI_B_UPPER) ke = min(ke, j0 + BN);
     const int wr = (wave & 1) * (BM / 2), wc = (wave >> 1) * (BN / 2);
 
     ACC accr[MI][NJ], acci[MI][NJ];
@@ -299,6 +307,10 @@ int run(hipStream_t s, GDims g, const Plan& p, const typename CT<T>::c* A, const
 //  TRI_B_BLOCK_LOWER  op(B) is zero above its block diagonal of 64 x 64 blocks and below it only
 //                     strictly: column block c of op(B) is nonzero in rows >= 64 (c + 1) only, and
 //                     the rows above are never read
+//  TRI_A_LOWER        op(A) is lower triangular (K == M): its entries right of the diagonal are
+//                     taken as zero (a tile's products end at its last row)
+//  TRI_B_UPPER        op(B) is upper triangular (K == N): its entries below the diagonal are taken
+//                     as zero
 int launch_zgemm_tri(hipStream_t s, int tri, int opa, int opb, int M, int N, int K, double alpha, const zd* A,
                      int lda, const zd* B, int ldb, double beta, zd* C, int ldc)
 {

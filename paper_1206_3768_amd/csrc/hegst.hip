@@ -115,15 +115,18 @@ int tri_inverse_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv
 }
 
 // H (n x n, leading dimension n) <- Linv A Linv^H with the explicit inverse Linv = L^{-1} (n x n,
-// zero above the diagonal) and A (n x n Hermitian, full storage): T = Linv A, the tiles of H on
-// or below the diagonal as T Linv^H, then the upper triangle mirrored (exactly Hermitian, real
-// diagonal).  12 n^3 real flops in three launches, against the panel algorithm's 4 n^3 in a few
-// hundred small ones: for orders where those launches dominate.  T: n x n elements.
+// lower triangular) and A (n x n Hermitian, full storage): T = Linv A (row tile i of T takes the
+// first i + 1 column tiles of Linv), the tiles of H on or below the diagonal as T Linv^H (tile
+// (i, j) takes the first j + 1 column tiles of T), then the upper triangle mirrored (exactly
+// Hermitian, real diagonal).  About 16 n^3 / 3 real flops in three launches, against the panel
+// algorithm's 4 n^3 in a few hundred small ones.  T: n x n elements.
 int hegst_explicit(hipStream_t s, int n, const zd* A, int lda, const zd* Linv, zd* T, zd* H, const GemmWs& gw)
 {
+    (void)gw;
     if (n <= 0) return 0;
-    int rc = launch_zgemm(s, OP_N, OP_N, n, n, n, 1.0, Linv, n, A, lda, 0.0, T, n, gw);
-    if (rc == 0) rc = launch_zgemm_tri(s, TRI_C_LOWER, OP_N, OP_C, n, n, n, 1.0, T, n, Linv, n, 0.0, H, n);
+    int rc = launch_zgemm_tri(s, TRI_A_LOWER, OP_N, OP_N, n, n, n, 1.0, Linv, n, A, lda, 0.0, T, n);
+    if (rc == 0)
+        rc = launch_zgemm_tri(s, TRI_C_LOWER | TRI_B_UPPER, OP_N, OP_C, n, n, n, 1.0, T, n, Linv, n, 0.0, H, n);
     if (rc == 0) rc = launch_mirror_lower(s, n, H, n);
     return rc;
 }
