@@ -255,6 +255,9 @@ chfsi_status chfsi_set_filter_plan(chfsi_handle h, int n, int m, int prec, const
  *  chfsi_reduce:  L L^H = S, H = L^{-1} A L^{-H} (exactly Hermitian: the upper triangle is the
  *                 conjugate of the lower one).  H, L: n x n device outputs
  *                 (leading dimension n).  CHFSI_ERR_NOT_HPD on a non-positive pivot.
+ *  chfsi_reduce_explicit: the same outputs, H formed from the explicit inverse L^{-1} (two
+ *                 products that skip its zero triangle), the form chfsi_solve takes for n <= 3072;
+ *                 any n.  Allocates and frees 2 n^2 complex elements of device scratch.
  *  chfsi_lanczos: k-step Lanczos with full reorthogonalisation from the stream-2 Philox vector;
  *                 theta[k] ascending Ritz values of T_k, zw[k] = |z_1j|^2, *beta_k, *k_used (host).
  *  chfsi_orthonormalize: Y (n x m) <- Q with Y = Q R, R upper triangular with real positive
@@ -263,6 +266,8 @@ chfsi_status chfsi_set_filter_plan(chfsi_handle h, int n, int m, int prec, const
  *                 theta ascending (host [m]); resid (host [m]) = ||H y_i - theta_i y_i||_2. */
 chfsi_status chfsi_reduce(chfsi_handle h, int n, const void* A, int lda, const void* S, int lds,
                           void* H, void* L);
+chfsi_status chfsi_reduce_explicit(chfsi_handle h, int n, const void* A, int lda, const void* S,
+                                   int lds, void* H, void* L);
 chfsi_status chfsi_lanczos(chfsi_handle h, int n, const void* H, int ldh, int k,
                            unsigned long long seed, double* theta, double* zw, double* beta_k,
                            int* k_used);

@@ -84,7 +84,7 @@ class Problem(C.Structure):
 
 
 EXPORTED = ["chfsi_default_params", "chfsi_create", "chfsi_destroy", "chfsi_solve", "chfsi_solve_batched",
-            "chfsi_filter", "chfsi_reduce", "chfsi_lanczos", "chfsi_orthonormalize", "chfsi_rayleigh_ritz",
+            "chfsi_filter", "chfsi_reduce", "chfsi_reduce_explicit", "chfsi_lanczos", "chfsi_orthonormalize", "chfsi_rayleigh_ritz",
             "chfsi_zgemm", "chfsi_random_block", "chfsi_set_degree_model", "chfsi_get_trace", "chfsi_mlp_forward",
             "chfsi_mlp_loss_grad", "chfsi_mlp_adam", "chfsi_mlp_train", "chfsi_status_string",
             "chfsi_filter_kernel_time", "chfsi_autotune_filter", "chfsi_set_filter_plan",
@@ -115,6 +115,7 @@ def load():
     lib.chfsi_lobpcg_default_params.restype = None
     lib.chfsi_lobpcg.argtypes = [vp, i, vp, i, vp, i, vp, i, i, vp, vp, C.POINTER(LobpcgParams), C.POINTER(LobpcgStats)]
     lib.chfsi_reduce.argtypes = [vp, i, vp, i, vp, i, vp, vp]
+    lib.chfsi_reduce_explicit.argtypes = [vp, i, vp, i, vp, i, vp, vp]
     lib.chfsi_lanczos.argtypes = [vp, i, vp, i, i, u, vp, vp, vp, vp]
     lib.chfsi_orthonormalize.argtypes = [vp, i, i, vp, i, i, vp, i]
     lib.chfsi_rayleigh_ritz.argtypes = [vp, i, vp, i, i, vp, i, vp, vp]
@@ -364,6 +365,10 @@ class Handle:
     def reduce(self, A, S, H, L):
         self._check(self.lib.chfsi_reduce(self.h, A.shape[-1], _ptr(A), A.shape[-1], _ptr(S), S.shape[-1],
                                           _ptr(H), _ptr(L)), "chfsi_reduce")
+
+    def reduce_explicit(self, A, S, H, L):
+        self._check(self.lib.chfsi_reduce_explicit(self.h, A.shape[-1], _ptr(A), A.shape[-1], _ptr(S), S.shape[-1],
+                                                   _ptr(H), _ptr(L)), "chfsi_reduce_explicit")
 
     def lanczos(self, H, k: int, seed: int):
         th = np.zeros(k); zw = np.zeros(k); bk = np.zeros(1); ku = np.zeros(1, dtype=np.int32)

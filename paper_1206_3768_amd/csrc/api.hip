@@ -248,9 +248,9 @@ static inline void mark(SolveState& s, int phase, hipStream_t st, bool begin)
     if (s.tm) s.tm->mark(phase, st, begin);
 }
 
-// Orders up to which H = L^{-1} A L^{-H} is formed from the explicit inverse L^{-1} (two products,
-// 12 n^3 flops in three launches) rather than by the panel algorithm (4 n^3 flops in about ten
-// launches per 64 columns): below it the launches dominate.
+// Orders up to which H = L^{-1} A L^{-H} is formed from the explicit inverse L^{-1} (two products
+// that skip its zero triangle, about 16 n^3 / 3 flops in three launches) rather than by the panel
+// algorithm (4 n^3 flops in about ten launches per 64 columns): below it the launches dominate.
 constexpr int EXPLICIT_REDUCTION_MAX_N = 3072;
 inline bool explicit_reduction(int n) { return n <= EXPLICIT_REDUCTION_MAX_N; }
 
@@ -796,6 +796,29 @@ chfsi_status chfsi_reduce(chfsi_handle h, int n, const void* A, int lda, const v
     TRYS(step_reduce(h, n, (const zd*)A, lda, (const zd*)S, lds, (zd*)H, (zd*)L, b.dinvL, b.hwork, b.info, b.gw));
     TRY(hipStreamSynchronize(h->stream));
     return CHFSI_SUCCESS;
+}
+
+chfsi_status chfsi_reduce_explicit(chfsi_handle h, int n, const void* A, int lda, const void* S, int lds, void* H,
+                                   void* L)
+{
+    if (!h || !A || !S || !H || !L || n <= 0 || lda < n || lds < n) return CHFSI_ERR_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return CHFSI_ERR_DEVICE;
+    SolveBufs b;
+    TRYS(prepare(h, b, n, 1, 1, false, CHFSI_FP64, true));
+    hipStream_t st = h->stream;
+    zd* work = nullptr;   // [L^{-1} | product buffer]
+    if (hipMalloc((void**)&work, 2 * (size_t)n * n * sizeof(zd)) != hipSuccess) return CHFSI_ERR_ALLOC;
+    int info = 0;
+    chfsi_status rc = step_factor_enqueue(h, n, (const zd*)S, lds, (zd*)L, b.dinvL, b.info, &info, b.gw);
+    if (rc == CHFSI_SUCCESS && tri_inverse_lower(st, n, (const zd*)L, n, b.dinvL, work, n, b.gw) != 0)
+        rc = CHFSI_ERR_DEVICE;
+    if (rc == CHFSI_SUCCESS &&
+        hegst_explicit(st, n, (const zd*)A, lda, work, work + (size_t)n * n, (zd*)H, b.gw) != 0)
+        rc = CHFSI_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess && rc == CHFSI_SUCCESS) rc = CHFSI_ERR_DEVICE;
+    (void)hipFree(work);
+    if (rc == CHFSI_SUCCESS && info != 0) rc = CHFSI_ERR_NOT_HPD;
+    return rc;
 }
 
 chfsi_status chfsi_lanczos(chfsi_handle h, int n, const void* H, int ldh, int k, unsigned long long seed,

@@ -183,12 +183,15 @@ def test_filter_closed_form_diagonal(hd, orc):
 
 # ---- reduction, Lanczos, QR, Rayleigh-Ritz ------------------------------------------------------
 
+@pytest.mark.parametrize("entry", ["reduce", "reduce_explicit"])
 @pytest.mark.parametrize("n,kappa", [(40, 0.0), (64, 0.0), (257, 0.0), (1100, 0.0), (300, 1e6), (700, 1e6)])
-def test_reduce_parity(hd, orc, torch_dev, n, kappa):
-    """The Hermitian two-sided reduction (64-column panels with lower-triangle rank-2k updates, then
-    one solve with a block-lower right-hand side) against the oracle's two triangular solves: one
-    panel (40, 64), several panels with a ragged last one (257), the recursive splits of the solve
-    (1100), and overlaps of condition number 1e6.  H's rounding grows with kappa(L) = sqrt(kappa)."""
+def test_reduce_parity(hd, orc, torch_dev, n, kappa, entry):
+    """The Hermitian two-sided reduction against the oracle's two triangular solves, in both of the
+    library's forms: 64-column panels with lower-triangle rank-2k updates and one solve with a
+    block-lower right-hand side (reduce), and two products with the explicit inverse L^{-1} that
+    end each tile's inner dimension at the diagonal (reduce_explicit).  One panel or tile row (40,
+    64), several with a ragged last one (257), the recursive splits (1100), and overlaps of
+    condition number 1e6.  H's rounding grows with kappa(L) = sqrt(kappa)."""
     spec = synth.SequenceSpec(n=n, n_low=max(4, n // 20), generalized=True, cycles=1, eps0=0, eps_decay=1, seed=8,
                               kappa=kappa)
     p = synth.designed_pencil(spec, keep_vectors=False)
@@ -197,7 +200,7 @@ def test_reduce_parity(hd, orc, torch_dev, n, kappa):
     n = spec.n
     dH = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
     dL = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
-    hd.reduce(dev(p.A), dev(p.S), dH, dL)
+    getattr(hd, entry)(dev(p.A), dev(p.S), dH, dL)
     H = host(dH)
     assert np.array_equal(H, H.conj().T)
     # both factors carry rounding amplified by the conditioning of the factorisation, which grows
@@ -229,14 +232,15 @@ def test_reduce_above_4096_by_sampled_identities(hd, torch_dev):
         assert abs(L[i] @ H @ L[j].conj() - p.A[i, j]) <= 1e-11 * scale_a
 
 
+@pytest.mark.parametrize("entry", ["reduce", "reduce_explicit"])
 @pytest.mark.parametrize("n,bad", [(40, 5), (1100, 1050)])
-def test_reduce_rejects_non_hpd(hd, torch_dev, n, bad):
+def test_reduce_rejects_non_hpd(hd, torch_dev, n, bad, entry):
     from paper_1206_3768_amd import chfsi
     S = np.eye(n, dtype=complex)
     S[bad, bad] = -1
     dH = torch_dev.empty((n, n), dtype=torch_dev.complex128, device="cuda")
     with pytest.raises(chfsi.ChfsiError) as ei:
-        hd.reduce(dev(herm(n)), dev(S), dH, dH.clone())
+        getattr(hd, entry)(dev(herm(n)), dev(S), dH, dH.clone())
     assert ei.value.status == 2
 
 
