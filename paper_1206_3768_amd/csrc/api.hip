@@ -294,7 +294,7 @@ chfsi_status reduce_with_cache(chfsi_handle h, SolveState& s)
             TRY(launch_zlacpy(st, n, n, fc.L, n, b.L, n));
             TRY(hipMemcpyAsync(b.dinvL, fc.dinv, sizeof(zd) * tri_dinv_elems(n), hipMemcpyDeviceToDevice, st));
             if (fc.Linv) {
-                TRY(hegst_explicit(st, n, s.A, s.lda, fc.Linv, fc.T, b.H, b.gw));
+                TRY(hegst_explicit(st, n, s.A, s.lda, fc.Linv, fc.T, b.H));
             } else {
                 TRY(launch_zlacpy(st, n, n, s.A, s.lda, b.H, n));
                 TRY(hegst_lower(st, n, b.H, n, b.L, n, b.dinvL, b.hwork, b.gw));
@@ -318,7 +318,7 @@ chfsi_status reduce_with_cache(chfsi_handle h, SolveState& s)
     if (fc.Linv) {
         TRYS(step_factor_enqueue(h, n, s.S, s.lds, b.L, b.dinvL, b.info, s.hi, b.gw));
         TRY(tri_inverse_lower(st, n, b.L, n, b.dinvL, fc.Linv, n, b.gw));
-        TRY(hegst_explicit(st, n, s.A, s.lda, fc.Linv, fc.T, b.H, b.gw));
+        TRY(hegst_explicit(st, n, s.A, s.lda, fc.Linv, fc.T, b.H));
     } else {
         TRYS(step_reduce_enqueue(h, n, s.A, s.lda, s.S, s.lds, b.H, b.L, b.dinvL, b.hwork, b.info, s.hi, b.gw));
     }
@@ -813,7 +813,7 @@ chfsi_status chfsi_reduce_explicit(chfsi_handle h, int n, const void* A, int lda
     if (rc == CHFSI_SUCCESS && tri_inverse_lower(st, n, (const zd*)L, n, b.dinvL, work, n, b.gw) != 0)
         rc = CHFSI_ERR_DEVICE;
     if (rc == CHFSI_SUCCESS &&
-        hegst_explicit(st, n, (const zd*)A, lda, work, work + (size_t)n * n, (zd*)H, b.gw) != 0)
+        hegst_explicit(st, n, (const zd*)A, lda, work, work + (size_t)n * n, (zd*)H) != 0)
         rc = CHFSI_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess && rc == CHFSI_SUCCESS) rc = CHFSI_ERR_DEVICE;
     (void)hipFree(work);

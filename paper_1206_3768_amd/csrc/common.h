@@ -192,7 +192,7 @@ int launch_first_step(hipStream_t s, int n, int w, double alpha, double shift, c
 int tri_inverse_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv, zd* X, int ldx, const GemmWs& gw);
 // H (ld n) <- Linv A Linv^H (exactly Hermitian) from the explicit inverse Linv = L^{-1} (ld n) and the
 // full Hermitian A; T: n x n elements of scratch
-int hegst_explicit(hipStream_t s, int n, const zd* A, int lda, const zd* Linv, zd* T, zd* H, const GemmWs& gw);
+int hegst_explicit(hipStream_t s, int n, const zd* A, int lda, const zd* Linv, zd* T, zd* H);
 
 // ---- Hermitian eigensolver of the Rayleigh quotient (eig.hip) -----------------------------------
 int eig_padded_order(int m);

@@ -120,9 +120,8 @@ int tri_inverse_lower(hipStream_t s, int n, const zd* L, int ldl, const zd* dinv
 // (i, j) takes the first j + 1 column tiles of T), then the upper triangle mirrored (exactly
 // Hermitian, real diagonal).  About 16 n^3 / 3 real flops in three launches, against the panel
 // algorithm's 4 n^3 in a few hundred small ones.  T: n x n elements.
-int hegst_explicit(hipStream_t s, int n, const zd* A, int lda, const zd* Linv, zd* T, zd* H, const GemmWs& gw)
+int hegst_explicit(hipStream_t s, int n, const zd* A, int lda, const zd* Linv, zd* T, zd* H)
 {
-    (void)gw;
     if (n <= 0) return 0;
     int rc = launch_zgemm_tri(s, TRI_A_LOWER, OP_N, OP_N, n, n, n, 1.0, Linv, n, A, lda, 0.0, T, n);
     if (rc == 0)
