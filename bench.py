@@ -17,7 +17,8 @@ vector and degree, divided by the filter phase time), ms_per_step = time to solu
 the roofline of the dominant kernel (the FP64 filter step) from the dispatches' own timestamps
 (the main kernel alone and the whole step with its split-K reduction), and the CPU reference timed
 on a bounded sample.  Extras: the n = 8192 sequence at degrees 8/12/16/20 with the FP64, FP32,
-BF16x3 and BF16x6 filters and their per-eigenpair errors against the CPU reference's eigenvalues
+BF16x3 and BF16x6 filters, and with the analytic and learned per-vector degrees in FP64 and BF16x3,
+and their per-eigenpair errors against the CPU reference's eigenvalues
 (tests/golden/c3_oracle_eigenvalues.json), the n = 2048 sequence (warm vs random start, mixed
 precision), the batched k-point cycle (32 problems, sequential vs one batch) and the learned
 per-vector degree against fixed degrees and the analytic rule (20-cycle n = 4096 sequence).
@@ -242,35 +243,66 @@ def phase_summary(timed) -> dict:
 
 
 def bench_c3_sweep(seq, spec, golden) -> dict:
-    """The n = 8192 sequence at degrees 8, 12, 16, 20 with every filter precision: warm cycles
-    1..cycles-1, time to solution, loops, matrix-vector products, precision switches, and the
-    per-eigenpair error of every converged eigenvalue against the CPU reference."""
+    """The n = 8192 sequence at degrees 8, 12, 16, 20 with every filter precision, then with the
+    analytic and learned per-vector degrees in FP64 and BF16x3: warm cycles 1..cycles-1, time to
+    solution, loops, matrix-vector products, precision switches, and the per-eigenpair error of
+    every converged eigenvalue against the CPU reference."""
     out = {"workload": f"n={spec.n} generalized sequence, nev {spec.nev}, nex {spec.nex}, warm cycles 1..{spec.cycles - 1}",
            "reference": "tests/golden/c3_oracle_eigenvalues.json (CPU oracle, FP64)" if golden else None}
     work = seq.new_block()
+
+    def run(base, **kw):
+        seq.solve(1, warm=True, X=work, **kw)   # untimed: workspace, H copies
+        rs = [seq.solve(c, warm=True, X=work, **kw) for c in range(1, spec.cycles)]
+        tot = sum(r.wall_ms for r in rs)
+        rec = {"all_converged": all(r.status == 0 for r in rs), "time_to_solution_ms": round(tot, 1),
+               "speedup_vs_fp64": round(base / tot, 3) if base else None,
+               "filter_ms": round(sum(r.stats["t_filter"] for r in rs), 1),
+               "matvecs": sum(r.stats["matvecs"] for r in rs), "loops": [r.stats["loops"] for r in rs],
+               "precision_switches": [r.stats["precision_switches"] for r in rs],
+               "max_resid": float(max(r.resid[:spec.nev].max() for r in rs))}
+        if golden:
+            per = {}
+            for r in rs:
+                if r.status == 0 and r.cycle in golden:
+                    _, summ = pair_errors(r.lam, golden[r.cycle])
+                    per[str(r.cycle)] = summ
+            rec["rel_eig_err_vs_oracle"] = per
+        return rec, tot
+
+    best_fixed = None
     for d in (8, 12, 16, 20):
         base = None
         for name in ("fp64", "fp32", "bf16x3", "bf16x6"):
-            seq.solve(1, warm=True, X=work, filter_precision=name, deg=d)   # untimed: workspace, H copies
-            rs = [seq.solve(c, warm=True, X=work, filter_precision=name, deg=d) for c in range(1, spec.cycles)]
-            tot = sum(r.wall_ms for r in rs)
+            rec, tot = run(base, filter_precision=name, deg=d)
             if name == "fp64":
                 base = tot
-            rec = {"all_converged": all(r.status == 0 for r in rs), "time_to_solution_ms": round(tot, 1),
-                   "speedup_vs_fp64": round(base / tot, 3) if base else None,
-                   "filter_ms": round(sum(r.stats["t_filter"] for r in rs), 1),
-                   "matvecs": sum(r.stats["matvecs"] for r in rs), "loops": [r.stats["loops"] for r in rs],
-                   "precision_switches": [r.stats["precision_switches"] for r in rs],
-                   "max_resid": float(max(r.resid[:spec.nev].max() for r in rs))}
-            if golden:
-                per = {}
-                for r in rs:
-                    if r.status == 0 and r.cycle in golden:
-                        _, summ = pair_errors(r.lam, golden[r.cycle])
-                        per[str(r.cycle)] = summ
-                rec["rel_eig_err_vs_oracle"] = per
+                rec["speedup_vs_fp64"] = 1.0
+                best_fixed = tot if best_fixed is None else min(best_fixed, tot)
             out[f"d{d}_{name}"] = rec
             log(f"c3 degree {d} {name}: {rec['time_to_solution_ms']} ms, loops {rec['loops']}")
+    # per-vector degrees on the same warm cycles: the analytic rule and the network (trained on the
+    # n = 4096 traces), with the margins chosen on the network's selection seed, never on this
+    # sequence; speedups against the fastest fixed degree in FP64
+    from paper_1206_3768_amd import chfsi, degree_model
+    info = degree_model.meta()
+    margin = int(info.get("margin", degree_model.LEARNED_MARGIN))
+    margin_an = int(info.get("analytic_margin", margin))
+    blob = degree_model.load()
+    policies = [("analytic", chfsi.DEG_ANALYTIC, margin_an)]
+    if blob is not None:
+        policies.append(("learned", chfsi.DEG_LEARNED, margin))
+        seq.h.set_degree_model(blob)
+    try:
+        for pol, code, mg in policies:
+            for name in ("fp64", "bf16x3"):
+                rec, _ = run(best_fixed, filter_precision=name, degree_policy=code, deg_margin=mg)
+                rec["speedup_vs_best_fixed_fp64"] = rec.pop("speedup_vs_fp64")
+                out[f"{pol}+{mg}_{name}"] = rec
+                log(f"c3 {pol}+{mg} {name}: {rec['time_to_solution_ms']} ms, loops {rec['loops']}")
+    finally:
+        if blob is not None:
+            seq.h.set_degree_model(None)
     return out
 
 
